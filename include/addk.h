@@ -1,0 +1,204 @@
+/*
+ * addk.h -- C ABI of the MI355X (gfx950) additive-kernel fast summation library.
+ *
+ * The library computes, for points x_1..x_N in R^D, feature windows W_1..W_P
+ * (|W_w| = d_w <= 3) and right-hand sides V (N x R):
+ *
+ *   Y        = sum_w sigma_w^2 K_w V                          (K V)
+ *   dY_dl_w  = sigma_w^2 (dK_w/dl_w) V                        (dK/dl_w V)
+ *   dY_ds_w  = 2 sigma_w K_w V                                (dK/dsigma_w V)
+ *
+ * with (K_w)_ij = kappa(||x_i^{W_w} - x_j^{W_w}||; l_w).  The kernel is the
+ * windowed additive kernel of eq. (3)/(4) of Wagner, Nestler & Stoll, "Fast
+ * evaluation of additive kernels" (Gaussian, "Implementing the NFFT approach";
+ * Matern-1/2, "Extension to other kernels"); its derivatives are those of the
+ * same sections.  Each window's product is evaluated by the NFFT-based fast
+ * summation of eqs. (5)-(7): window-function spreading onto an oversampled
+ * torus grid, FFT, multiplication by the kernel's periodised Fourier
+ * coefficients, inverse FFT and interpolation back to the points; the
+ * windows are then summed in FP64.  The trigonometric sum of eq. (6) runs
+ * over the modes k in {-n/2, ..., n/2-1}^d and its real part is returned.
+ *
+ * Conventions
+ *  - Every entry point returns an addk_status; no exception crosses the ABI.
+ *    A descriptive message for the last failure on the calling thread is
+ *    available from addk_last_error().
+ *  - Arguments are validated before any device work is queued.
+ *  - V, Y, G and all gradient/derivative outputs are DEVICE pointers to FP64
+ *    column-major N x R matrices with a leading dimension (element (i, r) at
+ *    ptr[i + r * ld]).  Outputs are in the caller's point order.
+ *  - "stream" is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is queued on it asynchronously; the call returns before the
+ *    results are ready.  A plan must not be used on two streams at once.
+ *  - The plan owns its device copies of the sorted points, permutation,
+ *    Fourier multipliers and workspace; the caller keeps ownership of every
+ *    pointer it passes.  Plan creation is synchronous.
+ */
+#ifndef ADDK_H
+#define ADDK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ADDK_OK = 0,
+    ADDK_ERR_INVALID_ARG = 1, /* bad sizes, pointers, parameters                      */
+    ADDK_ERR_UNSUPPORTED = 2, /* d_w > 3, grid > 128 per dimension, torus too small   */
+    ADDK_ERR_ACCURACY = 3,    /* requested parameters cannot be resolved (eta < 1)    */
+    ADDK_ERR_OOM = 4,         /* device or host allocation failed                     */
+    ADDK_ERR_HIP = 5          /* a HIP runtime call or kernel launch failed           */
+} addk_status;
+
+typedef enum {
+    ADDK_GAUSSIAN = 1, /* kappa(r) = exp(-r^2/(2 l^2)); derivative kernel r^2/(2l^2) kappa */
+    ADDK_MATERN12 = 3  /* kappa(r) = exp(-r/l);        derivative kernel (r/l) kappa       */
+} addk_kernel;
+
+typedef enum {
+    ADDK_FP64 = 0, /* spreading, FFT and interpolation in FP64                       */
+    ADDK_FP32 = 1  /* spreading, FFT and interpolation in FP32 with FP32 accumulation;
+                      multipliers are computed in FP64, window sums are FP64          */
+} addk_precision;
+
+/* flags for addk_plan_create (bitwise OR) */
+#define ADDK_COEF_ANALYTIC 0u   /* coefficients of the periodisation by summation (default)  */
+#define ADDK_COEF_SAMPLED 1u    /* DFT of n^d kernel samples of the simple periodic
+                                   continuation (Lemma 1 of the paper)                        */
+#define ADDK_TORUS_AUTO 0u      /* per-window torus period balancing image/truncation errors  */
+#define ADDK_TORUS_PAPER 2u     /* prescaling rule: period 2 * Lmax * sqrt(d_max)              */
+#define ADDK_NO_ACCURACY_CHECK 4u /* do not refuse windows with eta < 1                       */
+
+typedef struct addk_plan_s *addk_plan;
+typedef struct addk_batch_s *addk_batch;
+
+/*
+ * Create a plan: points, windows, kernel, parameters and grid sizes.
+ *
+ *  N, D, X, ldx     N points with D features, row-major (X[j*ldx + f]),
+ *                   host or device memory; copied, may be freed on return.
+ *                   N >= 0 (N = 0 gives a plan whose products are empty).
+ *  P, win_offsets, win_features
+ *                   window w uses features win_features[win_offsets[w] ..
+ *                   win_offsets[w+1]-1]; 1 <= d_w <= 3; host memory.
+ *  kernel           ADDK_GAUSSIAN or ADDK_MATERN12.
+ *  ell, sigma       P length scales (> 0) and P amplitudes sigma_w (>= 0), host.
+ *                   ell is in the units of X.
+ *  n                Fourier bandwidth per dimension (even, >= 4): modes
+ *                   k in {-n/2, ..., n/2-1}^d (the paper's m).
+ *  m                window half-width in oversampled grid cells (2..8);
+ *                   every point touches (2m)^d grid cells.
+ *  oversampling     sigma = n_os / n; n_os = round(sigma * n) must be a power
+ *                   of two in [16, 128] and exceed n.
+ *  precision        ADDK_FP64 or ADDK_FP32.
+ *  flags            ADDK_COEF_* | ADDK_TORUS_* | ADDK_NO_ACCURACY_CHECK.
+ *  stream           stream used for the set-up kernels.
+ * Errors: INVALID_ARG (bad sizes/values/pointers), UNSUPPORTED (d_w > 3,
+ * n_os outside [16,128] or not a power of two, data extent plus window wider
+ * than the torus), ACCURACY (eta_w = pi n l_w / (sqrt2 T_w) < 1), OOM, HIP.
+ */
+addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double *X, int64_t ldx,
+                             int32_t P, const int32_t *win_offsets, const int32_t *win_features,
+                             int32_t kernel, const double *ell, const double *sigma,
+                             int32_t n, int32_t m, double oversampling,
+                             int32_t precision, uint32_t flags, void *stream);
+
+/*
+ * Y = sum_w sigma_w^2 K_w V (eqs. (5)-(7) per window, then the window sum of
+ * eq. (4)).  V: N x R (ldv >= N), Y: N x R (ldy >= N); device pointers.
+ * R >= 1.  V and Y must not overlap.
+ */
+addk_status addk_matvec(addk_plan plan, int32_t R, const double *V, int64_t ldv,
+                        double *Y, int64_t ldy, void *stream);
+
+/*
+ * Derivative products ("Implementing the NFFT approach", "Extension to other
+ * kernels"): one spreading and forward FFT per window feed both the kernel's
+ * and the derivative kernel's multipliers.
+ *   dY_dell  : P blocks of N x R, block w at dY_dell + w * ldy * R:
+ *              sigma_w^2 (dK_w/dl_w) V = sigma_w^2 (2/l_w) K_der,w V (Gaussian)
+ *                                      = sigma_w^2 (1/l_w) K_derM,w V (Matern-1/2)
+ *   dY_dsigma: P blocks, 2 sigma_w K_w V
+ *   Y        : sum_w sigma_w^2 K_w V
+ * Any of the three may be NULL (not all three).  All use leading dimension ldy.
+ */
+addk_status addk_dmatvec(addk_plan plan, int32_t R, const double *V, int64_t ldv,
+                         double *dY_dell, double *dY_dsigma, double *Y, int64_t ldy,
+                         void *stream);
+
+/*
+ * Vector-Jacobian product of Y = K(l, sigma) V for a cotangent G (N x R):
+ *   grad_V         = K G        (K is symmetric)               N x R, ld ldgv
+ *   grad_ell[w]    = <G, sigma_w^2 dK_w/dl_w V>                 P doubles, device
+ *   grad_sigma[w]  = <G, 2 sigma_w K_w V>                       P doubles, device
+ * The scalar gradients are computed as Fourier-domain inner products of the
+ * spread-and-transformed G and V with the multipliers, so they are the exact
+ * derivatives of the approximate operator with the torus frozen.  Any output
+ * may be NULL.  ldv, ldg, ldgv >= N.
+ */
+addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv,
+                     const double *G, int64_t ldg, double *grad_V, int64_t ldgv,
+                     double *grad_ell, double *grad_sigma, void *stream);
+
+/* Replace l_w and sigma_w (host arrays of P) and recompute the multipliers; the
+ * torus periods, grids and point sort are kept, so products stay differentiable
+ * in l.  Errors: INVALID_ARG, ACCURACY (as in addk_plan_create). */
+addk_status addk_plan_update_params(addk_plan plan, const double *ell, const double *sigma,
+                                    void *stream);
+
+/* Plan facts.  Arrays are host memory with room for P entries (any may be NULL). */
+typedef struct {
+    int64_t N;
+    int32_t P;
+    int32_t n, m, n_os, precision, kernel;
+    int64_t workspace_bytes;    /* device bytes currently held by the plan           */
+    double err_estimate;        /* a-priori relative error estimate (max over windows) */
+} addk_plan_info;
+addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_period,
+                            double *eta, int32_t *window_dim);
+
+addk_status addk_plan_destroy(addk_plan plan);
+
+/*
+ * Batched products of many independent plans (uneven N, mixed d) with one
+ * fixed set of device buffers: the whole sequence of stage kernels of all
+ * plans is captured once into a hipGraph; every addk_batch_launch replays it.
+ * Each stage kernel covers the windows of all plans in a single launch.
+ *  plans[p]  plans of identical precision (they must outlive the batch)
+ *  R         RHS per problem (same for all)
+ *  V[p], ldv[p], Y[p], ldy[p]   device buffers bound to the graph (host arrays
+ *            of nprob device pointers / leading dimensions).
+ * Errors: INVALID_ARG, OOM, HIP.
+ */
+addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *plans, int32_t R,
+                              const double *const *V, const int64_t *ldv,
+                              double *const *Y, const int64_t *ldy, void *stream);
+/* Y[p] = K_p V[p] for all p: replays the captured graph on the stream. */
+addk_status addk_batch_launch(addk_batch batch, void *stream);
+/* The same products, launched eagerly (no graph); for comparison and debugging. */
+addk_status addk_batch_run_eager(addk_batch batch, void *stream);
+addk_status addk_batch_destroy(addk_batch batch);
+
+/* ---- host-only helpers (no GPU needed) ---------------------------------- */
+
+/* Torus period of a window: rule ADDK_TORUS_AUTO or ADDK_TORUS_PAPER.
+ * L = maximal per-coordinate extent of the window's points, dmax = largest
+ * window dimension of the plan (PAPER rule only). */
+addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, uint32_t rule,
+                              int32_t dmax, double *T);
+
+/* Fourier transform of the normalised Kaiser-Bessel window used for spreading,
+ * Psi(k) = int psi(z) e^{-2 pi i z k / n_os} dz, evaluated by Gauss-Legendre
+ * quadrature; psi(0) = 1. */
+addk_status addk_window_ft(int32_t m, int32_t n_os, double oversampling_b, double k, double *value);
+
+const char *addk_status_string(addk_status s);
+const char *addk_last_error(void);
+const char *addk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADDK_H */

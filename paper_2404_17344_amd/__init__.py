@@ -1,0 +1,243 @@
+"""Fast additive-kernel matvecs on AMD MI355X (gfx950).
+
+Python face of ``libaddk.so`` (C ABI in ``include/addk.h``).  This module only
+marshals arguments: every step of the products runs in the library's HIP
+kernels.  Torch supplies device memory and the current stream.
+
+Layout: an (N, R) tensor ``V`` is handed to the library as a column-major
+N x R matrix (its transpose is made contiguous), results come back as (N, R)
+views of column-major buffers.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, AddkError,  # noqa: F401
+                   ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK)
+
+__all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "KernelMatvec"]
+
+_KERNELS = {"gaussian": ADDK_GAUSSIAN, "matern12": ADDK_MATERN12, ADDK_GAUSSIAN: ADDK_GAUSSIAN,
+            ADDK_MATERN12: ADDK_MATERN12}
+_PREC = {"fp64": ADDK_FP64, "fp32": ADDK_FP32, ADDK_FP64: ADDK_FP64, ADDK_FP32: ADDK_FP32}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _colmajor(V):
+    """(N,) or (N, R) float64 CUDA tensor -> contiguous (R, N) tensor (column-major N x R)."""
+    torch = _torch()
+    if not isinstance(V, torch.Tensor) or not V.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if V.dtype != torch.float64:
+        raise TypeError("expected float64 (the ABI takes FP64 inputs and outputs)")
+    if V.dim() == 1:
+        V = V[:, None]
+    return V.t().contiguous()
+
+
+def torus_period(kernel, L: float, ell: float, n: int, paper_rule: bool = False, dmax: int = 3) -> float:
+    lib = _lib.load()
+    T = ctypes.c_double()
+    _lib.check(lib.addk_torus_period(_KERNELS[kernel], L, ell, n, ADDK_TORUS_PAPER if paper_rule else 0, dmax,
+                                     ctypes.byref(T)), "addk_torus_period")
+    return T.value
+
+
+def window_ft(m: int, n_os: int, oversampling: float, k: float) -> float:
+    lib = _lib.load()
+    v = ctypes.c_double()
+    _lib.check(lib.addk_window_ft(m, n_os, oversampling, k, ctypes.byref(v)), "addk_window_ft")
+    return v.value
+
+
+class Plan:
+    """A plan for y = sum_w sigma_w^2 K_w v over fixed points and windows."""
+
+    def __init__(self, X, windows: Sequence[Sequence[int]], ell, sigma, kernel="gaussian", n: int = 64,
+                 m: int = 6, oversampling: float = 2.0, precision="fp64", coef: str = "analytic",
+                 torus: str = "auto", check_accuracy: bool = True, stream=None):
+        lib = _lib.load()
+        torch = _torch()
+        if isinstance(X, torch.Tensor):
+            Xt = X.detach().to(torch.float64).contiguous()
+            N, D = Xt.shape
+            xptr = Xt.data_ptr() if N else None
+            self._xkeep = Xt
+        else:
+            Xn = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+            N, D = Xn.shape
+            xptr = Xn.ctypes.data if N else None
+            self._xkeep = Xn
+        off = [0]
+        feat = []
+        for w in windows:
+            feat.extend(int(f) for f in w)
+            off.append(len(feat))
+        self.P = len(windows)
+        self.N = int(N)
+        self.windows = [list(w) for w in windows]
+        off_a = (ctypes.c_int32 * len(off))(*off)
+        feat_a = (ctypes.c_int32 * max(1, len(feat)))(*feat)
+        ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))
+        sig_a = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (self.P,)))
+        flags = 0
+        if coef == "sampled":
+            flags |= ADDK_COEF_SAMPLED
+        if torus == "paper":
+            flags |= ADDK_TORUS_PAPER
+        if not check_accuracy:
+            flags |= ADDK_NO_ACCURACY_CHECK
+        h = ctypes.c_void_p()
+        st = _stream(stream) if torch.cuda.is_available() else ctypes.c_void_p(0)
+        _lib.check(lib.addk_plan_create(ctypes.byref(h), N, D, xptr, D, self.P, off_a, feat_a, _KERNELS[kernel],
+                                        ell_a.ctypes.data_as(_lib._pd), sig_a.ctypes.data_as(_lib._pd), n, m,
+                                        float(oversampling), _PREC[precision], flags, st), "addk_plan_create")
+        self._h = h
+        self._lib = lib
+        self.kernel = _KERNELS[kernel]
+        self.precision = _PREC[precision]
+        self.ell = ell_a.copy()
+        self.sigma = sig_a.copy()
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(self._lib.addk_plan_destroy(self._h), "addk_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- facts
+    def query(self):
+        info = _lib.AddkPlanInfo()
+        T = (ctypes.c_double * self.P)()
+        eta = (ctypes.c_double * self.P)()
+        dims = (ctypes.c_int32 * self.P)()
+        _lib.check(self._lib.addk_plan_query(self._h, ctypes.byref(info), T, eta, dims), "addk_plan_query")
+        return {"N": info.N, "P": info.P, "n": info.n, "m": info.m, "n_os": info.n_os,
+                "precision": info.precision, "kernel": info.kernel, "workspace_bytes": info.workspace_bytes,
+                "err_estimate": info.err_estimate, "T": list(T), "eta": list(eta), "d": list(dims)}
+
+    def update_params(self, ell, sigma, stream=None):
+        ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))
+        sig_a = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (self.P,)))
+        _lib.check(self._lib.addk_plan_update_params(self._h, ell_a.ctypes.data_as(_lib._pd),
+                                                     sig_a.ctypes.data_as(_lib._pd), _stream(stream)),
+                   "addk_plan_update_params")
+        self.ell, self.sigma = ell_a.copy(), sig_a.copy()
+
+    # -- products
+    def matvec(self, V, out=None, stream=None):
+        torch = _torch()
+        Vc = _colmajor(V)
+        R = Vc.shape[0]
+        Yc = out if out is not None else torch.empty((R, self.N), dtype=torch.float64, device=Vc.device)
+        _lib.check(self._lib.addk_matvec(self._h, R, Vc.data_ptr(), max(self.N, 1), Yc.data_ptr(), max(self.N, 1),
+                                         _stream(stream)), "addk_matvec")
+        return Yc.t()
+
+    def dmatvec(self, V, want_y=True, want_dell=True, want_dsigma=True, stream=None):
+        """Returns (Y, dY_dell, dY_dsigma) with dY_* of shape (P, N, R) (None where not requested)."""
+        torch = _torch()
+        Vc = _colmajor(V)
+        R = Vc.shape[0]
+        dev = Vc.device
+        Y = torch.empty((R, self.N), dtype=torch.float64, device=dev) if want_y else None
+        dl = torch.empty((self.P, R, self.N), dtype=torch.float64, device=dev) if want_dell else None
+        ds = torch.empty((self.P, R, self.N), dtype=torch.float64, device=dev) if want_dsigma else None
+        p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        _lib.check(self._lib.addk_dmatvec(self._h, R, Vc.data_ptr(), max(self.N, 1), p(dl), p(ds), p(Y),
+                                          max(self.N, 1), _stream(stream)), "addk_dmatvec")
+        t2 = lambda t: t.transpose(1, 2) if t is not None else None  # noqa: E731
+        return (Y.t() if Y is not None else None), t2(dl), t2(ds)
+
+    def vjp(self, V, G, want_v=True, want_params=True, stream=None):
+        """Gradients of <G, K V>: (K G, d/dl_w, d/dsigma_w)."""
+        torch = _torch()
+        Gc = _colmajor(G)
+        R = Gc.shape[0]
+        Vc = _colmajor(V) if want_params else None
+        dev = Gc.device
+        gV = torch.empty((R, self.N), dtype=torch.float64, device=dev) if want_v else None
+        gl = torch.empty((self.P,), dtype=torch.float64, device=dev) if want_params else None
+        gs = torch.empty((self.P,), dtype=torch.float64, device=dev) if want_params else None
+        p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        _lib.check(self._lib.addk_vjp(self._h, R, p(Vc), max(self.N, 1), Gc.data_ptr(), max(self.N, 1), p(gV),
+                                      max(self.N, 1), p(gl), p(gs), _stream(stream)), "addk_vjp")
+        return (gV.t() if gV is not None else None), gl, gs
+
+
+class Batch:
+    """Many plans multiplied together with bound device buffers, replayed as one hipGraph."""
+
+    def __init__(self, plans: Sequence[Plan], R: int, stream=None):
+        torch = _torch()
+        lib = _lib.load()
+        self.plans = list(plans)
+        self.R = R
+        self.V = [torch.zeros((R, p.N), dtype=torch.float64, device="cuda") for p in self.plans]
+        self.Y = [torch.zeros((R, p.N), dtype=torch.float64, device="cuda") for p in self.plans]
+        n = len(self.plans)
+        hp = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        vp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.V])
+        yp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.Y])
+        ld = (ctypes.c_int64 * n)(*[max(p.N, 1) for p in self.plans])
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _lib.check(lib.addk_batch_create(ctypes.byref(h), n, hp, R, vp, ld, yp, ld, _stream(stream)),
+                   "addk_batch_create")
+        self._h = h
+        self._lib = lib
+
+    def set_inputs(self, Vs):
+        for dst, src in zip(self.V, Vs):
+            dst.copy_(_colmajor(src))
+
+    def outputs(self):
+        return [y.t() for y in self.Y]
+
+    def launch(self, stream=None):
+        _lib.check(self._lib.addk_batch_launch(self._h, _stream(stream)), "addk_batch_launch")
+
+    def run_eager(self, stream=None):
+        _lib.check(self._lib.addk_batch_run_eager(self._h, _stream(stream)), "addk_batch_run_eager")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(self._lib.addk_batch_destroy(self._h), "addk_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def addk_matvec(plan: Plan, V):
+    return plan.matvec(V)
+
+
+from .autograd import KernelMatvec  # noqa: E402

@@ -1,0 +1,163 @@
+// Internal declarations of the additive-kernel fast summation library.
+//
+// Device data layout (per window w of a plan):
+//   coords   real [d][N]   point coordinates in oversampled-grid units, relative
+//                          to the window's grid box, sorted by spreading tile
+//   perm     int32 [N]     sorted position -> caller's point index
+//   Bk, Bd   real [(n+1)^d] Fourier multipliers of the kernel / derivative kernel
+//                          over the modes k in {-n/2..n/2}^d (deconvolution folded in)
+// Workspace (per engine; npair_cap complex grids per window, 2 real RHS per grid):
+//   G   [pair][ez][ey][ex]            spread grid (box only)
+//   A1  [pair][ez][ey][n1]            after the forward x pass (n1 = n + 1 modes)
+//   A2  [pair][ez][n1][n1]            after the forward y pass
+//   A3  [o][pair][ez][n1][n1]         after the fused z pass (o = kernel, derivative)
+//   A4  [o][pair][ez][ey][n1]         after the inverse y pass
+//   H   [o][pair][ez][ey][ex]         after the inverse x pass, read by interpolation
+//   Yw  [o][r][N] (FP64)              per-window interpolated products, caller order
+// Lower-dimensional windows use the same arrays with unit extents.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "addk.h"
+
+namespace addk {
+
+constexpr int kBlock = 256;      // threads per block of every stage kernel
+constexpr int kGroup = 16;       // lanes cooperating on one point in spread/interp
+constexpr int kChunk = 1024;     // maximal points per spread/interp work item
+constexpr int kMaxW = 16;        // maximal taps per dimension (m <= 8)
+constexpr int kMaxNos = 128;     // maximal oversampled grid per dimension
+constexpr int kLdsBudget = 64 * 1024;
+
+// Per-window descriptor read by every stage kernel (device copy per engine).
+struct WinDev {
+    int d, n, n1, nos, m, W, prob, flags;
+    int64_t N;
+    int lo[3];      // box origin in absolute torus grid cells (x, y, z)
+    int ext[3];     // box extent; unit for unused dimensions
+    int tb[3];      // tile edge in base cells
+    int ntile[3];   // tiles per dimension
+    int S[3];       // sub-grid edge of a tile: tb + W - 1 (unit for unused dims)
+    double b;       // Kaiser-Bessel shape parameter pi (2 - 1/sigma)
+    double inv_e2bm;  // 1 / (1 - exp(-2 b m))
+    double sig2, der_scale, dsig;  // sigma^2, sigma^2 * (2/l or 1/l), 2 sigma
+    const void *coords;
+    const int32_t *perm;
+    const void *Bk;
+    const void *Bd;
+    void *G, *A1, *A2, *A3, *A4, *H, *Gm, *Vm;  // workspace (complex interleaved)
+    int64_t szG, szA1, szA2, szA3, szA4, szH, szM;  // complex elements per pair
+    double *Yw;     // [2][Rcap][N]
+    int64_t Rcap;
+    int npair_cap;
+    int pad_;
+};
+
+// Problem-level input/output pointers (one per plan inside a batch).
+struct ProbDev {
+    int64_t N;
+    int32_t wbeg, wend;       // windows [wbeg, wend) of the engine belong to it
+    const double *V;
+    int64_t ldv;
+    double *Y;
+    int64_t ldy;
+    double *dYl;
+    double *dYs;
+};
+
+struct IoArgs {
+    const ProbDev *table;  // device table (batches) or nullptr
+    ProbDev single;        // used when table == nullptr
+};
+
+struct Chunk {
+    int32_t win, tile, start, count;
+};
+
+struct LineGroup {
+    int32_t win, grp;
+};
+
+// Stage identifiers for the FFT passes (axis, mode).
+enum FftStage { ST_FWD0 = 0, ST_FWD1, ST_FUSED2, ST_FUSED1, ST_FUSED0, ST_INV1, ST_INV0, ST_COUNT };
+
+// Host-side record of one window of a plan.
+struct WinHost {
+    int d;
+    int feat[3];
+    double ell, sigma, T, L, eta, center[3];
+    int lo[3], ext[3], tb[3], ntile[3], S[3];
+    int64_t ntiles;
+    void *coords = nullptr;
+    int32_t *perm = nullptr;
+    void *Bk = nullptr, *Bd = nullptr;
+    double *Bk64 = nullptr, *Bd64 = nullptr;
+    std::vector<Chunk> chunks;  // win field is filled by the engine
+};
+
+struct Plan;
+
+// An engine runs the stage kernels over a set of windows (one plan or a batch).
+struct Engine {
+    int precision = ADDK_FP64;
+    int nprob = 0;
+    std::vector<const Plan *> plans;
+    std::vector<WinDev> wdev;      // host mirror of the device descriptors
+    std::vector<int> wplan;        // plan index of each window
+    std::vector<int> wlocal;       // window index inside its plan
+    WinDev *d_wins = nullptr;
+    Chunk *d_chunks[4] = {nullptr, nullptr, nullptr, nullptr};  // per d (1..3)
+    int nchunks[4] = {0, 0, 0, 0};
+    LineGroup *d_groups[ST_COUNT] = {};
+    int ngroups[ST_COUNT] = {};
+    int maxvol[4] = {0, 0, 0, 0};  // largest tile sub-grid volume per d
+    int rb[4] = {0, 0, 0, 0};      // RHS per spread/interp pass per d (capacity)
+    void *ws = nullptr;            // grid workspace
+    int64_t ws_bytes = 0;
+    double *yw = nullptr;          // per-window FP64 products
+    int64_t yw_bytes = 0;
+    int npair_cap = 0;
+    int64_t rcap = 0;
+    ProbDev *d_probs = nullptr;
+    std::vector<ProbDev> probs;
+    double *d_partial = nullptr;   // reduction scratch for the vjp
+    int64_t partial_cap = 0;
+    bool dirty = true;             // descriptors need an upload
+};
+
+struct Plan {
+    int64_t N = 0;
+    int32_t D = 0, P = 0;
+    int32_t kernel = ADDK_GAUSSIAN, n = 0, m = 0, nos = 0, precision = ADDK_FP64;
+    uint32_t flags = 0;
+    double sigma_os = 2.0;
+    std::vector<WinHost> wins;
+    std::vector<double> psi_tab;   // Psi(k), k = -n/2..n/2
+    double *d_psi = nullptr;
+    Engine eng;
+    int device = 0;
+};
+
+// ---- helpers implemented in the .hip files --------------------------------
+void set_error(const std::string &msg);
+addk_status hip_fail(hipError_t e, const char *what);
+
+// kernels.hip
+addk_status engine_build_device(Engine &E, int device_precision);
+addk_status engine_ensure_workspace(Engine &E, int R);
+addk_status engine_run(Engine &E, int R, int nout, bool store_vmodes_only, bool store_gmodes,
+                       IoArgs io, hipStream_t st);
+addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st);
+addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st);
+addk_status engine_upload(Engine &E);
+void engine_free(Engine &E);
+
+// plan.hip
+addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);
+
+}  // namespace addk

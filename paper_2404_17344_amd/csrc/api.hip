@@ -1,0 +1,325 @@
+// Products exposed through the C ABI: K V, the derivative products, the
+// vector-Jacobian product and batched products captured into a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "addk_internal.h"
+
+namespace addk {
+
+static addk_status fail2(addk_status s, const std::string &msg)
+{
+    set_error(msg);
+    return s;
+}
+
+static bool on_device(const void *p)
+{
+    if (!p)
+        return false;
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+static addk_status check_mat(const void *p, int64_t ld, int64_t N, const char *name, bool required)
+{
+    if (!p) {
+        if (required)
+            return fail2(ADDK_ERR_INVALID_ARG, std::string(name) + " is NULL");
+        return ADDK_OK;
+    }
+    if (ld < N || ld < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, std::string("leading dimension of ") + name + " is smaller than N");
+    if (!on_device(p))
+        return fail2(ADDK_ERR_INVALID_ARG, std::string(name) + " must be a device pointer");
+    return ADDK_OK;
+}
+
+static ProbDev single_prob(const Plan &pl)
+{
+    ProbDev p;
+    std::memset(&p, 0, sizeof(p));
+    p.N = pl.N;
+    p.wbeg = 0;
+    p.wend = pl.P;
+    return p;
+}
+
+struct Batch {
+    Engine eng;
+    std::vector<Plan *> plans;
+    int R = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+static addk_status batch_enqueue(Batch &b, hipStream_t st)
+{
+    IoArgs io;
+    std::memset(&io, 0, sizeof(io));
+    io.table = b.eng.d_probs;
+    addk_status s = engine_run(b.eng, b.R, 1, false, false, io, st);
+    if (s == ADDK_OK)
+        s = engine_combine(b.eng, b.R, 1, io, st);
+    return s;
+}
+
+}  // namespace addk
+
+using namespace addk;
+
+extern "C" {
+
+addk_status addk_matvec(addk_plan plan, int32_t R, const double *V, int64_t ldv, double *Y, int64_t ldy, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    Plan &pl = *(Plan *)plan;
+    if (R < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, "R must be >= 1");
+    if (pl.N == 0)
+        return ADDK_OK;
+    addk_status s;
+    if ((s = check_mat(V, ldv, pl.N, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, pl.N, "Y", true)) != ADDK_OK)
+        return s;
+    IoArgs io;
+    std::memset(&io, 0, sizeof(io));
+    io.single = single_prob(pl);
+    io.single.V = V;
+    io.single.ldv = ldv;
+    io.single.Y = Y;
+    io.single.ldy = ldy;
+    hipStream_t st = (hipStream_t)stream;
+    s = engine_run(pl.eng, R, 1, false, false, io, st);
+    if (s != ADDK_OK)
+        return s;
+    return engine_combine(pl.eng, R, 1, io, st);
+}
+
+addk_status addk_dmatvec(addk_plan plan, int32_t R, const double *V, int64_t ldv, double *dY_dell, double *dY_dsigma,
+                         double *Y, int64_t ldy, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    Plan &pl = *(Plan *)plan;
+    if (R < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, "R must be >= 1");
+    if (!dY_dell && !dY_dsigma && !Y)
+        return fail2(ADDK_ERR_INVALID_ARG, "no output requested");
+    if (pl.N == 0)
+        return ADDK_OK;
+    addk_status s;
+    if ((s = check_mat(V, ldv, pl.N, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, pl.N, "Y", false)) != ADDK_OK ||
+        (s = check_mat(dY_dell, ldy, pl.N, "dY_dell", false)) != ADDK_OK ||
+        (s = check_mat(dY_dsigma, ldy, pl.N, "dY_dsigma", false)) != ADDK_OK)
+        return s;
+    IoArgs io;
+    std::memset(&io, 0, sizeof(io));
+    io.single = single_prob(pl);
+    io.single.V = V;
+    io.single.ldv = ldv;
+    io.single.Y = Y;
+    io.single.ldy = ldy;
+    io.single.dYl = dY_dell;
+    io.single.dYs = dY_dsigma;
+    hipStream_t st = (hipStream_t)stream;
+    const int nout = dY_dell ? 2 : 1;
+    s = engine_run(pl.eng, R, nout, false, false, io, st);
+    if (s != ADDK_OK)
+        return s;
+    const int mode = (Y ? 1 : 0) | (dY_dsigma ? 2 : 0) | (dY_dell ? 4 : 0);
+    return engine_combine(pl.eng, R, mode, io, st);
+}
+
+addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv, const double *G, int64_t ldg,
+                     double *grad_V, int64_t ldgv, double *grad_ell, double *grad_sigma, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    Plan &pl = *(Plan *)plan;
+    if (R < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, "R must be >= 1");
+    addk_status s;
+    const bool scalars = grad_ell || grad_sigma;
+    if ((grad_ell && !on_device(grad_ell)) || (grad_sigma && !on_device(grad_sigma)))
+        return fail2(ADDK_ERR_INVALID_ARG, "grad_ell and grad_sigma must be device pointers");
+    if (pl.N == 0) {
+        if (scalars) {
+            std::vector<double> z(pl.P, 0.0);
+            hipError_t e = hipSuccess;
+            if (grad_ell)
+                e = hipMemcpy(grad_ell, z.data(), pl.P * sizeof(double), hipMemcpyHostToDevice);
+            if (e == hipSuccess && grad_sigma)
+                e = hipMemcpy(grad_sigma, z.data(), pl.P * sizeof(double), hipMemcpyHostToDevice);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMemcpy");
+        }
+        return ADDK_OK;
+    }
+    if ((s = check_mat(G, ldg, pl.N, "G", true)) != ADDK_OK || (s = check_mat(V, ldv, pl.N, "V", scalars)) != ADDK_OK ||
+        (s = check_mat(grad_V, ldgv, pl.N, "grad_V", false)) != ADDK_OK)
+        return s;
+    hipStream_t st = (hipStream_t)stream;
+    IoArgs io;
+    std::memset(&io, 0, sizeof(io));
+    io.single = single_prob(pl);
+    if (scalars) {
+        io.single.V = V;
+        io.single.ldv = ldv;
+        s = engine_run(pl.eng, R, 0, true, false, io, st);  // V^ modes only
+        if (s != ADDK_OK)
+            return s;
+    }
+    io.single.V = G;
+    io.single.ldv = ldg;
+    io.single.Y = grad_V;
+    io.single.ldy = ldgv;
+    s = engine_run(pl.eng, R, grad_V ? 1 : 0, false, scalars, io, st);
+    if (s != ADDK_OK)
+        return s;
+    if (grad_V && (s = engine_combine(pl.eng, R, 1, io, st)) != ADDK_OK)
+        return s;
+    if (scalars)
+        return engine_mode_dot(pl.eng, (R + 1) / 2, grad_ell, grad_sigma, st);
+    return ADDK_OK;
+}
+
+addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *plans, int32_t R,
+                              const double *const *V, const int64_t *ldv, double *const *Y, const int64_t *ldy,
+                              void *stream)
+{
+    if (!out || nprob < 1 || !plans || R < 1 || !V || !ldv || !Y || !ldy)
+        return fail2(ADDK_ERR_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    const int prec = ((Plan *)plans[0])->precision;
+    for (int p = 0; p < nprob; ++p) {
+        if (!plans[p])
+            return fail2(ADDK_ERR_INVALID_ARG, "NULL plan in batch");
+        const Plan &pl = *(Plan *)plans[p];
+        if (pl.precision != prec)
+            return fail2(ADDK_ERR_INVALID_ARG, "all plans of a batch must share one precision");
+        if (pl.N > 0) {
+            addk_status s;
+            if ((s = check_mat(V[p], ldv[p], pl.N, "V[p]", true)) != ADDK_OK ||
+                (s = check_mat(Y[p], ldy[p], pl.N, "Y[p]", true)) != ADDK_OK)
+                return s;
+        }
+    }
+    Batch *b = new (std::nothrow) Batch();
+    if (!b)
+        return fail2(ADDK_ERR_OOM, "host allocation failed");
+    b->R = R;
+    Engine &E = b->eng;
+    E.nprob = nprob;
+    E.probs.resize(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        Plan *pl = (Plan *)plans[p];
+        b->plans.push_back(pl);
+        E.plans.push_back(pl);
+        ProbDev &pd = E.probs[p];
+        std::memset(&pd, 0, sizeof(pd));
+        pd.N = pl->N;
+        pd.wbeg = (int)E.wdev.size();
+        for (int w = 0; w < pl->P; ++w) {
+            WinDev d = pl->eng.wdev[w];
+            d.prob = p;
+            E.wdev.push_back(d);
+            E.wplan.push_back(p);
+            E.wlocal.push_back(w);
+        }
+        pd.wend = (int)E.wdev.size();
+        pd.V = V[p];
+        pd.ldv = ldv[p];
+        pd.Y = Y[p];
+        pd.ldy = ldy[p];
+    }
+    addk_status s = engine_build_device(E, prec);
+    if (s == ADDK_OK)
+        s = engine_ensure_workspace(E, R);
+    hipError_t e = hipSuccess;
+    if (s == ADDK_OK) {
+        e = hipMalloc(&E.d_probs, nprob * sizeof(ProbDev));
+        if (e == hipSuccess)
+            e = hipMemcpy(E.d_probs, E.probs.data(), nprob * sizeof(ProbDev), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            s = hip_fail(e, "batch problem table");
+    }
+    if (s == ADDK_OK) {
+        e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            s = hip_fail(e, "hipStreamCreate");
+    }
+    if (s == ADDK_OK) {
+        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            s = hip_fail(e, "hipStreamBeginCapture");
+        else {
+            addk_status s2 = batch_enqueue(*b, b->cap_stream);
+            e = hipStreamEndCapture(b->cap_stream, &b->graph);
+            if (s2 != ADDK_OK)
+                s = s2;
+            else if (e != hipSuccess)
+                s = hip_fail(e, "hipStreamEndCapture");
+        }
+    }
+    if (s == ADDK_OK) {
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
+            s = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (s != ADDK_OK) {
+        addk_batch_destroy((addk_batch)b);
+        return s;
+    }
+    (void)stream;
+    *out = (addk_batch)b;
+    return ADDK_OK;
+}
+
+addk_status addk_batch_launch(addk_batch batch, void *stream)
+{
+    if (!batch)
+        return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
+    Batch &b = *(Batch *)batch;
+    hipError_t e = hipGraphLaunch(b.exec, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGraphLaunch");
+    return ADDK_OK;
+}
+
+addk_status addk_batch_run_eager(addk_batch batch, void *stream)
+{
+    if (!batch)
+        return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
+    return batch_enqueue(*(Batch *)batch, (hipStream_t)stream);
+}
+
+addk_status addk_batch_destroy(addk_batch batch)
+{
+    if (!batch)
+        return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
+    Batch *b = (Batch *)batch;
+    (void)hipDeviceSynchronize();
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream)
+        (void)hipStreamDestroy(b->cap_stream);
+    engine_free(b->eng);
+    delete b;
+    return ADDK_OK;
+}
+
+}  // extern "C"

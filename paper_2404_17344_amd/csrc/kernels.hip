@@ -1,0 +1,1032 @@
+// Stage kernels of the NFFT-based fast summation (eqs. (5)-(7)) for gfx950 and
+// the engine that launches them over work lists spanning many windows.
+//
+//   spread  : g_l = sum_j v_j prod_i psi(u_ji - l_i)           (adjoint NFFT gridding)
+//   FFT     : forward line FFTs, keeping the modes k in [-n/2, n/2]
+//   multiply: h_k = B_k g_k  (B = periodised kernel coefficients / window transform^2)
+//   IFFT    : inverse line FFTs back to the grid box
+//   interp  : y_j = sum_l h_l prod_i psi(u_ji - l_i)            (NFFT gathering)
+//   combine : FP64 window sum y = sum_w sigma_w^2 y_w and derivative scalings
+//
+// Spreading and interpolation work on tiles of base cells: a block owns one
+// chunk of <= kChunk points of one tile and keeps the tile's sub-grid
+// (tile + window halo) for a block of RHS in LDS.  Sixteen lanes cooperate on
+// one point: lane g handles the taps g, g+16, ... so that the 16 LDS addresses
+// of one instruction are distinct.  Spreading accumulates with LDS atomics and
+// flushes the sub-grid to the global grid with float atomics; interpolation
+// stages the sub-grid with plain loads and reduces the 16 partial sums with
+// cross-lane shuffles.  The FFT keeps a group of lines in LDS and runs a
+// radix-2 Stockham transform; a fused pass does forward transform, the
+// multiplication for one or two multipliers and the inverse transform
+// without leaving LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+#include "addk_internal.h"
+
+namespace addk {
+
+template <typename real>
+struct cpx {
+    real x, y;
+};
+
+template <typename real>
+__device__ __forceinline__ cpx<real> cadd(cpx<real> a, cpx<real> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename real>
+__device__ __forceinline__ cpx<real> csub(cpx<real> a, cpx<real> b) { return {a.x - b.x, a.y - b.y}; }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void lds_add(float *p, float v) { __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void lds_add(double *p, double v) { __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ void gbl_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gbl_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// Normalised Kaiser-Bessel window in grid units (psi(0) = 1):
+//   psi(z) = (m / sinh(b m)) sinh(b s) / s,  s = sqrt(m^2 - z^2),  |z| <= m,
+// written with exponentials that stay finite in FP32.
+template <typename real>
+__device__ __forceinline__ real kb_psi(real z, real m, real b, real inv_e2bm)
+{
+    real s2 = m * m - z * z;
+    s2 = s2 > real(0) ? s2 : real(0);
+    real s = sqrt(s2);
+    s = s > real(1e-6) ? s : real(1e-6);
+    return m * (exp(b * (s - m)) - exp(-b * (s + m))) * inv_e2bm / s;
+}
+
+// First tap of a point at grid coordinate u: taps are base .. base + 2m - 1.
+template <typename real>
+__device__ __forceinline__ int base_cell(real u, int m)
+{
+    return (int)floor(u) - m + 1;
+}
+
+__device__ __forceinline__ ProbDev get_prob(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
+
+// ---------------------------------------------------------------------------
+// zero the spread grids of every window (npair grids each)
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_zero_grids(const WinDev *__restrict__ wins, int npair)
+{
+    const WinDev &w = wins[blockIdx.y];
+    real *G = (real *)w.G;
+    const int64_t n = 2 * w.szG * (int64_t)npair;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        G[i] = real(0);
+}
+
+// ---------------------------------------------------------------------------
+// spreading
+
+template <typename real, int D, int RB>
+__global__ __launch_bounds__(kBlock) void k_spread(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
+                                                   IoArgs io, int R)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int r0 = blockIdx.y * RB;
+    if (r0 >= R)
+        return;
+    const int nr = min(RB, R - r0);
+    const int S0 = w.S[0], S1 = D > 1 ? w.S[1] : 1, S2 = D > 2 ? w.S[2] : 1;
+    const int vol = S0 * S1 * S2;
+    real *sub = (real *)smem_raw;
+    real *wv = sub + RB * vol;  // [16 groups][D][kMaxW]
+
+    int t = ch.tile;
+    const int tx = t % w.ntile[0];
+    t /= w.ntile[0];
+    const int ty = t % w.ntile[1];
+    const int tz = t / w.ntile[1];
+    const int ox0 = tx * w.tb[0], oy0 = ty * w.tb[1], oz0 = tz * w.tb[2];
+
+    for (int i = threadIdx.x; i < RB * vol; i += kBlock)
+        sub[i] = real(0);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane >> 4, g = lane & 15;
+    real *mywv = wv + (wave * 4 + grp) * (D * kMaxW);
+    const real *coords = (const real *)w.coords;
+    const ProbDev pio = get_prob(io, w.prob);
+    const int W = w.W, m = w.m;
+    const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
+
+    for (int base = wave * 4; base < ch.count; base += 16) {
+        const int p = base + grp;
+        const bool act = p < ch.count;
+        const int j = ch.start + (act ? p : 0);
+        real u[3];
+        int bc[3];
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            u[dd] = coords[dd * w.N + j];
+            bc[dd] = base_cell(u[dd], m);
+        }
+        for (int q = g; q < D * W; q += kGroup) {
+            const int dd = q / W, o = q - dd * W;
+            const real uu = dd == 0 ? u[0] : (dd == 1 ? u[D > 1 ? 1 : 0] : u[D > 2 ? 2 : 0]);
+            const int b0 = dd == 0 ? bc[0] : (dd == 1 ? bc[D > 1 ? 1 : 0] : bc[D > 2 ? 2 : 0]);
+            mywv[dd * kMaxW + o] = kb_psi(uu - (real)(b0 + o), mm, bb, ie);
+        }
+        real v[RB];
+        const int orig = w.perm[j];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            v[i] = (act && i < nr) ? (real)pio.V[orig + (int64_t)(r0 + i) * pio.ldv] : real(0);
+        wave_sync();
+        if (act) {
+            const int lx = bc[0] - ox0;
+            const int ly = D > 1 ? bc[D > 1 ? 1 : 0] - oy0 : 0;
+            const int lz = D > 2 ? bc[D > 2 ? 2 : 0] - oz0 : 0;
+            if (D == 3) {
+                for (int pq = g; pq < W * W; pq += kGroup) {
+                    const int ox = pq % W, oy = pq / W;
+                    const real wxy = mywv[ox] * mywv[kMaxW + oy];
+                    int cell = (lz * S1 + ly + oy) * S0 + lx + ox;
+                    for (int oz = 0; oz < W; ++oz, cell += S0 * S1) {
+                        const real wt = wxy * mywv[2 * kMaxW + oz];
+#pragma unroll
+                        for (int i = 0; i < RB; ++i)
+                            lds_add(&sub[i * vol + cell], wt * v[i]);
+                    }
+                }
+            } else if (D == 2) {
+                for (int pq = g; pq < W * W; pq += kGroup) {
+                    const int ox = pq % W, oy = pq / W;
+                    const real wt = mywv[ox] * mywv[kMaxW + oy];
+                    const int cell = (ly + oy) * S0 + lx + ox;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        lds_add(&sub[i * vol + cell], wt * v[i]);
+                }
+            } else {
+                for (int ox = g; ox < W; ox += kGroup) {
+                    const real wt = mywv[ox];
+                    const int cell = lx + ox;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        lds_add(&sub[i * vol + cell], wt * v[i]);
+                }
+            }
+        }
+        wave_sync();
+    }
+    __syncthreads();
+
+    // flush the sub-grid: RHS r goes to component r % 2 of complex grid r / 2
+    real *G = (real *)w.G;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    for (int idx = threadIdx.x; idx < nr * vol; idx += kBlock) {
+        const int i = idx / vol, c = idx - i * vol;
+        const real val = sub[i * vol + c];
+        if (val == real(0))
+            continue;
+        const int cx = c % S0, cy = (c / S0) % S1, cz = c / (S0 * S1);
+        const int gx = ox0 + cx, gy = oy0 + cy, gz = oz0 + cz;
+        if (gx >= ex || gy >= ey || gz >= ez)
+            continue;
+        const int r = r0 + i;
+        const int64_t off = ((int64_t)(r >> 1) * w.szG + ((int64_t)gz * ey + gy) * ex + gx) * 2 + (r & 1);
+        gbl_add(&G[off], val);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interpolation
+
+template <typename real, int D, int RB>
+__global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
+                                                   int R)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int r0 = blockIdx.y * RB;
+    if (r0 >= R)
+        return;
+    const int o = blockIdx.z;
+    const int nr = min(RB, R - r0);
+    const int S0 = w.S[0], S1 = D > 1 ? w.S[1] : 1, S2 = D > 2 ? w.S[2] : 1;
+    const int vol = S0 * S1 * S2;
+    real *sub = (real *)smem_raw;
+    real *wv = sub + RB * vol;
+
+    int t = ch.tile;
+    const int tx = t % w.ntile[0];
+    t /= w.ntile[0];
+    const int ty = t % w.ntile[1];
+    const int tz = t / w.ntile[1];
+    const int ox0 = tx * w.tb[0], oy0 = ty * w.tb[1], oz0 = tz * w.tb[2];
+
+    // stage the sub-grid (both components of each complex grid at once)
+    const real *H = (const real *)w.H;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    const int np = (nr + 1) >> 1;
+    const int p0 = r0 >> 1;
+    for (int idx = threadIdx.x; idx < np * vol; idx += kBlock) {
+        const int pi = idx / vol, c = idx - pi * vol;
+        const int cx = c % S0, cy = (c / S0) % S1, cz = c / (S0 * S1);
+        const int gx = ox0 + cx, gy = oy0 + cy, gz = oz0 + cz;
+        real re = 0, im = 0;
+        if (gx < ex && gy < ey && gz < ez) {
+            const int64_t off =
+                ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
+            re = H[off];
+            im = H[off + 1];
+        }
+        sub[(2 * pi) * vol + c] = re;
+        if (2 * pi + 1 < RB)
+            sub[(2 * pi + 1) * vol + c] = im;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane >> 4, g = lane & 15;
+    real *mywv = wv + (wave * 4 + grp) * (D * kMaxW);
+    const real *coords = (const real *)w.coords;
+    const int W = w.W, m = w.m;
+    const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
+    double *dst = w.Yw + ((int64_t)o * w.Rcap + r0) * w.N;
+
+    for (int base = wave * 4; base < ch.count; base += 16) {
+        const int p = base + grp;
+        const bool act = p < ch.count;
+        const int j = ch.start + (act ? p : 0);
+        real u[3];
+        int bc[3];
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            u[dd] = coords[dd * w.N + j];
+            bc[dd] = base_cell(u[dd], m);
+        }
+        for (int q = g; q < D * W; q += kGroup) {
+            const int dd = q / W, oo = q - dd * W;
+            const real uu = dd == 0 ? u[0] : (dd == 1 ? u[D > 1 ? 1 : 0] : u[D > 2 ? 2 : 0]);
+            const int b0 = dd == 0 ? bc[0] : (dd == 1 ? bc[D > 1 ? 1 : 0] : bc[D > 2 ? 2 : 0]);
+            mywv[dd * kMaxW + oo] = kb_psi(uu - (real)(b0 + oo), mm, bb, ie);
+        }
+        wave_sync();
+        real acc[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            acc[i] = real(0);
+        if (act) {
+            const int lx = bc[0] - ox0;
+            const int ly = D > 1 ? bc[D > 1 ? 1 : 0] - oy0 : 0;
+            const int lz = D > 2 ? bc[D > 2 ? 2 : 0] - oz0 : 0;
+            if (D == 3) {
+                for (int pq = g; pq < W * W; pq += kGroup) {
+                    const int ox = pq % W, oy = pq / W;
+                    const real wxy = mywv[ox] * mywv[kMaxW + oy];
+                    int cell = (lz * S1 + ly + oy) * S0 + lx + ox;
+                    for (int oz = 0; oz < W; ++oz, cell += S0 * S1) {
+                        const real wt = wxy * mywv[2 * kMaxW + oz];
+#pragma unroll
+                        for (int i = 0; i < RB; ++i)
+                            acc[i] += wt * sub[i * vol + cell];
+                    }
+                }
+            } else if (D == 2) {
+                for (int pq = g; pq < W * W; pq += kGroup) {
+                    const int ox = pq % W, oy = pq / W;
+                    const real wt = mywv[ox] * mywv[kMaxW + oy];
+                    const int cell = (ly + oy) * S0 + lx + ox;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i] += wt * sub[i * vol + cell];
+                }
+            } else {
+                for (int ox = g; ox < W; ox += kGroup) {
+                    const real wt = mywv[ox];
+                    const int cell = lx + ox;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i] += wt * sub[i * vol + cell];
+                }
+            }
+        }
+        // reduce the 16 partial sums of the group
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1)
+                acc[i] += __shfl_xor(acc[i], off, kGroup);
+        }
+        if (act) {
+            const int orig = w.perm[j];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (i == g && i < nr)
+                    dst[(int64_t)i * w.N + orig] = (double)acc[i];
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// line FFTs in LDS (radix-2 Stockham), pruned to the box and to the kept modes
+
+template <typename real>
+__device__ cpx<real> *fft_lines(cpx<real> *a, cpx<real> *b, const cpx<real> *tw, int nos, int L, real sign)
+{
+    const int h = nos >> 1;
+    for (int Ns = 1; Ns < nos; Ns <<= 1) {
+        for (int t = threadIdx.x; t < L * h; t += kBlock) {
+            const int l = t / h, j = t - l * h;
+            const cpx<real> x0 = a[l * nos + j], x1 = a[l * nos + j + h];
+            const int k = j & (Ns - 1);
+            const cpx<real> c = tw[k * (h / Ns)];
+            const real sy = sign * c.y;
+            const cpx<real> y1 = {x1.x * c.x - x1.y * sy, x1.x * sy + x1.y * c.x};
+            const int idx = ((j - k) << 1) + k;
+            b[l * nos + idx] = cadd(x0, y1);
+            b[l * nos + idx + Ns] = csub(x0, y1);
+        }
+        __syncthreads();
+        cpx<real> *s = a;
+        a = b;
+        b = s;
+    }
+    return a;
+}
+
+struct FftCall {
+    int npair;
+    int nout;       // fused: number of multipliers / inverse outputs (0, 1, 2)
+    int modes_sel;  // fused: 0 none, 1 store forward modes into Vm, 2 into Gm
+};
+
+// Array dims (x, y, z) of the stage's input and output and their pointers.
+template <typename real>
+struct StageArrays {
+    const cpx<real> *in;
+    cpx<real> *out;
+    int din[3], dout[3];
+};
+
+template <typename real, int AXIS, int MODE>
+__device__ __forceinline__ void select_arrays(const WinDev &w, int pair, int o, StageArrays<real> &sa)
+{
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2], n1 = w.n1;
+    const int64_t po = (int64_t)o * w.npair_cap + pair;
+    auto set = [](int *dd, int a, int b, int c) { dd[0] = a; dd[1] = b; dd[2] = c; };
+    if (MODE == 0 && AXIS == 0) {  // G -> A1
+        sa.in = (const cpx<real> *)w.G + pair * w.szG;
+        sa.out = (cpx<real> *)w.A1 + pair * w.szA1;
+        set(sa.din, ex, ey, ez);
+        set(sa.dout, n1, ey, ez);
+    } else if (MODE == 0 && AXIS == 1) {  // A1 -> A2
+        sa.in = (const cpx<real> *)w.A1 + pair * w.szA1;
+        sa.out = (cpx<real> *)w.A2 + pair * w.szA2;
+        set(sa.din, n1, ey, ez);
+        set(sa.dout, n1, n1, ez);
+    } else if (MODE == 2 && AXIS == 2) {  // A2 -> A3[o]
+        sa.in = (const cpx<real> *)w.A2 + pair * w.szA2;
+        sa.out = (cpx<real> *)w.A3 + po * w.szA3;
+        set(sa.din, n1, n1, ez);
+        set(sa.dout, n1, n1, ez);
+    } else if (MODE == 2 && AXIS == 1) {  // d = 2: A1 -> A3[o]
+        sa.in = (const cpx<real> *)w.A1 + pair * w.szA1;
+        sa.out = (cpx<real> *)w.A3 + po * w.szA3;
+        set(sa.din, n1, ey, 1);
+        set(sa.dout, n1, ey, 1);
+    } else if (MODE == 2 && AXIS == 0) {  // d = 1: G -> H[o]
+        sa.in = (const cpx<real> *)w.G + pair * w.szG;
+        sa.out = (cpx<real> *)w.H + po * w.szH;
+        set(sa.din, ex, 1, 1);
+        set(sa.dout, ex, 1, 1);
+    } else if (MODE == 1 && AXIS == 1) {  // A3[o] -> A4[o]
+        sa.in = (const cpx<real> *)w.A3 + po * w.szA3;
+        sa.out = (cpx<real> *)w.A4 + po * w.szA4;
+        set(sa.din, n1, n1, ez);
+        set(sa.dout, n1, ey, ez);
+    } else {  // MODE 1, AXIS 0: d = 3 A4[o] -> H[o], d = 2 A3[o] -> H[o]
+        sa.in = w.d == 3 ? (const cpx<real> *)w.A4 + po * w.szA4 : (const cpx<real> *)w.A3 + po * w.szA3;
+        sa.out = (cpx<real> *)w.H + po * w.szH;
+        set(sa.din, n1, ey, ez);
+        set(sa.dout, ex, ey, ez);
+    }
+}
+
+__device__ __forceinline__ int64_t line_addr(const int *dims, int axis, int i0, int i1, int i2)
+{
+    return ((int64_t)i2 * dims[1] + i1) * dims[0] + i0;
+}
+
+template <typename real, int AXIS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins, const LineGroup *__restrict__ groups,
+                                                FftCall call)
+{
+    constexpr int L = sizeof(real) == 4 ? 16 : 8;
+    using C = cpx<real>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const LineGroup lg = groups[blockIdx.x];
+    const WinDev &w = wins[lg.win];
+    const int nos = w.nos, n1 = w.n1, half = w.n >> 1;
+    int pair, o;
+    if (MODE == 1) {
+        pair = blockIdx.y % call.npair;
+        o = blockIdx.y / call.npair;
+    } else {
+        pair = blockIdx.y;
+        o = 0;
+    }
+    StageArrays<real> sa;
+    select_arrays<real, AXIS, MODE>(w, pair, o, sa);
+
+    C *tw = (C *)smem_raw;
+    C *buf0 = tw + kMaxNos / 2;
+    C *buf1 = buf0 + L * kMaxNos;
+    C *buf2 = buf1 + L * kMaxNos;
+    for (int q = threadIdx.x; q < nos / 2; q += kBlock) {
+        double s, c;
+        sincospi(2.0 * q / nos, &s, &c);
+        tw[q] = {(real)c, (real)s};
+    }
+
+    // lines of this group: coordinates (a, b) of the two non-transform axes
+    const int *dims = sa.din;
+    int la0 = 0, lb = 0, nvalid = 0;  // first line's inner index and outer index
+    if (AXIS == 0) {
+        const int rows = dims[1] * dims[2];
+        la0 = lg.grp * L;  // row index
+        nvalid = min(L, rows - la0);
+    } else {
+        const int e0 = dims[0];
+        const int ng0 = (e0 + L - 1) / L;
+        lb = lg.grp / ng0;
+        la0 = (lg.grp % ng0) * L;
+        nvalid = min(L, e0 - la0);
+    }
+    const int Lin = dims[AXIS];
+    const int Lout = sa.dout[AXIS];
+
+    auto addr = [&](const int *dd, int l, int q) -> int64_t {
+        if (AXIS == 0) {
+            const int row = la0 + l;
+            return (int64_t)row * dd[0] + q;
+        } else if (AXIS == 1) {
+            return line_addr(dd, 1, la0 + l, q, lb);
+        } else {
+            return line_addr(dd, 2, la0 + l, lb, q);
+        }
+    };
+
+    for (int i = threadIdx.x; i < L * nos; i += kBlock)
+        buf0[i] = {real(0), real(0)};
+    __syncthreads();
+    for (int t = threadIdx.x; t < L * Lin; t += kBlock) {
+        int l, q;
+        if (AXIS == 0) {
+            l = t / Lin;
+            q = t - l * Lin;
+        } else {
+            l = t % L;
+            q = t / L;
+        }
+        if (l < nvalid) {
+            const int p = MODE == 1 ? (q - half + nos) % nos : w.lo[AXIS] + q;
+            buf0[l * nos + p] = sa.in[addr(sa.din, l, q)];
+        }
+    }
+    __syncthreads();
+    const real sgn = MODE == 1 ? real(1) : real(-1);
+    C *res = fft_lines<real>(buf0, buf1, tw, nos, L, sgn);
+
+    if (MODE == 0 || MODE == 1) {
+        for (int t = threadIdx.x; t < L * Lout; t += kBlock) {
+            int l, q;
+            if (AXIS == 0) {
+                l = t / Lout;
+                q = t - l * Lout;
+            } else {
+                l = t % L;
+                q = t / L;
+            }
+            if (l < nvalid) {
+                const int p = MODE == 0 ? (q - half + nos) % nos : w.lo[AXIS] + q;
+                sa.out[addr(sa.dout, l, q)] = res[l * nos + p];
+            }
+        }
+        return;
+    }
+
+    // fused: forward result in res; multiply and transform back for each output
+    C *fw = res;
+    C *x0 = res == buf0 ? buf1 : buf0;
+    C *x1 = buf2;
+    // mode-space offset of each line inside the multiplier array
+    auto lineoff = [&](int l) -> int64_t {
+        if (AXIS == 2)
+            return (int64_t)lb * n1 + la0 + l;
+        if (AXIS == 1)
+            return la0 + l;
+        return 0;
+    };
+    int64_t stride_c = 1;
+    for (int a = 0; a < AXIS; ++a)
+        stride_c *= n1;
+    if (call.modes_sel) {
+        C *M = (C *)(call.modes_sel == 1 ? w.Vm : w.Gm) + (int64_t)pair * w.szM;
+        for (int t = threadIdx.x; t < L * n1; t += kBlock) {
+            const int l = t % L, c = t / L;
+            if (l < nvalid)
+                M[c * stride_c + lineoff(l)] = fw[l * nos + (c - half + nos) % nos];
+        }
+    }
+    for (int oo = 0; oo < call.nout; ++oo) {
+        const real *B = (const real *)(oo == 0 ? w.Bk : w.Bd);
+        for (int i = threadIdx.x; i < L * nos; i += kBlock)
+            x0[i] = {real(0), real(0)};
+        __syncthreads();
+        for (int t = threadIdx.x; t < L * n1; t += kBlock) {
+            const int l = t % L, c = t / L;
+            if (l < nvalid) {
+                const int p = (c - half + nos) % nos;
+                const real bm = B[c * stride_c + lineoff(l)];
+                const C v = fw[l * nos + p];
+                x0[l * nos + p] = {v.x * bm, v.y * bm};
+            }
+        }
+        __syncthreads();
+        C *r2 = fft_lines<real>(x0, x1, tw, nos, L, real(1));
+        C *out = sa.out + (int64_t)oo * w.npair_cap * w.szH * (AXIS == 0) +
+                 (int64_t)oo * w.npair_cap * w.szA3 * (AXIS != 0);
+        for (int t = threadIdx.x; t < L * Lout; t += kBlock) {
+            int l, q;
+            if (AXIS == 0) {
+                l = t / Lout;
+                q = t - l * Lout;
+            } else {
+                l = t % L;
+                q = t / L;
+            }
+            if (l < nvalid)
+                out[addr(sa.dout, l, q)] = r2[l * nos + w.lo[AXIS] + q];
+        }
+        __syncthreads();
+        if (r2 != x0) {  // keep x0/x1 roles for the next output
+            C *s = x0;
+            x0 = x1;
+            x1 = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 window sum, derivative scalings, caller order
+
+__global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
+{
+    const ProbDev p = get_prob(io, blockIdx.y);
+    const int64_t total = p.N * (int64_t)R;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t r = e / p.N, i = e - r * p.N;
+        double y = 0.0;
+        for (int wi = p.wbeg; wi < p.wend; ++wi) {
+            const WinDev &w = wins[wi];
+            const double kv = w.Yw[r * w.N + i];
+            y += w.sig2 * kv;
+            const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
+            if ((mode & 2) && p.dYs)
+                p.dYs[blk + i + r * p.ldy] = w.dsig * kv;
+            if ((mode & 4) && p.dYl)
+                p.dYl[blk + i + r * p.ldy] = w.der_scale * w.Yw[(w.Rcap + r) * w.N + i];
+        }
+        if ((mode & 1) && p.Y)
+            p.Y[i + r * p.ldy] = y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fourier-domain inner products for the vjp: sum over pairs and modes of
+// Re(conj(G^_k) B_k V^_k) for the kernel and derivative multipliers.
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_mode_dot(const WinDev *__restrict__ wins, int win, int npair,
+                                                     double *partial)
+{
+    const WinDev &w = wins[win];
+    const int64_t total = (int64_t)npair * w.szM;
+    const cpx<real> *Gm = (const cpx<real> *)w.Gm;
+    const cpx<real> *Vm = (const cpx<real> *)w.Vm;
+    const real *Bk = (const real *)w.Bk;
+    const real *Bd = (const real *)w.Bd;
+    double sk = 0.0, sd = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t idx = e % w.szM;
+        const cpx<real> g = Gm[e], v = Vm[e];
+        const double re = (double)g.x * (double)v.x + (double)g.y * (double)v.y;
+        sk += (double)Bk[idx] * re;
+        sd += (double)Bd[idx] * re;
+    }
+    __shared__ double red[2][kBlock];
+    red[0][threadIdx.x] = sk;
+    red[1][threadIdx.x] = sd;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0][0];
+        partial[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+__global__ void k_mode_dot_finish(const WinDev *__restrict__ wins, int win, int nblk, const double *partial,
+                                  double *grad_ell, double *grad_sig)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double sk = 0.0, sd = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        sk += partial[2 * b];
+        sd += partial[2 * b + 1];
+    }
+    const WinDev &w = wins[win];
+    if (grad_ell)
+        grad_ell[0] = w.der_scale * sd;
+    if (grad_sig)
+        grad_sig[0] = w.dsig * sk;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int lines_per_group(int precision) { return precision == ADDK_FP32 ? 16 : 8; }
+
+static size_t real_size(int precision) { return precision == ADDK_FP32 ? sizeof(float) : sizeof(double); }
+
+static int pick_rb(int vol, int precision, int D)
+{
+    const size_t rs = real_size(precision);
+    const size_t wv = (size_t)16 * D * kMaxW * rs;
+    int rb = 16;
+    while (rb > 1 && (size_t)rb * vol * rs + wv > (size_t)kLdsBudget)
+        rb >>= 1;
+    return rb;
+}
+
+static int ngroups_stage(const WinDev &w, int st, int L)
+{
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2], n1 = w.n1;
+    auto cdiv = [](int a, int b) { return (a + b - 1) / b; };
+    switch (st) {
+    case ST_FWD0:
+        return w.d >= 2 ? cdiv(ey * ez, L) : 0;
+    case ST_FWD1:
+        return w.d == 3 ? ez * cdiv(n1, L) : 0;
+    case ST_FUSED2:
+        return w.d == 3 ? n1 * cdiv(n1, L) : 0;
+    case ST_FUSED1:
+        return w.d == 2 ? cdiv(n1, L) : 0;
+    case ST_FUSED0:
+        return w.d == 1 ? 1 : 0;
+    case ST_INV1:
+        return w.d == 3 ? ez * cdiv(n1, L) : 0;
+    case ST_INV0:
+        return w.d >= 2 ? cdiv(ey * ez, L) : 0;
+    }
+    return 0;
+}
+
+static void free_dev(void *p)
+{
+    if (p)
+        (void)hipFree(p);
+}
+
+void engine_free(Engine &E)
+{
+    free_dev(E.d_wins);
+    for (int d = 0; d < 4; ++d)
+        free_dev(E.d_chunks[d]);
+    for (int s = 0; s < ST_COUNT; ++s)
+        free_dev(E.d_groups[s]);
+    free_dev(E.ws);
+    free_dev(E.yw);
+    free_dev(E.d_probs);
+    free_dev(E.d_partial);
+    E = Engine();
+}
+
+// Device work lists for the engine's windows (descriptors are uploaded by
+// engine_ensure_workspace, which knows the workspace pointers).
+addk_status engine_build_device(Engine &E, int precision)
+{
+    E.precision = precision;
+    const int L = lines_per_group(precision);
+    std::vector<Chunk> ch[4];
+    std::vector<LineGroup> gr[ST_COUNT];
+    for (int d = 0; d < 4; ++d) {
+        E.maxvol[d] = 0;
+        E.rb[d] = 0;
+    }
+    for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
+        const WinDev &w = E.wdev[wi];
+        const WinHost &h = E.plans[E.wplan[wi]]->wins[E.wlocal[wi]];
+        for (const Chunk &c : h.chunks) {
+            Chunk cc = c;
+            cc.win = (int)wi;
+            ch[w.d].push_back(cc);
+        }
+        E.maxvol[w.d] = std::max(E.maxvol[w.d], w.S[0] * w.S[1] * w.S[2]);
+        for (int s = 0; s < ST_COUNT; ++s) {
+            const int ng = ngroups_stage(w, s, L);
+            for (int g = 0; g < ng; ++g)
+                gr[s].push_back({(int)wi, g});
+        }
+    }
+    for (int d = 1; d <= 3; ++d) {
+        if (E.maxvol[d])
+            E.rb[d] = pick_rb(E.maxvol[d], precision, d);
+        E.nchunks[d] = (int)ch[d].size();
+        free_dev(E.d_chunks[d]);
+        E.d_chunks[d] = nullptr;
+        if (!ch[d].empty()) {
+            hipError_t e = hipMalloc(&E.d_chunks[d], ch[d].size() * sizeof(Chunk));
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMalloc(chunks)");
+            e = hipMemcpy(E.d_chunks[d], ch[d].data(), ch[d].size() * sizeof(Chunk), hipMemcpyHostToDevice);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMemcpy(chunks)");
+        }
+    }
+    for (int s = 0; s < ST_COUNT; ++s) {
+        E.ngroups[s] = (int)gr[s].size();
+        free_dev(E.d_groups[s]);
+        E.d_groups[s] = nullptr;
+        if (!gr[s].empty()) {
+            hipError_t e = hipMalloc(&E.d_groups[s], gr[s].size() * sizeof(LineGroup));
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMalloc(groups)");
+            e = hipMemcpy(E.d_groups[s], gr[s].data(), gr[s].size() * sizeof(LineGroup), hipMemcpyHostToDevice);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMemcpy(groups)");
+        }
+    }
+    return ADDK_OK;
+}
+
+// Allocate grids for at least ceil(R/2) complex grids per window and the FP64
+// per-window products for R right-hand sides; upload the descriptors.
+addk_status engine_ensure_workspace(Engine &E, int R)
+{
+    const int npair = (R + 1) / 2;
+    const bool grow = npair > E.npair_cap || R > E.rcap || !E.ws;
+    if (!grow)
+        return E.dirty ? engine_upload(E) : ADDK_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceSynchronize");
+    const int cap = std::max(npair, E.npair_cap);
+    const int64_t rcap = std::max<int64_t>(R, E.rcap);
+    const size_t cs = 2 * real_size(E.precision);
+    int64_t total = 0, ytotal = 0;
+    for (WinDev &w : E.wdev) {
+        const int64_t ex = w.ext[0], ey = w.ext[1], ez = w.ext[2], n1 = w.n1;
+        w.szG = ex * ey * ez;
+        w.szH = w.szG;
+        w.szA1 = w.d >= 2 ? n1 * ey * ez : 0;
+        w.szA2 = w.d == 3 ? n1 * n1 * ez : 0;
+        w.szA3 = w.d == 3 ? n1 * n1 * ez : (w.d == 2 ? n1 * ey : 0);
+        w.szA4 = w.d == 3 ? n1 * ey * ez : 0;
+        w.szM = w.d == 3 ? n1 * n1 * n1 : (w.d == 2 ? n1 * n1 : n1);
+        total += (int64_t)cap * (w.szG + w.szA1 + w.szA2 + 2 * (w.szA3 + w.szA4 + w.szH) + 2 * w.szM);
+        ytotal += 2 * rcap * w.N;
+    }
+    free_dev(E.ws);
+    free_dev(E.yw);
+    E.ws = nullptr;
+    E.yw = nullptr;
+    const int64_t bytes = std::max<int64_t>(total * (int64_t)cs, 256);
+    e = hipMalloc(&E.ws, bytes);
+    if (e != hipSuccess) {
+        set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        return ADDK_ERR_OOM;
+    }
+    const int64_t ybytes = std::max<int64_t>(ytotal * (int64_t)sizeof(double), 256);
+    e = hipMalloc(&E.yw, ybytes);
+    if (e != hipSuccess) {
+        set_error("per-window product buffer allocation failed");
+        return ADDK_ERR_OOM;
+    }
+    E.ws_bytes = bytes;
+    E.yw_bytes = ybytes;
+    char *p = (char *)E.ws;
+    double *yp = E.yw;
+    for (WinDev &w : E.wdev) {
+        auto take = [&](int64_t n) {
+            void *q = p;
+            p += n * cs;
+            return q;
+        };
+        w.G = take(cap * w.szG);
+        w.A1 = take(cap * w.szA1);
+        w.A2 = take(cap * w.szA2);
+        w.A3 = take(2 * cap * w.szA3);
+        w.A4 = take(2 * cap * w.szA4);
+        w.H = take(2 * cap * w.szH);
+        w.Vm = take(cap * w.szM);
+        w.Gm = take(cap * w.szM);
+        w.npair_cap = cap;
+        w.Rcap = rcap;
+        w.Yw = yp;
+        yp += 2 * rcap * w.N;
+    }
+    E.npair_cap = cap;
+    E.rcap = rcap;
+    return engine_upload(E);
+}
+
+// Upload the window descriptors (after workspace or parameter changes).  Synchronous.
+addk_status engine_upload(Engine &E)
+{
+    hipError_t e;
+    if (!E.d_wins) {
+        e = hipMalloc(&E.d_wins, std::max<size_t>(1, E.wdev.size()) * sizeof(WinDev));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(descriptors)");
+    }
+    if (!E.wdev.empty()) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess)
+            return hip_fail(e, "hipDeviceSynchronize");
+        e = hipMemcpy(E.d_wins, E.wdev.data(), E.wdev.size() * sizeof(WinDev), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMemcpy(descriptors)");
+    }
+    E.dirty = false;
+    return ADDK_OK;
+}
+
+template <typename real, int D, int RB>
+static void launch_spread_rb(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    const size_t sh = ((size_t)RB * E.maxvol[D] + 16 * D * kMaxW) * sizeof(real);
+    dim3 grid(E.nchunks[D], (R + RB - 1) / RB);
+    hipLaunchKernelGGL((k_spread<real, D, RB>), grid, dim3(kBlock), sh, st, E.d_wins, E.d_chunks[D], io, R);
+}
+
+template <typename real, int D, int RB>
+static void launch_interp_rb(Engine &E, int R, int nout, hipStream_t st)
+{
+    const size_t sh = ((size_t)RB * E.maxvol[D] + 16 * D * kMaxW) * sizeof(real);
+    dim3 grid(E.nchunks[D], (R + RB - 1) / RB, nout);
+    hipLaunchKernelGGL((k_interp<real, D, RB>), grid, dim3(kBlock), sh, st, E.d_wins, E.d_chunks[D], R);
+}
+
+static int rb_for(const Engine &E, int D, int R)
+{
+    int rb = 1;
+    while (rb < R && rb < E.rb[D])
+        rb <<= 1;
+    return rb;
+}
+
+template <typename real, int D>
+static void launch_spread(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    switch (rb_for(E, D, R)) {
+    case 1: launch_spread_rb<real, D, 1>(E, R, io, st); break;
+    case 2: launch_spread_rb<real, D, 2>(E, R, io, st); break;
+    case 4: launch_spread_rb<real, D, 4>(E, R, io, st); break;
+    case 8: launch_spread_rb<real, D, 8>(E, R, io, st); break;
+    default: launch_spread_rb<real, D, 16>(E, R, io, st); break;
+    }
+}
+
+template <typename real, int D>
+static void launch_interp(Engine &E, int R, int nout, hipStream_t st)
+{
+    switch (rb_for(E, D, R)) {
+    case 1: launch_interp_rb<real, D, 1>(E, R, nout, st); break;
+    case 2: launch_interp_rb<real, D, 2>(E, R, nout, st); break;
+    case 4: launch_interp_rb<real, D, 4>(E, R, nout, st); break;
+    case 8: launch_interp_rb<real, D, 8>(E, R, nout, st); break;
+    default: launch_interp_rb<real, D, 16>(E, R, nout, st); break;
+    }
+}
+
+template <typename real, int AXIS, int MODE>
+static void launch_fft(Engine &E, int st_id, int ny, FftCall call, hipStream_t st)
+{
+    if (!E.ngroups[st_id] || ny <= 0)
+        return;
+    constexpr int L = sizeof(real) == 4 ? 16 : 8;
+    const size_t sh = (kMaxNos / 2 + 3 * L * kMaxNos) * sizeof(cpx<real>);
+    hipLaunchKernelGGL((k_fft<real, AXIS, MODE>), dim3(E.ngroups[st_id], ny), dim3(kBlock), sh, st, E.d_wins,
+                       E.d_groups[st_id], call);
+}
+
+template <typename real>
+static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp, IoArgs io, hipStream_t st)
+{
+    const int npair = (R + 1) / 2;
+    const int nw = (int)E.wdev.size();
+    if (nw == 0)
+        return ADDK_OK;
+    hipLaunchKernelGGL(k_zero_grids<real>, dim3(64, nw), dim3(kBlock), 0, st, E.d_wins, npair);
+    if (E.nchunks[1]) launch_spread<real, 1>(E, R, io, st);
+    if (E.nchunks[2]) launch_spread<real, 2>(E, R, io, st);
+    if (E.nchunks[3]) launch_spread<real, 3>(E, R, io, st);
+    FftCall fc{npair, nout, modes_sel};
+    launch_fft<real, 0, 0>(E, ST_FWD0, npair, fc, st);
+    launch_fft<real, 1, 0>(E, ST_FWD1, npair, fc, st);
+    launch_fft<real, 2, 2>(E, ST_FUSED2, npair, fc, st);
+    launch_fft<real, 1, 2>(E, ST_FUSED1, npair, fc, st);
+    launch_fft<real, 0, 2>(E, ST_FUSED0, npair, fc, st);
+    if (nout > 0) {
+        launch_fft<real, 1, 1>(E, ST_INV1, npair * nout, fc, st);
+        launch_fft<real, 0, 1>(E, ST_INV0, npair * nout, fc, st);
+        if (interp) {
+            if (E.nchunks[1]) launch_interp<real, 1>(E, R, nout, st);
+            if (E.nchunks[2]) launch_interp<real, 2>(E, R, nout, st);
+            if (E.nchunks[3]) launch_interp<real, 3>(E, R, nout, st);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "stage kernel launch");
+    return ADDK_OK;
+}
+
+addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io, hipStream_t st)
+{
+    addk_status s = engine_ensure_workspace(E, R);
+    if (s != ADDK_OK)
+        return s;
+    const int modes_sel = vmodes_only ? 1 : (store_gmodes ? 2 : 0);
+    const int no = vmodes_only ? 0 : nout;
+    if (E.precision == ADDK_FP32)
+        return run_t<float>(E, R, no, modes_sel, !vmodes_only, io, st);
+    return run_t<double>(E, R, no, modes_sel, !vmodes_only, io, st);
+}
+
+addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st)
+{
+    if (E.wdev.empty())
+        return ADDK_OK;
+    int64_t maxN = 0;
+    for (const ProbDev &p : E.probs)
+        maxN = std::max(maxN, p.N);
+    if (!io.table)
+        maxN = io.single.N;
+    const int64_t work = maxN * R;
+    if (work == 0)
+        return ADDK_OK;
+    const int bx = (int)std::min<int64_t>((work + kBlock - 1) / kBlock, 4096);
+    const int ny = io.table ? E.nprob : 1;
+    hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "combine launch");
+    return ADDK_OK;
+}
+
+// grad outputs: d_out_ell[w], d_out_sig[w] for every window (device pointers, may be null)
+addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st)
+{
+    const int nblk = 256;
+    const int64_t need = (int64_t)2 * nblk * std::max<int64_t>(1, (int64_t)E.wdev.size());
+    if (E.partial_cap < need) {
+        free_dev(E.d_partial);
+        E.d_partial = nullptr;
+        hipError_t e = hipMalloc(&E.d_partial, need * sizeof(double));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(partials)");
+        E.partial_cap = need;
+    }
+    for (int wi = 0; wi < (int)E.wdev.size(); ++wi) {
+        double *part = E.d_partial + (int64_t)2 * nblk * wi;
+        if (E.precision == ADDK_FP32)
+            hipLaunchKernelGGL(k_mode_dot<float>, dim3(nblk), dim3(kBlock), 0, st, E.d_wins, wi, npair, part);
+        else
+            hipLaunchKernelGGL(k_mode_dot<double>, dim3(nblk), dim3(kBlock), 0, st, E.d_wins, wi, npair, part);
+        hipLaunchKernelGGL(k_mode_dot_finish, dim3(1), dim3(64), 0, st, E.d_wins, wi, nblk, part,
+                           grad_ell ? grad_ell + E.wlocal[wi] : nullptr, grad_sig ? grad_sig + E.wlocal[wi] : nullptr);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "mode-dot launch");
+    return ADDK_OK;
+}
+
+}  // namespace addk

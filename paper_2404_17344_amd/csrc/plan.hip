@@ -1,0 +1,907 @@
+// Plan construction (torus map, grid box, tile sort) and the Fourier
+// multipliers of the NFFT-based fast summation.
+//
+// Torus map ("Scaling the data" section, generalised per window): a window's
+// points are centred on their bounding box and divided by a torus period T_w,
+// x~ = (x - c_w) / T_w, so that all differences lie well inside one period.
+// T_w follows either the automatic rule (the image error of the periodised
+// kernel balanced against the error of truncating its Fourier series to
+// |k| <= n/2) or the paper's prescaling rule.
+//
+// Multipliers: the trigonometric sum of eq. (6) uses coefficients c_k of the
+// T-periodic kernel, either the continuous Fourier transform sampled at k/T
+// (periodisation by summation) or the DFT of n^d kernel samples (Lemma 1).
+// The real part of the sum over the non-symmetric index set I_n equals the sum
+// over k in {-n/2..n/2}^d with weight 1/2 on modes that lie in exactly one of
+// I_n and -I_n; that symmetric form keeps real inputs real, which lets two
+// real right-hand sides share one complex grid.  The window deconvolution
+// 1 / prod_i Psi(k_i)^2 (Psi: Fourier transform of the spreading window) is
+// folded into the same array.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "addk_internal.h"
+
+namespace addk {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+addk_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return ADDK_ERR_HIP;
+}
+
+static addk_status fail(addk_status s, const std::string &msg)
+{
+    set_error(msg);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// host math
+
+static double kb_psi_host(double z, int m, double b)
+{
+    const double mm = m;
+    double s2 = mm * mm - z * z;
+    if (s2 < 0.0)
+        s2 = 0.0;
+    double s = std::sqrt(s2);
+    const double ie = 1.0 / (1.0 - std::exp(-2.0 * b * mm));
+    if (s < 1e-12)
+        return mm * 2.0 * b * std::exp(-b * mm) * ie;
+    return mm * (std::exp(b * (s - mm)) - std::exp(-b * (s + mm))) * ie / s;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), z1, dp;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            dp = n * (z * p1 - p2) / (z * z - 1.0);
+            z1 = z;
+            z = z1 - p1 / dp;
+            if (std::fabs(z - z1) < 1e-16)
+                break;
+        }
+        double p1 = 1.0, p2 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+            const double p3 = p2;
+            p2 = p1;
+            p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        dp = n * (z * p1 - p2) / (z * z - 1.0);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Psi(k) = int_{-m}^{m} psi(z) cos(2 pi z k / nos) dz (psi is even and smooth on
+// [-m, m], so Gauss-Legendre converges quickly).
+static double window_ft(int m, int nos, double b, double k)
+{
+    static std::mutex mu;
+    static std::vector<double> gx, gw;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (gx.empty())
+            gauss_legendre(160, gx, gw);
+    }
+    double s = 0.0;
+    for (size_t q = 0; q < gx.size(); ++q) {
+        const double z = m * gx[q];
+        s += gw[q] * kb_psi_host(z, m, b) * std::cos(2.0 * M_PI * z * k / nos);
+    }
+    return m * s;
+}
+
+static double torus_period(int kernel, double L, double ell, int n, uint32_t rule, int dmax)
+{
+    if ((rule & ADDK_TORUS_PAPER) && L > 0.0)
+        return 2.0 * L * std::sqrt((double)dmax);
+    if (kernel == ADDK_GAUSSIAN)
+        return 0.5 * (L + std::sqrt(L * L + 4.0 * M_PI * ell * ell * n));
+    return L + ell * std::log((double)n);
+}
+
+// A-priori relative error estimate of one window: image + truncation + window terms.
+static double error_estimate(int kernel, double L, double T, double ell, int n, int m, double sig)
+{
+    double img, trunc;
+    if (kernel == ADDK_GAUSSIAN) {
+        img = std::exp(-(T - L) * (T - L) / (2.0 * ell * ell));
+        trunc = std::exp(-2.0 * M_PI * M_PI * ell * ell * (n / 2.0) * (n / 2.0) / (T * T));
+    } else {
+        img = std::exp(-(T - L) / ell);
+        trunc = T / (M_PI * M_PI * ell * n);
+    }
+    const double win = 4.0 * std::exp(-2.0 * M_PI * m * std::sqrt(1.0 - 1.0 / sig));
+    return img + trunc + win;
+}
+
+// ---------------------------------------------------------------------------
+// plan kernels
+
+__global__ void k_minmax(const double *__restrict__ X, int64_t ldx, int64_t N, int d, int f0, int f1, int f2,
+                         double *partial)
+{
+    __shared__ double red[6][256];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int f[3] = {f0, f1, f2};
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x)
+        for (int dd = 0; dd < d; ++dd) {
+            const double x = X[j * ldx + f[dd]];
+            mn[dd] = fmin(mn[dd], x);
+            mx[dd] = fmax(mx[dd], x);
+        }
+    for (int dd = 0; dd < 3; ++dd) {
+        red[dd][threadIdx.x] = mn[dd];
+        red[3 + dd][threadIdx.x] = mx[dd];
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int dd = 0; dd < 3; ++dd) {
+                red[dd][threadIdx.x] = fmin(red[dd][threadIdx.x], red[dd][threadIdx.x + s]);
+                red[3 + dd][threadIdx.x] = fmax(red[3 + dd][threadIdx.x], red[3 + dd][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6)
+        partial[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct KeyArgs {
+    int d, nos, m, W;
+    int f[3];
+    double c[3];
+    double invT;
+    int lo[3], ext[3], tb[3], ntile[3];
+};
+
+template <typename real>
+__device__ __forceinline__ int base_cell_p(real u, int m)
+{
+    return (int)floor(u) - m + 1;
+}
+
+// grid coordinate relative to the box, rounded to the plan's precision; tile key
+template <typename real>
+__global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, KeyArgs a, real *ucoord,
+                       int32_t *key, int32_t *hist, int32_t *bad)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        int t[3] = {0, 0, 0};
+        bool ok = true;
+        for (int dd = 0; dd < a.d; ++dd) {
+            const double x = X[j * ldx + a.f[dd]];
+            const double u = ((x - a.c[dd]) * a.invT + 0.5) * a.nos - a.lo[dd];
+            const real ur = (real)u;
+            ucoord[dd * N + j] = ur;
+            const int b = base_cell_p(ur, a.m);
+            if (b < 0 || b + a.W > a.ext[dd])
+                ok = false;
+            t[dd] = b / a.tb[dd];
+            if (t[dd] >= a.ntile[dd])
+                ok = false;
+        }
+        if (!ok) {
+            atomicOr(bad, 1);
+            key[j] = 0;
+            continue;
+        }
+        const int k = t[0] + a.ntile[0] * (t[1] + a.ntile[1] * t[2]);
+        key[j] = k;
+        atomicAdd(&hist[k], 1);
+    }
+}
+
+template <typename real>
+__global__ void k_scatter(int64_t N, int d, const real *__restrict__ ucoord, const int32_t *__restrict__ key,
+                          int32_t *cursor, real *sorted, int32_t *perm)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+        const int pos = atomicAdd(&cursor[key[j]], 1);
+        for (int dd = 0; dd < d; ++dd)
+            sorted[dd * N + pos] = ucoord[dd * N + j];
+        perm[pos] = (int32_t)j;
+    }
+}
+
+// Continuous Fourier transform of the kernel (der = 0) or of its derivative
+// kernel (der = 1) at squared frequency xi2, in d dimensions.
+__device__ double kernel_ft_dev(int kernel, double xi2, double ell, int d, int der)
+{
+    const double pi = 3.14159265358979323846;
+    if (kernel == ADDK_GAUSSIAN) {
+        const double base = pow(ell * sqrt(2.0 * pi), (double)d) * exp(-2.0 * pi * pi * ell * ell * xi2);
+        return der ? (0.5 * d - 2.0 * pi * pi * ell * ell * xi2) * base : base;
+    }
+    const double cd = d == 1 ? 2.0 : (d == 2 ? 2.0 * pi : 8.0 * pi);
+    const double u = 4.0 * pi * pi * ell * ell * xi2;
+    const double base = cd * pow(ell, (double)d) / pow(1.0 + u, 0.5 * (d + 1));
+    return der ? (d - (d + 1) * u / (1.0 + u)) * base : base;
+}
+
+__device__ __forceinline__ double herm_weight(const int *k, int d, int half)
+{
+    int kp = 0, km = 0;
+    for (int i = 0; i < d; ++i) {
+        kp += k[i] == half;
+        km += k[i] == -half;
+    }
+    return 0.5 * ((kp == 0 ? 1.0 : 0.0) + (km == 0 ? 1.0 : 0.0));
+}
+
+__global__ void k_coef_analytic(double *Bk, double *Bd, int d, int n, double T, double ell, int kernel,
+                                const double *__restrict__ psi)
+{
+    const int n1 = n + 1, half = n / 2;
+    int64_t tot = n1;
+    for (int i = 1; i < d; ++i)
+        tot *= n1;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+        int k[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+        int64_t r = idx;
+        double xi2 = 0.0, dec = 1.0;
+        for (int i = 0; i < d; ++i) {
+            c[i] = (int)(r % n1);
+            r /= n1;
+            k[i] = c[i] - half;
+            xi2 += (double)k[i] * k[i];
+            dec /= psi[c[i]] * psi[c[i]];
+        }
+        xi2 /= T * T;
+        const double om = herm_weight(k, d, half) * dec / pow(T, (double)d);
+        Bk[idx] = om * kernel_ft_dev(kernel, xi2, ell, d, 0);
+        Bd[idx] = om * kernel_ft_dev(kernel, xi2, ell, d, 1);
+    }
+}
+
+// kernel samples kappa(T j / n), j in I_n^d (array index j + n/2 per axis); complex output
+__global__ void k_samples(double2 *s, int d, int n, double T, double ell, int kernel, int der)
+{
+    int64_t tot = n;
+    for (int i = 1; i < d; ++i)
+        tot *= n;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = idx;
+        double r2 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            const int j = (int)(r % n) - n / 2;
+            r /= n;
+            const double x = T * j / n;
+            r2 += x * x;
+        }
+        double v;
+        if (kernel == ADDK_GAUSSIAN) {
+            const double e = exp(-r2 / (2.0 * ell * ell));
+            v = der ? r2 / (2.0 * ell * ell) * e : e;
+        } else {
+            const double rr = sqrt(r2);
+            const double e = exp(-rr / ell);
+            v = der ? rr / ell * e : e;
+        }
+        s[idx] = make_double2(v, 0.0);
+    }
+}
+
+// out_k = sum_j in_j exp(-2 pi i j k / n) along one axis; j, k in I_n (index + n/2)
+__global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, int n, int axis)
+{
+    int64_t tot = n, stride = 1;
+    for (int i = 1; i < d; ++i)
+        tot *= n;
+    for (int i = 0; i < axis; ++i)
+        stride *= n;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int kc = (int)((idx / stride) % n);
+        const int64_t basei = idx - (int64_t)kc * stride;
+        const int k = kc - n / 2;
+        double re = 0.0, im = 0.0;
+        for (int jc = 0; jc < n; ++jc) {
+            const int j = jc - n / 2;
+            const int jk = (int)((((int64_t)j * k) % n + n) % n);
+            double sn, cs;
+            sincospi(-2.0 * jk / n, &sn, &cs);
+            const double2 v = in[basei + (int64_t)jc * stride];
+            re += v.x * cs - v.y * sn;
+            im += v.x * sn + v.y * cs;
+        }
+        out[idx] = make_double2(re, im);
+    }
+}
+
+__global__ void k_coef_from_hat(const double2 *__restrict__ chat, double *B, int d, int n,
+                                const double *__restrict__ psi)
+{
+    const int n1 = n + 1, half = n / 2;
+    int64_t tot = n1;
+    for (int i = 1; i < d; ++i)
+        tot *= n1;
+    double scale = 1.0;
+    for (int i = 0; i < d; ++i)
+        scale /= n;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+        int k[3] = {0, 0, 0};
+        int64_t r = idx, hidx = 0, hs = 1;
+        double dec = 1.0;
+        for (int i = 0; i < d; ++i) {
+            const int c = (int)(r % n1);
+            r /= n1;
+            k[i] = c - half;
+            const int kk = k[i] == half ? -half : k[i];  // c^ is n-periodic in k
+            hidx += (int64_t)(kk + half) * hs;
+            hs *= n;
+            dec /= psi[c] * psi[c];
+        }
+        B[idx] = herm_weight(k, d, half) * dec * scale * chat[hidx].x;
+    }
+}
+
+__global__ void k_to_float(const double *__restrict__ in, float *out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+// ---------------------------------------------------------------------------
+
+static int64_t ipow(int64_t a, int d)
+{
+    int64_t r = 1;
+    for (int i = 0; i < d; ++i)
+        r *= a;
+    return r;
+}
+
+static hipError_t free_win_arrays(WinHost &w)
+{
+    auto f = [](void *p) {
+        if (p)
+            (void)hipFree(p);
+    };
+    f(w.coords);
+    f(w.perm);
+    if (w.Bk != (void *)w.Bk64)
+        f(w.Bk);
+    if (w.Bd != (void *)w.Bd64)
+        f(w.Bd);
+    f(w.Bk64);
+    f(w.Bd64);
+    w.coords = nullptr;
+    w.perm = nullptr;
+    w.Bk = w.Bd = nullptr;
+    w.Bk64 = w.Bd64 = nullptr;
+    return hipSuccess;
+}
+
+addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
+{
+    const int n1 = pl.n + 1;
+    const double b = M_PI * (2.0 - 1.0 / pl.sigma_os);
+    if (pl.psi_tab.empty()) {
+        pl.psi_tab.resize(n1);
+        for (int c = 0; c < n1; ++c)
+            pl.psi_tab[c] = window_ft(pl.m, pl.nos, b, (double)(c - pl.n / 2));
+        hipError_t e = hipMalloc(&pl.d_psi, n1 * sizeof(double));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(psi)");
+        e = hipMemcpy(pl.d_psi, pl.psi_tab.data(), n1 * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMemcpy(psi)");
+    }
+    for (WinHost &w : pl.wins) {
+        const int64_t tot = ipow(n1, w.d);
+        hipError_t e;
+        if (!w.Bk64) {
+            if ((e = hipMalloc(&w.Bk64, tot * sizeof(double))) != hipSuccess ||
+                (e = hipMalloc(&w.Bd64, tot * sizeof(double))) != hipSuccess)
+                return fail(ADDK_ERR_OOM, "multiplier allocation failed");
+            if (pl.precision == ADDK_FP32) {
+                if ((e = hipMalloc(&w.Bk, tot * sizeof(float))) != hipSuccess ||
+                    (e = hipMalloc(&w.Bd, tot * sizeof(float))) != hipSuccess)
+                    return fail(ADDK_ERR_OOM, "multiplier allocation failed");
+            } else {
+                w.Bk = w.Bk64;
+                w.Bd = w.Bd64;
+            }
+        }
+        const int nb = (int)std::min<int64_t>((tot + 255) / 256, 1024);
+        if (pl.flags & ADDK_COEF_SAMPLED) {
+            const int64_t ns = ipow(pl.n, w.d);
+            double2 *s0 = nullptr, *s1 = nullptr;
+            if ((e = hipMalloc(&s0, ns * sizeof(double2))) != hipSuccess ||
+                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess)
+                return fail(ADDK_ERR_OOM, "sample buffer allocation failed");
+            const int nbs = (int)std::min<int64_t>((ns + 255) / 256, 1024);
+            for (int der = 0; der < 2; ++der) {
+                hipLaunchKernelGGL(k_samples, dim3(nbs), dim3(256), 0, st, s0, w.d, pl.n, w.T, w.ell, pl.kernel, der);
+                double2 *a = s0, *bb = s1;
+                for (int ax = 0; ax < w.d; ++ax) {
+                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, pl.n, ax);
+                    std::swap(a, bb);
+                }
+                hipLaunchKernelGGL(k_coef_from_hat, dim3(nb), dim3(256), 0, st, a, der ? w.Bd64 : w.Bk64, w.d,
+                                   pl.n, pl.d_psi);
+            }
+            e = hipStreamSynchronize(st);
+            (void)hipFree(s0);
+            (void)hipFree(s1);
+            if (e != hipSuccess)
+                return hip_fail(e, "sampled coefficients");
+        } else {
+            hipLaunchKernelGGL(k_coef_analytic, dim3(nb), dim3(256), 0, st, w.Bk64, w.Bd64, w.d, pl.n, w.T, w.ell,
+                               pl.kernel, pl.d_psi);
+        }
+        if (pl.precision == ADDK_FP32) {
+            hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, st, w.Bk64, (float *)w.Bk, tot);
+            hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, st, w.Bd64, (float *)w.Bd, tot);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return hip_fail(e, "multiplier kernels");
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return hip_fail(e, "multiplier kernels");
+    return ADDK_OK;
+}
+
+static bool is_device_ptr(const void *p)
+{
+    if (!p)
+        return false;
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+static void fill_windesc(const Plan &pl, const WinHost &w, int prob, WinDev &d)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.d = w.d;
+    d.n = pl.n;
+    d.n1 = pl.n + 1;
+    d.nos = pl.nos;
+    d.m = pl.m;
+    d.W = 2 * pl.m;
+    d.prob = prob;
+    d.N = pl.N;
+    for (int i = 0; i < 3; ++i) {
+        d.lo[i] = w.lo[i];
+        d.ext[i] = w.ext[i];
+        d.tb[i] = w.tb[i];
+        d.ntile[i] = w.ntile[i];
+        d.S[i] = w.S[i];
+    }
+    d.b = M_PI * (2.0 - 1.0 / pl.sigma_os);
+    d.inv_e2bm = 1.0 / (1.0 - std::exp(-2.0 * d.b * pl.m));
+    d.sig2 = w.sigma * w.sigma;
+    d.der_scale = d.sig2 * (pl.kernel == ADDK_GAUSSIAN ? 2.0 / w.ell : 1.0 / w.ell);
+    d.dsig = 2.0 * w.sigma;
+    d.coords = w.coords;
+    d.perm = w.perm;
+    d.Bk = w.Bk;
+    d.Bd = w.Bd;
+}
+
+static addk_status build_plan_engine(Plan &pl)
+{
+    Engine &E = pl.eng;
+    E.plans.assign(1, &pl);
+    E.nprob = 1;
+    E.wdev.resize(pl.P);
+    E.wplan.assign(pl.P, 0);
+    E.wlocal.resize(pl.P);
+    for (int w = 0; w < pl.P; ++w) {
+        fill_windesc(pl, pl.wins[w], 0, E.wdev[w]);
+        E.wlocal[w] = w;
+    }
+    E.dirty = true;
+    return engine_build_device(E, pl.precision);
+}
+
+// Lay out one window: box, tiles, sorted coordinates, permutation, chunks.
+static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t ldx, int dmax, hipStream_t st)
+{
+    const int64_t N = pl.N;
+    const int m = pl.m, W = 2 * m, nos = pl.nos;
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    hipError_t e;
+    if (N > 0) {
+        const int nb = (int)std::min<int64_t>((N + 255) / 256, 512);
+        double *part = nullptr;
+        if ((e = hipMalloc(&part, nb * 6 * sizeof(double))) != hipSuccess)
+            return fail(ADDK_ERR_OOM, "allocation failed");
+        hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(256), 0, st, dX, ldx, N, w.d, w.feat[0], w.feat[1], w.feat[2],
+                           part);
+        std::vector<double> hp(nb * 6);
+        e = hipMemcpyAsync(hp.data(), part, nb * 6 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        (void)hipFree(part);
+        if (e != hipSuccess)
+            return hip_fail(e, "bounding box");
+        for (int dd = 0; dd < w.d; ++dd) {
+            mn[dd] = INFINITY;
+            mx[dd] = -INFINITY;
+            for (int b = 0; b < nb; ++b) {
+                mn[dd] = std::min(mn[dd], hp[b * 6 + dd]);
+                mx[dd] = std::max(mx[dd], hp[b * 6 + 3 + dd]);
+            }
+            if (!std::isfinite(mn[dd]) || !std::isfinite(mx[dd]))
+                return fail(ADDK_ERR_INVALID_ARG, "point coordinates must be finite");
+        }
+    }
+    double L = 0.0;
+    for (int dd = 0; dd < w.d; ++dd) {
+        w.center[dd] = 0.5 * (mn[dd] + mx[dd]);
+        L = std::max(L, mx[dd] - mn[dd]);
+    }
+    w.L = L;
+    w.T = torus_period(pl.kernel, L, w.ell, pl.n, pl.flags & ADDK_TORUS_PAPER, dmax);
+    w.eta = M_PI * pl.n * w.ell / (std::sqrt(2.0) * w.T);
+    if (w.eta < 1.0 && !(pl.flags & ADDK_NO_ACCURACY_CHECK))
+        return fail(ADDK_ERR_ACCURACY, "window length scale too small for the grid: eta = pi n l / (sqrt2 T) = " +
+                                           std::to_string(w.eta) + " < 1 (increase n or l)");
+    // box in grid cells (one cell of margin on both sides covers rounding of u)
+    for (int dd = 0; dd < 3; ++dd) {
+        if (dd < w.d) {
+            const double umin = ((mn[dd] - w.center[dd]) / w.T + 0.5) * nos;
+            const double umax = ((mx[dd] - w.center[dd]) / w.T + 0.5) * nos;
+            const int lo = (int)std::floor(umin) - m;
+            const int hi = (int)std::floor(umax) + m + 1;
+            if (lo < 0 || hi > nos - 1)
+                return fail(ADDK_ERR_UNSUPPORTED,
+                            "data extent plus window support does not fit the torus (increase n or oversampling, "
+                            "or use the automatic torus rule)");
+            w.lo[dd] = lo;
+            w.ext[dd] = hi - lo + 1;
+            const int nbase = w.ext[dd] - W + 1;
+            const int tb = w.d == 3 ? 4 : (w.d == 2 ? 16 : 256);
+            w.tb[dd] = std::min(tb, nbase);
+            w.ntile[dd] = (nbase + w.tb[dd] - 1) / w.tb[dd];
+            w.S[dd] = w.tb[dd] + W - 1;
+        } else {
+            w.lo[dd] = 0;
+            w.ext[dd] = 1;
+            w.tb[dd] = 1;
+            w.ntile[dd] = 1;
+            w.S[dd] = 1;
+        }
+    }
+    w.ntiles = (int64_t)w.ntile[0] * w.ntile[1] * w.ntile[2];
+    const size_t rs = pl.precision == ADDK_FP32 ? sizeof(float) : sizeof(double);
+    if ((e = hipMalloc(&w.coords, std::max<int64_t>(1, N * w.d) * rs)) != hipSuccess ||
+        (e = hipMalloc(&w.perm, std::max<int64_t>(1, N) * sizeof(int32_t))) != hipSuccess)
+        return fail(ADDK_ERR_OOM, "point arrays allocation failed");
+    w.chunks.clear();
+    if (N == 0)
+        return ADDK_OK;
+    void *ucoord = nullptr;
+    int32_t *key = nullptr, *hist = nullptr, *bad = nullptr;
+    if ((e = hipMalloc(&ucoord, N * w.d * rs)) != hipSuccess || (e = hipMalloc(&key, N * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&hist, (w.ntiles + 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&bad, sizeof(int32_t))) != hipSuccess)
+        return fail(ADDK_ERR_OOM, "sort buffers allocation failed");
+    KeyArgs ka;
+    std::memset(&ka, 0, sizeof(ka));
+    ka.d = w.d;
+    ka.nos = nos;
+    ka.m = m;
+    ka.W = W;
+    ka.invT = 1.0 / w.T;
+    for (int dd = 0; dd < 3; ++dd) {
+        ka.f[dd] = dd < w.d ? w.feat[dd] : 0;
+        ka.c[dd] = dd < w.d ? w.center[dd] : 0.0;
+        ka.lo[dd] = w.lo[dd];
+        ka.ext[dd] = w.ext[dd];
+        ka.tb[dd] = w.tb[dd];
+        ka.ntile[dd] = w.ntile[dd];
+    }
+    // zero with small kernels (no memset nodes: the same code may be captured)
+    std::vector<int32_t> zeros(w.ntiles + 1, 0);
+    e = hipMemcpy(hist, zeros.data(), (w.ntiles + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bad, zeros.data(), sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMemcpy");
+    const int nb = (int)std::min<int64_t>((N + 255) / 256, 4096);
+    if (pl.precision == ADDK_FP32)
+        hipLaunchKernelGGL(k_keys<float>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (float *)ucoord, key, hist, bad);
+    else
+        hipLaunchKernelGGL(k_keys<double>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (double *)ucoord, key, hist,
+                           bad);
+    std::vector<int32_t> h(w.ntiles + 1);
+    int32_t hbad = 0;
+    e = hipMemcpyAsync(h.data(), hist, w.ntiles * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return hip_fail(e, "tile histogram");
+    if (hbad)
+        return fail(ADDK_ERR_INVALID_ARG, "internal: a point fell outside its grid box");
+    std::vector<int32_t> off(w.ntiles + 1, 0);
+    for (int64_t t = 0; t < w.ntiles; ++t) {
+        off[t + 1] = off[t] + h[t];
+        for (int s = 0; s < h[t]; s += kChunk)
+            w.chunks.push_back({0, (int32_t)t, off[t] + s, std::min(kChunk, h[t] - s)});
+    }
+    e = hipMemcpy(hist, off.data(), w.ntiles * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMemcpy(offsets)");
+    if (pl.precision == ADDK_FP32)
+        hipLaunchKernelGGL(k_scatter<float>, dim3(nb), dim3(256), 0, st, N, w.d, (const float *)ucoord, key, hist,
+                           (float *)w.coords, w.perm);
+    else
+        hipLaunchKernelGGL(k_scatter<double>, dim3(nb), dim3(256), 0, st, N, w.d, (const double *)ucoord, key, hist,
+                           (double *)w.coords, w.perm);
+    e = hipStreamSynchronize(st);
+    (void)hipFree(ucoord);
+    (void)hipFree(key);
+    (void)hipFree(hist);
+    (void)hipFree(bad);
+    if (e != hipSuccess)
+        return hip_fail(e, "tile scatter");
+    return ADDK_OK;
+}
+
+static void plan_release(Plan *pl)
+{
+    if (!pl)
+        return;
+    for (WinHost &w : pl->wins)
+        free_win_arrays(w);
+    if (pl->d_psi)
+        (void)hipFree(pl->d_psi);
+    engine_free(pl->eng);
+    delete pl;
+}
+
+}  // namespace addk
+
+using namespace addk;
+
+extern "C" {
+
+const char *addk_status_string(addk_status s)
+{
+    switch (s) {
+    case ADDK_OK: return "ok";
+    case ADDK_ERR_INVALID_ARG: return "invalid argument";
+    case ADDK_ERR_UNSUPPORTED: return "unsupported configuration";
+    case ADDK_ERR_ACCURACY: return "accuracy requirement cannot be met";
+    case ADDK_ERR_OOM: return "out of memory";
+    case ADDK_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *addk_last_error(void) { return g_last_error.c_str(); }
+
+const char *addk_version(void) { return "addk 0.1 (gfx950)"; }
+
+addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, uint32_t rule, int32_t dmax, double *T)
+{
+    if (!T || !(L >= 0.0) || !(ell > 0.0) || n < 2 || dmax < 1 || (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12))
+        return fail(ADDK_ERR_INVALID_ARG, "addk_torus_period: bad argument");
+    *T = torus_period(kernel, L, ell, n, rule, dmax);
+    return ADDK_OK;
+}
+
+addk_status addk_window_ft(int32_t m, int32_t n_os, double oversampling, double k, double *value)
+{
+    if (!value || m < 1 || n_os < 2 || !(oversampling > 1.0))
+        return fail(ADDK_ERR_INVALID_ARG, "addk_window_ft: bad argument");
+    *value = window_ft(m, n_os, M_PI * (2.0 - 1.0 / oversampling), k);
+    return ADDK_OK;
+}
+
+addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double *X, int64_t ldx, int32_t P,
+                             const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
+                             const double *ell, const double *sigma, int32_t n, int32_t m, double oversampling,
+                             int32_t precision, uint32_t flags, void *stream)
+{
+    if (!out)
+        return fail(ADDK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (N < 0 || N > INT32_MAX || D <= 0 || (N > 0 && (!X || ldx < D)) || P <= 0 || !win_offsets || !win_features ||
+        !ell || !sigma)
+        return fail(ADDK_ERR_INVALID_ARG, "bad sizes or NULL pointers");
+    if (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12)
+        return fail(ADDK_ERR_INVALID_ARG, "kernel must be ADDK_GAUSSIAN or ADDK_MATERN12");
+    if (precision != ADDK_FP64 && precision != ADDK_FP32)
+        return fail(ADDK_ERR_INVALID_ARG, "precision must be ADDK_FP64 or ADDK_FP32");
+    if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK))
+        return fail(ADDK_ERR_INVALID_ARG, "unknown flags");
+    if (n < 4 || (n & 1))
+        return fail(ADDK_ERR_INVALID_ARG, "n must be even and >= 4");
+    if (m < 2 || m > kMaxW / 2)
+        return fail(ADDK_ERR_UNSUPPORTED, "m must be in [2, 8]");
+    if (!(oversampling > 1.0) || !std::isfinite(oversampling))
+        return fail(ADDK_ERR_INVALID_ARG, "oversampling must be > 1");
+    const long nos = std::lround(oversampling * n);
+    if (nos < 16 || nos > kMaxNos || (nos & (nos - 1)) || nos <= n)
+        return fail(ADDK_ERR_UNSUPPORTED, "oversampled grid n_os = round(sigma n) must be a power of two in [16, 128] "
+                                          "and exceed n");
+    if (4 * m > nos)
+        return fail(ADDK_ERR_UNSUPPORTED, "window support 2m must not exceed half the oversampled grid");
+    if (win_offsets[0] != 0)
+        return fail(ADDK_ERR_INVALID_ARG, "win_offsets[0] must be 0");
+    int dmax = 1;
+    for (int w = 0; w < P; ++w) {
+        const int dw = win_offsets[w + 1] - win_offsets[w];
+        if (dw <= 0)
+            return fail(ADDK_ERR_INVALID_ARG, "empty or decreasing window offsets");
+        if (dw > 3)
+            return fail(ADDK_ERR_UNSUPPORTED, "window dimension d_w must be <= 3");
+        for (int q = win_offsets[w]; q < win_offsets[w + 1]; ++q)
+            if (win_features[q] < 0 || win_features[q] >= D)
+                return fail(ADDK_ERR_INVALID_ARG, "window feature index out of range");
+        if (!(ell[w] > 0.0) || !std::isfinite(ell[w]))
+            return fail(ADDK_ERR_INVALID_ARG, "length scales must be positive and finite");
+        if (!(sigma[w] >= 0.0) || !std::isfinite(sigma[w]))
+            return fail(ADDK_ERR_INVALID_ARG, "amplitudes sigma_w must be >= 0 and finite");
+        dmax = std::max(dmax, dw);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Plan *pl = new (std::nothrow) Plan();
+    if (!pl)
+        return fail(ADDK_ERR_OOM, "host allocation failed");
+    (void)hipGetDevice(&pl->device);
+    pl->N = N;
+    pl->D = D;
+    pl->P = P;
+    pl->kernel = kernel;
+    pl->n = n;
+    pl->m = m;
+    pl->nos = (int)nos;
+    pl->precision = precision;
+    pl->flags = flags;
+    pl->sigma_os = (double)nos / n;
+    pl->wins.resize(P);
+    for (int w = 0; w < P; ++w) {
+        WinHost &wh = pl->wins[w];
+        wh.d = win_offsets[w + 1] - win_offsets[w];
+        for (int q = 0; q < 3; ++q)
+            wh.feat[q] = q < wh.d ? win_features[win_offsets[w] + q] : 0;
+        wh.ell = ell[w];
+        wh.sigma = sigma[w];
+    }
+    // device copy of X (contiguous rows)
+    double *dX = nullptr;
+    addk_status s = ADDK_OK;
+    hipError_t e = hipSuccess;
+    if (N > 0) {
+        e = hipMalloc(&dX, N * D * sizeof(double));
+        if (e != hipSuccess) {
+            plan_release(pl);
+            return fail(ADDK_ERR_OOM, "allocation of the point copy failed");
+        }
+        const hipMemcpyKind kind = is_device_ptr(X) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        e = hipMemcpy2D(dX, D * sizeof(double), X, ldx * sizeof(double), D * sizeof(double), N, kind);
+        if (e != hipSuccess) {
+            (void)hipFree(dX);
+            plan_release(pl);
+            return hip_fail(e, "copy of the points");
+        }
+    }
+    for (int w = 0; w < P && s == ADDK_OK; ++w)
+        s = plan_window(*pl, pl->wins[w], dX, D, dmax, st);
+    if (dX)
+        (void)hipFree(dX);
+    if (s == ADDK_OK)
+        s = plan_compute_multipliers(*pl, st);
+    if (s == ADDK_OK)
+        s = build_plan_engine(*pl);
+    if (s != ADDK_OK) {
+        plan_release(pl);
+        return s;
+    }
+    *out = (addk_plan)pl;
+    return ADDK_OK;
+}
+
+addk_status addk_plan_destroy(addk_plan plan)
+{
+    if (!plan)
+        return fail(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    plan_release((Plan *)plan);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceSynchronize");
+    return ADDK_OK;
+}
+
+addk_status addk_plan_update_params(addk_plan plan, const double *ell, const double *sigma, void *stream)
+{
+    if (!plan || !ell || !sigma)
+        return fail(ADDK_ERR_INVALID_ARG, "NULL argument");
+    Plan &pl = *(Plan *)plan;
+    for (int w = 0; w < pl.P; ++w) {
+        if (!(ell[w] > 0.0) || !std::isfinite(ell[w]) || !(sigma[w] >= 0.0) || !std::isfinite(sigma[w]))
+            return fail(ADDK_ERR_INVALID_ARG, "length scales must be > 0 and amplitudes >= 0");
+        const double eta = M_PI * pl.n * ell[w] / (std::sqrt(2.0) * pl.wins[w].T);
+        if (eta < 1.0 && !(pl.flags & ADDK_NO_ACCURACY_CHECK))
+            return fail(ADDK_ERR_ACCURACY, "eta < 1 for the new length scale");
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceSynchronize");
+    for (int w = 0; w < pl.P; ++w) {
+        pl.wins[w].ell = ell[w];
+        pl.wins[w].sigma = sigma[w];
+        pl.wins[w].eta = M_PI * pl.n * ell[w] / (std::sqrt(2.0) * pl.wins[w].T);
+    }
+    addk_status s = plan_compute_multipliers(pl, (hipStream_t)stream);
+    if (s != ADDK_OK)
+        return s;
+    for (int w = 0; w < pl.P; ++w) {
+        WinDev &d = pl.eng.wdev[w];
+        d.sig2 = sigma[w] * sigma[w];
+        d.der_scale = d.sig2 * (pl.kernel == ADDK_GAUSSIAN ? 2.0 / ell[w] : 1.0 / ell[w]);
+        d.dsig = 2.0 * sigma[w];
+    }
+    pl.eng.dirty = true;
+    return engine_upload(pl.eng);
+}
+
+addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_period, double *eta,
+                            int32_t *window_dim)
+{
+    if (!plan)
+        return fail(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    const Plan &pl = *(const Plan *)plan;
+    if (info) {
+        info->N = pl.N;
+        info->P = pl.P;
+        info->n = pl.n;
+        info->m = pl.m;
+        info->n_os = pl.nos;
+        info->precision = pl.precision;
+        info->kernel = pl.kernel;
+        info->workspace_bytes = pl.eng.ws_bytes + pl.eng.yw_bytes;
+        double est = 0.0;
+        for (const WinHost &w : pl.wins)
+            est = std::max(est, error_estimate(pl.kernel, w.L, w.T, w.ell, pl.n, pl.m, pl.sigma_os));
+        info->err_estimate = est;
+    }
+    for (int w = 0; w < pl.P; ++w) {
+        if (torus_period)
+            torus_period[w] = pl.wins[w].T;
+        if (eta)
+            eta[w] = pl.wins[w].eta;
+        if (window_dim)
+            window_dim[w] = pl.wins[w].d;
+    }
+    return ADDK_OK;
+}
+
+}  // extern "C"

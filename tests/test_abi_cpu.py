@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/addk.h, and its host-only helpers agree
+with the independent oracle / quadrature."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import fourier as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2404_17344_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libaddk.so not built")
+    return L
+
+
+def test_every_declared_function_is_exported():
+    L = _lib()
+    lib = L.load()
+    header = open(os.path.join(ROOT, "include", "addk.h")).read()
+    names = set(re.findall(r"\b(addk_[a-z_]+)\s*\(", header))
+    assert len(names) >= 15
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+    assert set(L._SIGS) == names
+
+
+def test_status_strings_and_version():
+    L = _lib()
+    lib = L.load()
+    for s in range(6):
+        assert len(lib.addk_status_string(s)) > 0
+    assert b"gfx950" in lib.addk_version()
+
+
+@pytest.mark.parametrize("kernel", [F.GAUSSIAN, F.MATERN12])
+@pytest.mark.parametrize("L,ell,n", [(0.5, 0.1, 64), (0.5, 0.05, 32), (0.3, 0.2, 16), (0.0, 0.1, 64)])
+def test_torus_period_matches_oracle_rule(kernel, L, ell, n):
+    import paper_2404_17344_amd as A
+    _lib()
+    assert A.torus_period(kernel, L, ell, n) == pytest.approx(F.torus_period_auto(kernel, L, ell, n), rel=1e-14)
+    if L > 0:
+        assert A.torus_period(kernel, L, ell, n, paper_rule=True, dmax=3) == pytest.approx(
+            F.torus_period_paper(L, 3), rel=1e-14)
+
+
+def _kb(z, m, b):
+    s = np.sqrt(np.maximum(m * m - z * z, 0.0))
+    return np.where(s > 1e-12, np.sinh(b * s) / np.where(s > 1e-12, s, 1.0), b) * m / np.sinh(b * m)
+
+
+@pytest.mark.parametrize("m,nos", [(4, 64), (6, 128), (6, 64)])
+def test_window_transform_matches_adaptive_quadrature(m, nos):
+    """Psi(k) = int psi(z) cos(2 pi z k / n_os) dz for the normalised Kaiser-Bessel window."""
+    import paper_2404_17344_amd as A
+    _lib()
+    b = math.pi * (2.0 - 0.5)
+    for k in [0, 1, 7, nos // 4, nos // 4 - 1]:
+        ref, _ = integrate.quad(lambda z: _kb(z, m, b) * math.cos(2 * math.pi * z * k / nos), -m, m, limit=400,
+                                epsabs=1e-14, epsrel=1e-14)
+        assert A.window_ft(m, nos, 2.0, k) == pytest.approx(ref, rel=1e-12)
+
+
+def test_window_transform_close_to_kaiser_bessel_closed_form():
+    """The untruncated window's transform is I0(m sqrt(b^2 - (2 pi k / n_os)^2)) up to
+    normalisation; truncation changes it only at the window-error level."""
+    import paper_2404_17344_amd as A
+    from scipy.special import i0
+    _lib()
+    m, nos = 6, 128
+    b = math.pi * 1.5
+    norm = math.pi * m / math.sinh(b * m)  # psi = (pi m / sinh(b m)) * sinh(b s) / (pi s)
+    for k in [0, 5, 20, 32]:
+        closed = norm * i0(m * math.sqrt(b * b - (2 * math.pi * k / nos) ** 2))
+        assert A.window_ft(m, nos, 2.0, k) == pytest.approx(closed, rel=1e-9)
+
+
+def test_helpers_reject_bad_arguments():
+    import paper_2404_17344_amd as A
+    _lib()
+    with pytest.raises(A.AddkError):
+        A.torus_period(F.GAUSSIAN, 0.5, -1.0, 64)
+    with pytest.raises(A.AddkError):
+        A.window_ft(0, 128, 2.0, 0.0)
+
+
+def test_header_documents_every_entry_point():
+    header = open(os.path.join(ROOT, "include", "addk.h")).read()
+    for name in ["addk_plan_create", "addk_matvec", "addk_dmatvec", "addk_vjp", "addk_batch_create"]:
+        i = header.index(name + "(")
+        assert "*/" in header[max(0, i - 1500):i], name  # a comment block precedes the declaration
