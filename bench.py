@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the additive-kernel matvec and its l-derivative products on one MI355X.
+
+Workload (the large configuration): N = 1e6 points, D = 15 i.i.d. N(0,1)
+features min-max scaled to [-1/4, 1/4], 5 consecutive d = 3 windows, Gaussian
+kernel l_w = 0.1, sigma_w = 1, R = 16 right-hand sides, n = 64, m = 6,
+oversampling 2; FP32 spreading/FFT/interpolation, FP64 multipliers and window
+sums.  Synthetic data (seeded); inputs resident in HBM before timing.
+
+One step = one ``addk_dmatvec`` call producing K V and (dK/dl_w) V for all five
+windows for the 16 right-hand sides.  ``value`` = right-hand-side vectors per
+second for which both products (K v and all dK/dl_w v) are delivered.
+
+Printed as one JSON line, with
+  roofline     : the dominant kernel's algorithmic FLOP rate (HIP events over
+                 the timed region) against the FP32 vector peak,
+  cpu_baseline : the FP64 CPU oracle timed on a bounded sample of output rows,
+  accuracy     : FP32 result vs the FP64 GPU path and vs the oracle rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "kernel matvecs/s and ∂K/∂ℓ matvecs/s at N=1e6, 5×d=3 windows, at rel err ≤1e-5"
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def relerr_cols(a: np.ndarray, b: np.ndarray) -> float:
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return float(max(np.linalg.norm(a[:, r] - b[:, r]) / np.linalg.norm(b[:, r]) for r in range(b.shape[1])))
+
+
+def log(msg: str):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=1000000, help="points (default: the full 1e6 workload)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested; run with --gpus 1)" % args.gpus, flush=True)
+        sys.exit(0)
+
+    import torch
+
+    import paper_2404_17344_amd as A
+    import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log("generating inputs")
+    p = WL.large_c5(N=args.N)
+    N, R, P, W = p.N, p.R, p.P, 2 * p.m
+    V = torch.from_numpy(p.V).to(dev)
+    torch.cuda.synchronize()
+
+    log("plan (fp32)")
+    t0 = time.perf_counter()
+    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision="fp32")
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+
+    def step():
+        return plan.dmatvec(V, want_y=True, want_dell=True, want_dsigma=False)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    plan.profile(True)
+    plan.profile_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        out = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    stages = plan.profile_read()
+    plan.profile(False)
+    value = R / (ms_per_step * 1e-3)
+
+    # Algorithmic FLOPs per launch: one FMA (2 flop) per tap, point-window pair and
+    # RHS; interpolation launches produce two outputs (kernel and derivative kernel).
+    # Dense-cell and tile kernels split the point-window pairs between them.
+    q = plan.query()
+    taps = W ** 3
+    pts = {"spread_dense": q["dense_points"], "spread": q["tile_points"],
+           "interp_dense": q["dense_points"], "interp": q["tile_points"]}
+    outs = {"spread_dense": 1, "spread": 1, "interp_dense": 2, "interp": 2}
+    flops = {k: 2.0 * taps * pts[k] * R * outs[k] for k in pts}
+    cand = [k for k in flops if stages[k][1] > 0]
+    dom = max(cand, key=lambda s: stages[s][0])
+    tot_ms, launches = stages[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops[dom],
+                "point_window_pairs": pts[dom]}
+    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
+
+    accuracy = {}
+    Y32 = out[0].cpu().numpy()
+    dl32 = out[1].cpu().numpy()
+    if not args.no_accuracy:
+        log("fp64 reference run")
+        del out
+        plan64 = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision="fp64")
+        Y64, dl64, _ = plan64.dmatvec(V, want_dsigma=False)
+        Y64 = Y64.cpu().numpy()
+        dl64 = dl64.cpu().numpy()
+        accuracy["rel_err_Y_vs_fp64_gpu"] = relerr_cols(Y32, Y64)
+        accuracy["rel_err_dY_dell_vs_fp64_gpu"] = max(relerr_cols(dl32[w], dl64[w]) for w in range(P))
+        plan64.close()
+        del plan64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.direct import oracle_direct, oracle_threads
+        rng = np.random.default_rng(17345)
+        log("cpu baseline (oracle)")
+        probe = rng.choice(N, 8, replace=False)
+        t0 = time.perf_counter()
+        oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe, want_derivs=True)
+        t_probe = time.perf_counter() - t0
+        nrows = int(min(max(8, 8 * args.cpu_seconds / max(t_probe, 1e-3)), 4096))
+        rows = rng.choice(N, nrows, replace=False)
+        t0 = time.perf_counter()
+        Yo, dlo, _ = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=rows, want_derivs=True)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(R * (nrows / N) / t_cpu, 6), "unit": "matvecs/s", "cores": oracle_threads(),
+               "kind": "oracle",
+               "sample": "%d of %d output rows, all 5 windows, 16 RHS, K v and dK/dl_w v, FP64 direct sums; "
+                         "%.1f s; rate scaled by N/rows" % (nrows, N, t_cpu)}
+        if not args.no_accuracy:
+            accuracy["rel_err_Y_vs_oracle_rows"] = relerr_cols(Y32[rows], Yo)
+            accuracy["rel_err_dY_dell_vs_oracle_rows"] = max(relerr_cols(dl32[w][rows], dlo[w]) for w in range(P))
+            accuracy["oracle_rows"] = nrows
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large additive Gaussian: N=%d, D=15 N(0,1) features min-max scaled, 5 windows d=3, "
+                               "l=0.1, sigma=1, R=16, n=64, m=6, oversampling 2" % N,
+                   "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "oversampling": p.oversampling,
+                   "step": "addk_dmatvec: K V and dK/dl_w V, all windows",
+                   "precision": "FP32 spread/FFT/interp, FP64 multipliers and window sums"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "stage_avg_ms": stage_ms,
+        "plan_ms": round(plan_ms, 2),
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,8 @@ typedef enum {
 #define ADDK_TORUS_AUTO 0u      /* per-window torus period balancing image/truncation errors  */
 #define ADDK_TORUS_PAPER 2u     /* prescaling rule: period 2 * Lmax * sqrt(d_max)              */
 #define ADDK_NO_ACCURACY_CHECK 4u /* do not refuse windows with eta < 1                       */
+#define ADDK_TILE_KERNELS_ONLY 8u /* route every point through the tile kernels (no dense-cell
+                                     kernels); same results up to rounding, for comparison     */
 
 typedef struct addk_plan_s *addk_plan;
 typedef struct addk_batch_s *addk_batch;
@@ -155,6 +157,8 @@ typedef struct {
     int32_t n, m, n_os, precision, kernel;
     int64_t workspace_bytes;    /* device bytes currently held by the plan           */
     double err_estimate;        /* a-priori relative error estimate (max over windows) */
+    int64_t dense_points;       /* point-window pairs handled by the dense-cell kernels */
+    int64_t tile_points;        /* point-window pairs handled by the tile kernels       */
 } addk_plan_info;
 addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_period,
                             double *eta, int32_t *window_dim);
@@ -180,6 +184,24 @@ addk_status addk_batch_launch(addk_batch batch, void *stream);
 /* The same products, launched eagerly (no graph); for comparison and debugging. */
 addk_status addk_batch_run_eager(addk_batch batch, void *stream);
 addk_status addk_batch_destroy(addk_batch batch);
+
+/*
+ * Stage timing for measurement.  When enabled, a pair of HIP events is recorded
+ * on the call's stream around every stage kernel launch of the plan's products
+ * (asynchronous; no synchronisation is added to the products themselves).
+ * addk_plan_profile_read synchronises the device, returns the summed kernel
+ * time in milliseconds and the number of launches per stage since the last
+ * read, and clears them.  Stage ids: see addk_stage_name (0 .. ADDK_NSTAGES-1).
+ * Errors: INVALID_ARG (NULL plan), HIP.
+ */
+#define ADDK_NSTAGES 12
+addk_status addk_plan_profile(addk_plan plan, int32_t enable);
+addk_status addk_plan_profile_read(addk_plan plan, double *total_ms, int32_t *launches);
+/* "zero", "spread", "fft_x_fwd", "fft_y_fwd", "fft_fused", "fft_y_inv",
+ * "fft_x_inv", "interp", "combine", "mode_dot", "spread_dense", "interp_dense";
+ * NULL for other ids.  Spreading and interpolation run in two kernels: tile
+ * kernels for sparsely populated cells and dense-cell kernels. */
+const char *addk_stage_name(int32_t stage);
 
 /* ---- host-only helpers (no GPU needed) ---------------------------------- */
 

@@ -69,7 +69,7 @@ class Plan:
 
     def __init__(self, X, windows: Sequence[Sequence[int]], ell, sigma, kernel="gaussian", n: int = 64,
                  m: int = 6, oversampling: float = 2.0, precision="fp64", coef: str = "analytic",
-                 torus: str = "auto", check_accuracy: bool = True, stream=None):
+                 torus: str = "auto", check_accuracy: bool = True, dense_kernels: bool = True, stream=None):
         lib = _lib.load()
         torch = _torch()
         if isinstance(X, torch.Tensor):
@@ -101,6 +101,8 @@ class Plan:
             flags |= ADDK_TORUS_PAPER
         if not check_accuracy:
             flags |= ADDK_NO_ACCURACY_CHECK
+        if not dense_kernels:
+            flags |= _lib.ADDK_TILE_KERNELS_ONLY
         h = ctypes.c_void_p()
         st = _stream(stream) if torch.cuda.is_available() else ctypes.c_void_p(0)
         _lib.check(lib.addk_plan_create(ctypes.byref(h), N, D, xptr, D, self.P, off_a, feat_a, _KERNELS[kernel],
@@ -138,7 +140,8 @@ class Plan:
         _lib.check(self._lib.addk_plan_query(self._h, ctypes.byref(info), T, eta, dims), "addk_plan_query")
         return {"N": info.N, "P": info.P, "n": info.n, "m": info.m, "n_os": info.n_os,
                 "precision": info.precision, "kernel": info.kernel, "workspace_bytes": info.workspace_bytes,
-                "err_estimate": info.err_estimate, "T": list(T), "eta": list(eta), "d": list(dims)}
+                "err_estimate": info.err_estimate, "T": list(T), "eta": list(eta), "d": list(dims),
+                "dense_points": info.dense_points, "tile_points": info.tile_points}
 
     def update_params(self, ell, sigma, stream=None):
         ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))
@@ -147,6 +150,17 @@ class Plan:
                                                      sig_a.ctypes.data_as(_lib._pd), _stream(stream)),
                    "addk_plan_update_params")
         self.ell, self.sigma = ell_a.copy(), sig_a.copy()
+
+    # -- stage timing (HIP events recorded around every stage launch)
+    def profile(self, enable: bool = True):
+        _lib.check(self._lib.addk_plan_profile(self._h, 1 if enable else 0), "addk_plan_profile")
+
+    def profile_read(self):
+        """{stage name: (total_ms, launches)} since the last read (synchronises)."""
+        ms = (ctypes.c_double * _lib.ADDK_NSTAGES)()
+        cnt = (ctypes.c_int32 * _lib.ADDK_NSTAGES)()
+        _lib.check(self._lib.addk_plan_profile_read(self._h, ms, cnt), "addk_plan_profile_read")
+        return {self._lib.addk_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(_lib.ADDK_NSTAGES)}
 
     # -- products
     def matvec(self, V, out=None, stream=None):

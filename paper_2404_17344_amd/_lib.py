@@ -28,12 +28,15 @@ ADDK_COEF_SAMPLED = 1
 ADDK_TORUS_AUTO = 0
 ADDK_TORUS_PAPER = 2
 ADDK_NO_ACCURACY_CHECK = 4
+ADDK_TILE_KERNELS_ONLY = 8
+ADDK_NSTAGES = 12
 
 
 class AddkPlanInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("P", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_os", ctypes.c_int32), ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64), ("err_estimate", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_int64), ("err_estimate", ctypes.c_double),
+                ("dense_points", ctypes.c_int64), ("tile_points", ctypes.c_int64)]
 
 
 _lib = None
@@ -61,6 +64,9 @@ _SIGS = {
     "addk_batch_launch": [_vp, _vp],
     "addk_batch_run_eager": [_vp, _vp],
     "addk_batch_destroy": [_vp],
+    "addk_plan_profile": [_vp, _i32],
+    "addk_plan_profile_read": [_vp, _pd, _pi32],
+    "addk_stage_name": [_i32],
     "addk_torus_period": [_i32, _d, _d, _i32, _u32, _i32, _pd],
     "addk_window_ft": [_i32, _i32, _d, _d, _pd],
     "addk_status_string": [_i32],
@@ -81,7 +87,8 @@ def load():
     for name, args in _SIGS.items():
         f = getattr(lib, name)
         f.argtypes = args
-        f.restype = ctypes.c_char_p if name in ("addk_status_string", "addk_last_error", "addk_version") else _i32
+        f.restype = ctypes.c_char_p if name in ("addk_status_string", "addk_last_error", "addk_version",
+                                               "addk_stage_name") else _i32
     _lib = lib
     return lib
 

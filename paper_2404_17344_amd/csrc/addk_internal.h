@@ -33,6 +33,9 @@ constexpr int kChunk = 1024;     // maximal points per spread/interp work item
 constexpr int kMaxW = 16;        // maximal taps per dimension (m <= 8)
 constexpr int kMaxNos = 128;     // maximal oversampled grid per dimension
 constexpr int kLdsBudget = 64 * 1024;
+constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
+constexpr int kDenseChunk = 256; // maximal points per dense work item
+constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).
 struct WinDev {
@@ -97,10 +100,20 @@ struct WinHost {
     int32_t *perm = nullptr;
     void *Bk = nullptr, *Bd = nullptr;
     double *Bk64 = nullptr, *Bd64 = nullptr;
-    std::vector<Chunk> chunks;  // win field is filled by the engine
+    std::vector<Chunk> chunks;  // sparse tile chunks; win field is filled by the engine
+    std::vector<Chunk> dense;   // dense cell runs; tile field holds the packed base cell
+    int64_t ndense_pts = 0;
 };
 
 struct Plan;
+
+enum ProfStage { PS_ZERO = 0, PS_SPREAD, PS_FFT_X_FWD, PS_FFT_Y_FWD, PS_FFT_FUSED, PS_FFT_Y_INV, PS_FFT_X_INV,
+                 PS_INTERP, PS_COMBINE, PS_MODE_DOT, PS_SPREAD_DENSE, PS_INTERP_DENSE, PS_COUNT };
+
+struct ProfRec {
+    int stage;
+    hipEvent_t a, b;
+};
 
 // An engine runs the stage kernels over a set of windows (one plan or a batch).
 struct Engine {
@@ -113,6 +126,10 @@ struct Engine {
     WinDev *d_wins = nullptr;
     Chunk *d_chunks[4] = {nullptr, nullptr, nullptr, nullptr};  // per d (1..3)
     int nchunks[4] = {0, 0, 0, 0};
+    Chunk *d_dense[4][2] = {};     // dense cell runs per d and window width (2m = 8, 12)
+    int ndense[4][2] = {};
+    int cur_dense = 0;
+    int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
     LineGroup *d_groups[ST_COUNT] = {};
     int ngroups[ST_COUNT] = {};
     int maxvol[4] = {0, 0, 0, 0};  // largest tile sub-grid volume per d
@@ -128,6 +145,19 @@ struct Engine {
     double *d_partial = nullptr;   // reduction scratch for the vjp
     int64_t partial_cap = 0;
     bool dirty = true;             // descriptors need an upload
+    bool prof = false;             // record stage events
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> evpool;
+};
+
+// Records a HIP event pair around one stage launch when profiling is on.
+struct StageTimer {
+    Engine &E;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageTimer(Engine &e, int s, hipStream_t t);
+    ~StageTimer();
 };
 
 struct Plan {
@@ -156,6 +186,13 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
 addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st);
 addk_status engine_upload(Engine &E);
 void engine_free(Engine &E);
+addk_status engine_profile_read(Engine &E, double *ms, int32_t *count);
+
+// dense.hip
+void launch_spread_dense(Engine &E, int D, int wi, int R, IoArgs io, hipStream_t st);
+void launch_interp_dense(Engine &E, int D, int wi, int R, int nout, hipStream_t st);
+bool dense_width_ok(int W);
+bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st);
 
 // plan.hip
 addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);

@@ -195,6 +195,31 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv, co
     return ADDK_OK;
 }
 
+addk_status addk_plan_profile(addk_plan plan, int32_t enable)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    ((Plan *)plan)->eng.prof = enable != 0;
+    return ADDK_OK;
+}
+
+addk_status addk_plan_profile_read(addk_plan plan, double *total_ms, int32_t *launches)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    return engine_profile_read(((Plan *)plan)->eng, total_ms, launches);
+}
+
+const char *addk_stage_name(int32_t stage)
+{
+    static const char *names[PS_COUNT] = {"zero",      "spread",    "fft_x_fwd", "fft_y_fwd",    "fft_fused",
+                                          "fft_y_inv", "fft_x_inv", "interp",    "combine",      "mode_dot",
+                                          "spread_dense", "interp_dense"};
+    if (stage < 0 || stage >= PS_COUNT)
+        return nullptr;
+    return names[stage];
+}
+
 addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *plans, int32_t R,
                               const double *const *V, const int64_t *ldv, double *const *Y, const int64_t *ldy,
                               void *stream)

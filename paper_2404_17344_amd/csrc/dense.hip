@@ -1,0 +1,562 @@
+// Spreading and interpolation for densely populated grid cells.
+//
+// Points are sorted by their base cell (the first of the (2m)^d grid cells a
+// point touches).  A cell that holds many points contributes, for each of its
+// points, to the same (2m)^d block of grid cells.  These kernels exploit that:
+//
+//  * spread: the threads of a block own grid cells of that block (one x-y
+//    column of taps each, all z taps held in registers, for a few RHS) and
+//    loop over the cell's points, whose window values and RHS entries are
+//    staged in LDS and read by every thread alike.  Accumulation is in
+//    registers; each thread adds its column to the global grid once.
+//  * interp: the block first copies the (2m)^d block of grid values for a set
+//    of RHS into LDS ([cell][rhs] layout), then every lane takes one point and
+//    all lanes walk the taps in the same order, so each LDS read is a
+//    broadcast of one address.
+//
+// Cells with few points use the tile kernels in kernels.hip instead.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "addk_internal.h"
+
+namespace addk {
+
+template <typename real>
+__device__ __forceinline__ real kb_psi_d(real z, real m, real b, real inv_e2bm)
+{
+    real s2 = m * m - z * z;
+    s2 = s2 > real(0) ? s2 : real(0);
+    real s = sqrt(s2);
+    s = s > real(1e-6) ? s : real(1e-6);
+    return m * (exp(b * (s - m)) - exp(-b * (s + m))) * inv_e2bm / s;
+}
+
+// FP32: hardware exp2 and reciprocal (a few ulp), ample for the FP32 path.
+template <>
+__device__ __forceinline__ float kb_psi_d<float>(float z, float m, float b, float inv_e2bm)
+{
+    float s2 = m * m - z * z;
+    s2 = s2 > 0.f ? s2 : 0.f;
+    float s = __builtin_sqrtf(s2);
+    s = s > 1e-6f ? s : 1e-6f;
+    const float l2e = 1.4426950408889634f;
+    return m * (__builtin_amdgcn_exp2f(b * (s - m) * l2e) - __builtin_amdgcn_exp2f(-b * (s + m) * l2e)) * inv_e2bm *
+           __builtin_amdgcn_rcpf(s);
+}
+
+__device__ __forceinline__ void unpack_cell(int packed, int &bx, int &by, int &bz)
+{
+    bx = packed & 1023;
+    by = (packed >> 10) & 1023;
+    bz = packed >> 20;
+}
+
+__device__ __forceinline__ ProbDev get_prob_d(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
+
+__device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// ---------------------------------------------------------------------------
+// spread, dense cells.  blockDim.x = OUT * NRG threads; thread (q, rg) owns
+// outer tap q and RHS rg*RT .. rg*RT+RT-1 of the block's RHS range.
+template <typename real, int D, int W, int RT>
+__global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
+                                                       IoArgs io, int R, int NRG)
+{
+    constexpr int OUT = D == 3 ? W * W : W;  // taps owned by thread groups
+    constexpr int IN = D == 1 ? 1 : W;       // taps accumulated per thread (last dimension)
+    constexpr int PB = 32;                   // points staged per round
+    __shared__ real pw[PB][D][W];
+    __shared__ real pv[PB][16];
+
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    const int RBB = RT * NRG;
+    const int r0 = blockIdx.y * RBB;
+    if (r0 >= R)
+        return;
+    const int t = threadIdx.x;
+    const int q = t % OUT, rg = t / OUT;
+    const int ox = D == 3 ? q % W : q;
+    const int oy = D == 3 ? q / W : 0;
+    int bx, by, bz;
+    unpack_cell(it.tile, bx, by, bz);
+    const int bb[3] = {bx, by, bz};
+    const real *coords = (const real *)w.coords;
+    const ProbDev pio = get_prob_d(io, w.prob);
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+
+    real acc[IN][RT];
+#pragma unroll
+    for (int k = 0; k < IN; ++k)
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+            acc[k][i] = real(0);
+
+    for (int p0 = 0; p0 < it.count; p0 += PB) {
+        const int np = min(PB, it.count - p0);
+        for (int e = t; e < np * D * W; e += blockDim.x) {
+            const int p = e / (D * W), rem = e - p * (D * W);
+            const int dd = rem / W, o = rem - dd * W;
+            const real u = coords[dd * w.N + it.start + p0 + p];
+            pw[p][dd][o] = kb_psi_d(u - (real)(bb[dd] + o), mm, kb, ie);
+        }
+        for (int e = t; e < np * RBB; e += blockDim.x) {
+            const int p = e / RBB, i = e - p * RBB;
+            const int r = r0 + i;
+            const int orig = w.perm[it.start + p0 + p];
+            pv[p][i] = r < R ? (real)pio.V[orig + (int64_t)r * pio.ldv] : real(0);
+        }
+        __syncthreads();
+        for (int p = 0; p < np; ++p) {
+            const real wo = D == 3 ? pw[p][0][ox] * pw[p][D > 1 ? 1 : 0][oy] : pw[p][0][ox];
+            real vv[RT];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                vv[i] = pv[p][rg * RT + i];
+            if (D == 1) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    acc[0][i] += wo * vv[i];
+            } else {
+#pragma unroll
+                for (int k = 0; k < IN; ++k) {
+                    const real wt = wo * pw[p][D - 1][k];
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+                        acc[k][i] += wt * vv[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    real *G = (real *)w.G;
+    const int ex = w.ext[0], ey = w.ext[1];
+#pragma unroll
+    for (int k = 0; k < IN; ++k) {
+        int x, y, z;
+        if (D == 3) {
+            x = bx + ox;
+            y = by + oy;
+            z = bz + k;
+        } else if (D == 2) {
+            x = bx + ox;
+            y = by + k;
+            z = 0;
+        } else {
+            x = bx + ox;
+            y = 0;
+            z = 0;
+        }
+        const int64_t cell = ((int64_t)z * ey + y) * ex + x;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const int r = r0 + rg * RT + i;
+            if (r < R)
+                gadd(&G[((int64_t)(r >> 1) * w.szG + cell) * 2 + (r & 1)], acc[k][i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interp, dense cells.  One lane per point; the (2m)^d block of grid values of
+// the cell is staged in LDS as [cell][RB].
+template <typename real, int D, int W, int RB>
+__global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
+                                                         int R)
+{
+    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    real *sub = (real *)smem_raw;
+
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    const int r0 = blockIdx.y * RB;
+    if (r0 >= R)
+        return;
+    const int o = blockIdx.z;
+    const int nr = min(RB, R - r0);
+    int bx, by, bz;
+    unpack_cell(it.tile, bx, by, bz);
+
+    const real *H = (const real *)w.H;
+    const int ex = w.ext[0], ey = w.ext[1];
+    const int np = (nr + 1) >> 1;
+    const int p0 = r0 >> 1;
+    for (int idx = threadIdx.x; idx < np * NC; idx += kBlock) {
+        const int pi = idx / NC, c = idx - pi * NC;
+        const int cx = c % W, cy = D > 1 ? (c / W) % W : 0, cz = D > 2 ? c / (W * W) : 0;
+        const int64_t off =
+            ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)(bz + cz) * ey + by + cy) * ex + bx + cx) * 2;
+        sub[c * RB + 2 * pi] = H[off];
+        if (2 * pi + 1 < RB)
+            sub[c * RB + 2 * pi + 1] = H[off + 1];
+    }
+    __syncthreads();
+
+    const int p = threadIdx.x;
+    if (p >= it.count)
+        return;
+    const int j = it.start + p;
+    const real *coords = (const real *)w.coords;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    const real ux = coords[j];
+    real wy[W], wz[W];
+    if (D > 1) {
+        const real uy = coords[w.N + j];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            wy[k] = kb_psi_d(uy - (real)(by + k), mm, kb, ie);
+    }
+    if (D > 2) {
+        const real uz = coords[2 * w.N + j];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            wz[k] = kb_psi_d(uz - (real)(bz + k), mm, kb, ie);
+    }
+    real acc[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        acc[i] = real(0);
+    for (int ox = 0; ox < W; ++ox) {
+        const real wxo = kb_psi_d(ux - (real)(bx + ox), mm, kb, ie);
+        if (D == 1) {
+            const real *s = sub + ox * RB;
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                acc[i] += wxo * s[i];
+        } else if (D == 2) {
+#pragma unroll
+            for (int oy = 0; oy < W; ++oy) {
+                const real wt = wxo * wy[oy];
+                const real *s = sub + (ox + W * oy) * RB;
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    acc[i] += wt * s[i];
+            }
+        } else {
+            // the next tap's grid values are loaded before the current tap's FMAs
+            real cur[RB], nxt[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                cur[i] = sub[ox * RB + i];
+#pragma unroll
+            for (int oy = 0; oy < W; ++oy) {
+                const real wxy = wxo * wy[oy];
+#pragma unroll
+                for (int oz = 0; oz < W; ++oz) {
+                    const int tn = oy * W + oz + 1;  // next tap in (oy, oz) order
+                    if (tn < W * W) {
+                        const real *s = sub + (ox + W * ((tn / W) + W * (tn % W))) * RB;
+#pragma unroll
+                        for (int i = 0; i < RB; ++i)
+                            nxt[i] = s[i];
+                    }
+                    const real wt = wxy * wz[oz];
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i] += wt * cur[i];
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        cur[i] = nxt[i];
+                }
+            }
+        }
+    }
+    const int orig = w.perm[j];
+    double *dst = w.Yw + ((int64_t)o * w.Rcap + r0) * w.N + orig;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        if (i < nr)
+            dst[(int64_t)i * w.N] = (double)acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+bool dense_width_ok(int W) { return W == 8 || W == 12; }
+
+template <typename real, int D, int W>
+static void spread_dense_w(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    const int OUT = D == 3 ? W * W : W;
+    if (R == 1) {
+        dim3 grid(E.ndense[D][E.cur_dense], R);
+        hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, E.d_dense[D][E.cur_dense], io,
+                           R, 1);
+        return;
+    }
+    const int nrg = std::min(4, (R + 3) / 4);
+    dim3 grid(E.ndense[D][E.cur_dense], (R + 4 * nrg - 1) / (4 * nrg));
+    hipLaunchKernelGGL((k_spread_dense<real, D, W, 4>), grid, dim3(OUT * nrg), 0, st, E.d_wins, E.d_dense[D][E.cur_dense],
+                       io, R, nrg);
+}
+
+template <typename real, int D, int W, int RB>
+static void interp_dense_rb(Engine &E, int R, int nout, hipStream_t st)
+{
+    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    dim3 grid(E.ndense[D][E.cur_dense], (R + RB - 1) / RB, nout);
+    hipLaunchKernelGGL((k_interp_dense<real, D, W, RB>), grid, dim3(kBlock), (size_t)NC * RB * sizeof(real), st,
+                       E.d_wins, E.d_dense[D][E.cur_dense], R);
+}
+
+template <typename real, int D, int W>
+static void interp_dense_w(Engine &E, int R, int nout, hipStream_t st)
+{
+    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    int rbmax = 16;
+    while (rbmax > 1 && (size_t)NC * rbmax * sizeof(real) > (size_t)kLdsBudget)
+        rbmax >>= 1;
+    int rb = 1;
+    while (rb < R && rb < rbmax)
+        rb <<= 1;
+    switch (rb) {
+    case 1: interp_dense_rb<real, D, W, 1>(E, R, nout, st); break;
+    case 2: interp_dense_rb<real, D, W, 2>(E, R, nout, st); break;
+    case 4: interp_dense_rb<real, D, W, 4>(E, R, nout, st); break;
+    case 8: interp_dense_rb<real, D, W, 8>(E, R, nout, st); break;
+    default: interp_dense_rb<real, D, W, 16>(E, R, nout, st); break;
+    }
+}
+
+template <typename real, int D>
+static void spread_dense_d(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
+{
+    if (wi == 0)
+        spread_dense_w<real, D, 8>(E, R, io, st);
+    else
+        spread_dense_w<real, D, 12>(E, R, io, st);
+}
+
+template <typename real, int D>
+static void interp_dense_d(Engine &E, int wi, int R, int nout, hipStream_t st)
+{
+    if (wi == 0)
+        interp_dense_w<real, D, 8>(E, R, nout, st);
+    else
+        interp_dense_w<real, D, 12>(E, R, nout, st);
+}
+
+// wi selects the window width: 0 -> 2m = 8, 1 -> 2m = 12
+void launch_spread_dense(Engine &E, int D, int wi, int R, IoArgs io, hipStream_t st)
+{
+    E.cur_dense = wi;
+    if (E.precision == ADDK_FP32) {
+        if (D == 1) spread_dense_d<float, 1>(E, wi, R, io, st);
+        if (D == 2) spread_dense_d<float, 2>(E, wi, R, io, st);
+        if (D == 3) spread_dense_d<float, 3>(E, wi, R, io, st);
+    } else {
+        if (D == 1) spread_dense_d<double, 1>(E, wi, R, io, st);
+        if (D == 2) spread_dense_d<double, 2>(E, wi, R, io, st);
+        if (D == 3) spread_dense_d<double, 3>(E, wi, R, io, st);
+    }
+}
+
+void launch_interp_dense(Engine &E, int D, int wi, int R, int nout, hipStream_t st)
+{
+    E.cur_dense = wi;
+    if (E.precision == ADDK_FP32) {
+        if (D == 1) interp_dense_d<float, 1>(E, wi, R, nout, st);
+        if (D == 2) interp_dense_d<float, 2>(E, wi, R, nout, st);
+        if (D == 3) interp_dense_d<float, 3>(E, wi, R, nout, st);
+    } else {
+        if (D == 1) interp_dense_d<double, 1>(E, wi, R, nout, st);
+        if (D == 2) interp_dense_d<double, 2>(E, wi, R, nout, st);
+        if (D == 3) interp_dense_d<double, 3>(E, wi, R, nout, st);
+    }
+}
+
+}  // namespace addk
+
+namespace addk {
+
+// ---------------------------------------------------------------------------
+// spread, sparsely populated cells of one tile, without atomics in LDS.
+// The block owns the tile's sub-grid (tile + window halo).  For d = 3 each
+// thread owns one x-y column of it with every z cell in registers; for d <= 2
+// each thread owns up to CPT cells.  Points of the chunk are staged in LDS
+// (window values, base cell, RHS values) and visited by every thread; a
+// thread adds w * v to the cells of its column that lie in the point's
+// support.  The sub-grid is then added to the global grid.
+template <typename real, int D, int W, int RT>
+__global__ __launch_bounds__(kBlock) void k_spread_tile(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
+                                                        IoArgs io, int R)
+{
+    constexpr int TB = D == 3 ? 4 : (D == 2 ? 16 : 256);  // maximal tile edge in base cells
+    constexpr int SZ = TB + W - 1;                         // maximal sub-grid edge
+    constexpr int NZ = D == 3 ? SZ : 1;                    // z cells per thread (column)
+    constexpr int CPT = D == 3 ? 1 : (D == 2 ? (SZ * SZ + kBlock - 1) / kBlock : (SZ + kBlock - 1) / kBlock);
+    constexpr int PB = 64;
+    __shared__ real pw[PB][D][W];
+    __shared__ int pb[PB][3];
+    __shared__ real pv[PB][RT];
+
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int r0 = blockIdx.y * RT;
+    if (r0 >= R)
+        return;
+    const int S0 = w.S[0], S1 = D > 1 ? w.S[1] : 1, S2 = D > 2 ? w.S[2] : 1;
+    int tl = ch.tile;
+    const int tx = tl % w.ntile[0];
+    tl /= w.ntile[0];
+    const int ty = tl % w.ntile[1];
+    const int tz = tl / w.ntile[1];
+    const int o0[3] = {tx * w.tb[0], ty * w.tb[1], tz * w.tb[2]};
+    const real *coords = (const real *)w.coords;
+    const ProbDev pio = get_prob_d(io, w.prob);
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    const int t = threadIdx.x;
+
+    // cells owned by this thread (sub-grid coordinates)
+    int cx[CPT], cy[CPT];
+    bool own[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int lin = t + c * kBlock;
+        if (D == 3) {
+            cx[c] = lin % S0;
+            cy[c] = lin / S0;
+            own[c] = cy[c] < S1;
+        } else if (D == 2) {
+            cx[c] = lin % S0;
+            cy[c] = lin / S0;
+            own[c] = cy[c] < S1;
+        } else {
+            cx[c] = lin;
+            cy[c] = 0;
+            own[c] = lin < S0;
+        }
+    }
+    real acc[CPT][NZ][RT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int z = 0; z < NZ; ++z)
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                acc[c][z][i] = real(0);
+
+    for (int p0 = 0; p0 < ch.count; p0 += PB) {
+        const int np = min(PB, ch.count - p0);
+        for (int e = t; e < np * D; e += kBlock) {
+            const int p = e / D, dd = e - p * D;
+            const real u = coords[dd * w.N + ch.start + p0 + p];
+            pb[p][dd] = (int)floor(u) - w.m + 1 - o0[dd];
+        }
+        for (int e = t; e < np * RT; e += kBlock) {
+            const int p = e / RT, i = e - p * RT;
+            const int r = r0 + i;
+            const int orig = w.perm[ch.start + p0 + p];
+            pv[p][i] = r < R ? (real)pio.V[orig + (int64_t)r * pio.ldv] : real(0);
+        }
+        __syncthreads();
+        for (int e = t; e < np * D * W; e += kBlock) {
+            const int p = e / (D * W), rem = e - p * (D * W);
+            const int dd = rem / W, o = rem - dd * W;
+            const real u = coords[dd * w.N + ch.start + p0 + p];
+            pw[p][dd][o] = kb_psi_d(u - (real)(pb[p][dd] + o0[dd] + o), mm, kb, ie);
+        }
+        __syncthreads();
+        for (int p = 0; p < np; ++p) {
+            real vv[RT];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                vv[i] = pv[p][i];
+            const int bx = pb[p][0], by = D > 1 ? pb[p][D > 1 ? 1 : 0] : 0, bz = D > 2 ? pb[p][D > 2 ? 2 : 0] : 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int ox = cx[c] - bx, oy = cy[c] - by;
+                const bool inx = (unsigned)ox < (unsigned)W;
+                const bool iny = D == 1 || (unsigned)oy < (unsigned)W;
+                real wxy = inx ? pw[p][0][inx ? ox : 0] : real(0);
+                if (D > 1)
+                    wxy *= iny ? pw[p][D > 1 ? 1 : 0][iny ? oy : 0] : real(0);
+                if (!own[c])
+                    wxy = real(0);
+                if (D == 3) {
+#pragma unroll
+                    for (int z = 0; z < NZ; ++z) {
+                        const int oz = z - bz;
+                        const bool inz = (unsigned)oz < (unsigned)W;
+                        const real wt = inz ? wxy * pw[p][D > 2 ? 2 : 0][inz ? oz : 0] : real(0);
+#pragma unroll
+                        for (int i = 0; i < RT; ++i)
+                            acc[c][z][i] += wt * vv[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+                        acc[c][0][i] += wxy * vv[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    real *G = (real *)w.G;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        if (!own[c])
+            continue;
+        const int gx = o0[0] + cx[c], gy = D > 1 ? o0[1] + cy[c] : 0;
+        if (gx >= ex || gy >= ey)
+            continue;
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) {
+            const int gz = D > 2 ? o0[2] + z : 0;
+            if (D > 2 && (z >= S2 || gz >= ez))
+                continue;
+            const int64_t cell = ((int64_t)gz * ey + gy) * ex + gx;
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int r = r0 + i;
+                if (r < R && acc[c][z][i] != real(0))
+                    gadd(&G[((int64_t)(r >> 1) * w.szG + cell) * 2 + (r & 1)], acc[c][z][i]);
+            }
+        }
+    }
+}
+
+template <typename real, int D, int W, int RT>
+static void spread_tile_rt(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    dim3 grid(E.nchunks[D], (R + RT - 1) / RT);
+    hipLaunchKernelGGL((k_spread_tile<real, D, W, RT>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_chunks[D], io, R);
+}
+
+template <typename real, int D, int W>
+static void spread_tile_w(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    if (R == 1)
+        spread_tile_rt<real, D, W, 1>(E, R, io, st);
+    else if (R == 2)
+        spread_tile_rt<real, D, W, 2>(E, R, io, st);
+    else
+        spread_tile_rt<real, D, W, 4>(E, R, io, st);
+}
+
+// Returns false when the tile kernel has no instantiation for the engine's window width.
+bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st)
+{
+    const int W = E.tile_w[D];
+    if (W != 8 && W != 12)
+        return false;
+    if (E.precision == ADDK_FP32) {
+        if (D == 1) { if (W == 8) spread_tile_w<float, 1, 8>(E, R, io, st); else spread_tile_w<float, 1, 12>(E, R, io, st); }
+        if (D == 2) { if (W == 8) spread_tile_w<float, 2, 8>(E, R, io, st); else spread_tile_w<float, 2, 12>(E, R, io, st); }
+        if (D == 3) { if (W == 8) spread_tile_w<float, 3, 8>(E, R, io, st); else spread_tile_w<float, 3, 12>(E, R, io, st); }
+    } else {
+        if (D == 1) { if (W == 8) spread_tile_w<double, 1, 8>(E, R, io, st); else spread_tile_w<double, 1, 12>(E, R, io, st); }
+        if (D == 2) { if (W == 8) spread_tile_w<double, 2, 8>(E, R, io, st); else spread_tile_w<double, 2, 12>(E, R, io, st); }
+        if (D == 3) { if (W == 8) spread_tile_w<double, 3, 8>(E, R, io, st); else spread_tile_w<double, 3, 12>(E, R, io, st); }
+    }
+    return true;
+}
+
+}  // namespace addk

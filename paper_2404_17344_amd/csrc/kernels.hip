@@ -713,17 +713,87 @@ static void free_dev(void *p)
         (void)hipFree(p);
 }
 
+static hipEvent_t take_event(Engine &E)
+{
+    if (!E.evpool.empty()) {
+        hipEvent_t e = E.evpool.back();
+        E.evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+StageTimer::StageTimer(Engine &e, int s, hipStream_t t) : E(e), stage(s), st(t)
+{
+    if (E.prof) {
+        a = take_event(E);
+        if (a)
+            (void)hipEventRecord(a, st);
+    }
+}
+
+StageTimer::~StageTimer()
+{
+    if (E.prof && a) {
+        hipEvent_t b = take_event(E);
+        if (b) {
+            (void)hipEventRecord(b, st);
+            E.recs.push_back({stage, a, b});
+        } else {
+            E.evpool.push_back(a);
+        }
+    }
+}
+
+addk_status engine_profile_read(Engine &E, double *ms, int32_t *count)
+{
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceSynchronize");
+    for (int s = 0; s < PS_COUNT; ++s) {
+        if (ms)
+            ms[s] = 0.0;
+        if (count)
+            count[s] = 0;
+    }
+    for (const ProfRec &r : E.recs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            if (ms)
+                ms[r.stage] += t;
+            if (count)
+                count[r.stage] += 1;
+        }
+        E.evpool.push_back(r.a);
+        E.evpool.push_back(r.b);
+    }
+    E.recs.clear();
+    return ADDK_OK;
+}
+
 void engine_free(Engine &E)
 {
     free_dev(E.d_wins);
-    for (int d = 0; d < 4; ++d)
+    for (int d = 0; d < 4; ++d) {
         free_dev(E.d_chunks[d]);
+        free_dev(E.d_dense[d][0]);
+        free_dev(E.d_dense[d][1]);
+    }
     for (int s = 0; s < ST_COUNT; ++s)
         free_dev(E.d_groups[s]);
     free_dev(E.ws);
     free_dev(E.yw);
     free_dev(E.d_probs);
     free_dev(E.d_partial);
+    for (const ProfRec &r : E.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t ev : E.evpool)
+        (void)hipEventDestroy(ev);
     E = Engine();
 }
 
@@ -734,10 +804,12 @@ addk_status engine_build_device(Engine &E, int precision)
     E.precision = precision;
     const int L = lines_per_group(precision);
     std::vector<Chunk> ch[4];
+    std::vector<Chunk> dn[4][2];
     std::vector<LineGroup> gr[ST_COUNT];
     for (int d = 0; d < 4; ++d) {
         E.maxvol[d] = 0;
         E.rb[d] = 0;
+        E.tile_w[d] = 0;
     }
     for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
         const WinDev &w = E.wdev[wi];
@@ -747,7 +819,18 @@ addk_status engine_build_device(Engine &E, int precision)
             cc.win = (int)wi;
             ch[w.d].push_back(cc);
         }
+        for (const Chunk &c : h.dense) {
+            Chunk cc = c;
+            cc.win = (int)wi;
+            dn[w.d][w.W == 8 ? 0 : 1].push_back(cc);
+        }
         E.maxvol[w.d] = std::max(E.maxvol[w.d], w.S[0] * w.S[1] * w.S[2]);
+        if (!h.chunks.empty()) {
+            if (E.tile_w[w.d] == 0)
+                E.tile_w[w.d] = w.W;
+            else if (E.tile_w[w.d] != w.W)
+                E.tile_w[w.d] = -1;
+        }
         for (int s = 0; s < ST_COUNT; ++s) {
             const int ng = ngroups_stage(w, s, L);
             for (int g = 0; g < ng; ++g)
@@ -769,6 +852,21 @@ addk_status engine_build_device(Engine &E, int precision)
                 return hip_fail(e, "hipMemcpy(chunks)");
         }
     }
+    for (int d = 1; d <= 3; ++d)
+        for (int wi = 0; wi < 2; ++wi) {
+            E.ndense[d][wi] = (int)dn[d][wi].size();
+            free_dev(E.d_dense[d][wi]);
+            E.d_dense[d][wi] = nullptr;
+            if (!dn[d][wi].empty()) {
+                hipError_t e = hipMalloc(&E.d_dense[d][wi], dn[d][wi].size() * sizeof(Chunk));
+                if (e != hipSuccess)
+                    return hip_fail(e, "hipMalloc(dense items)");
+                e = hipMemcpy(E.d_dense[d][wi], dn[d][wi].data(), dn[d][wi].size() * sizeof(Chunk),
+                              hipMemcpyHostToDevice);
+                if (e != hipSuccess)
+                    return hip_fail(e, "hipMemcpy(dense items)");
+            }
+        }
     for (int s = 0; s < ST_COUNT; ++s) {
         E.ngroups[s] = (int)gr[s].size();
         free_dev(E.d_groups[s]);
@@ -943,23 +1041,73 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
     const int nw = (int)E.wdev.size();
     if (nw == 0)
         return ADDK_OK;
-    hipLaunchKernelGGL(k_zero_grids<real>, dim3(64, nw), dim3(kBlock), 0, st, E.d_wins, npair);
-    if (E.nchunks[1]) launch_spread<real, 1>(E, R, io, st);
-    if (E.nchunks[2]) launch_spread<real, 2>(E, R, io, st);
-    if (E.nchunks[3]) launch_spread<real, 3>(E, R, io, st);
+    {
+        StageTimer t(E, PS_ZERO, st);
+        hipLaunchKernelGGL(k_zero_grids<real>, dim3(64, nw), dim3(kBlock), 0, st, E.d_wins, npair);
+    }
+    for (int d = 1; d <= 3; ++d) {
+        if (!E.nchunks[d])
+            continue;
+        StageTimer t(E, PS_SPREAD, st);
+        if (launch_spread_tile(E, d, R, io, st))
+            continue;
+        if (d == 1) launch_spread<real, 1>(E, R, io, st);
+        if (d == 2) launch_spread<real, 2>(E, R, io, st);
+        if (d == 3) launch_spread<real, 3>(E, R, io, st);
+    }
+    for (int d = 1; d <= 3; ++d)
+        for (int wi = 0; wi < 2; ++wi) {
+            if (!E.ndense[d][wi])
+                continue;
+            StageTimer t(E, PS_SPREAD_DENSE, st);
+            launch_spread_dense(E, d, wi, R, io, st);
+        }
     FftCall fc{npair, nout, modes_sel};
-    launch_fft<real, 0, 0>(E, ST_FWD0, npair, fc, st);
-    launch_fft<real, 1, 0>(E, ST_FWD1, npair, fc, st);
-    launch_fft<real, 2, 2>(E, ST_FUSED2, npair, fc, st);
-    launch_fft<real, 1, 2>(E, ST_FUSED1, npair, fc, st);
-    launch_fft<real, 0, 2>(E, ST_FUSED0, npair, fc, st);
+    if (E.ngroups[ST_FWD0]) {
+        StageTimer t(E, PS_FFT_X_FWD, st);
+        launch_fft<real, 0, 0>(E, ST_FWD0, npair, fc, st);
+    }
+    if (E.ngroups[ST_FWD1]) {
+        StageTimer t(E, PS_FFT_Y_FWD, st);
+        launch_fft<real, 1, 0>(E, ST_FWD1, npair, fc, st);
+    }
+    if (E.ngroups[ST_FUSED2]) {
+        StageTimer t(E, PS_FFT_FUSED, st);
+        launch_fft<real, 2, 2>(E, ST_FUSED2, npair, fc, st);
+    }
+    if (E.ngroups[ST_FUSED1]) {
+        StageTimer t(E, PS_FFT_FUSED, st);
+        launch_fft<real, 1, 2>(E, ST_FUSED1, npair, fc, st);
+    }
+    if (E.ngroups[ST_FUSED0]) {
+        StageTimer t(E, PS_FFT_FUSED, st);
+        launch_fft<real, 0, 2>(E, ST_FUSED0, npair, fc, st);
+    }
     if (nout > 0) {
-        launch_fft<real, 1, 1>(E, ST_INV1, npair * nout, fc, st);
-        launch_fft<real, 0, 1>(E, ST_INV0, npair * nout, fc, st);
+        if (E.ngroups[ST_INV1]) {
+            StageTimer t(E, PS_FFT_Y_INV, st);
+            launch_fft<real, 1, 1>(E, ST_INV1, npair * nout, fc, st);
+        }
+        if (E.ngroups[ST_INV0]) {
+            StageTimer t(E, PS_FFT_X_INV, st);
+            launch_fft<real, 0, 1>(E, ST_INV0, npair * nout, fc, st);
+        }
         if (interp) {
-            if (E.nchunks[1]) launch_interp<real, 1>(E, R, nout, st);
-            if (E.nchunks[2]) launch_interp<real, 2>(E, R, nout, st);
-            if (E.nchunks[3]) launch_interp<real, 3>(E, R, nout, st);
+            for (int d = 1; d <= 3; ++d) {
+                if (!E.nchunks[d])
+                    continue;
+                StageTimer t(E, PS_INTERP, st);
+                if (d == 1) launch_interp<real, 1>(E, R, nout, st);
+                if (d == 2) launch_interp<real, 2>(E, R, nout, st);
+                if (d == 3) launch_interp<real, 3>(E, R, nout, st);
+            }
+            for (int d = 1; d <= 3; ++d)
+                for (int wi = 0; wi < 2; ++wi) {
+                    if (!E.ndense[d][wi])
+                        continue;
+                    StageTimer t(E, PS_INTERP_DENSE, st);
+                    launch_interp_dense(E, d, wi, R, nout, st);
+                }
         }
     }
     hipError_t e = hipGetLastError();
@@ -994,6 +1142,7 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
         return ADDK_OK;
     const int bx = (int)std::min<int64_t>((work + kBlock - 1) / kBlock, 4096);
     const int ny = io.table ? E.nprob : 1;
+    StageTimer t(E, PS_COMBINE, st);
     hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -1014,6 +1163,7 @@ addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad
             return hip_fail(e, "hipMalloc(partials)");
         E.partial_cap = need;
     }
+    StageTimer t(E, PS_MODE_DOT, st);
     for (int wi = 0; wi < (int)E.wdev.size(); ++wi) {
         double *part = E.d_partial + (int64_t)2 * nblk * wi;
         if (E.precision == ADDK_FP32)

@@ -20,7 +20,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -45,6 +48,21 @@ static addk_status fail(addk_status s, const std::string &msg)
 {
     set_error(msg);
     return s;
+}
+
+// ADDK_LOG=1 prints plan facts and set-up timings to stderr.
+static bool log_on()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("ADDK_LOG");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+
+static double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 // ---------------------------------------------------------------------------
@@ -172,7 +190,7 @@ __global__ void k_minmax(const double *__restrict__ X, int64_t ldx, int64_t N, i
 }
 
 struct KeyArgs {
-    int d, nos, m, W;
+    int d, nos, m, W, cpt;
     int f[3];
     double c[3];
     double invT;
@@ -191,7 +209,7 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
                        int32_t *key, int32_t *hist, int32_t *bad)
 {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
-        int t[3] = {0, 0, 0};
+        int t[3] = {0, 0, 0}, b3[3] = {0, 0, 0};
         bool ok = true;
         for (int dd = 0; dd < a.d; ++dd) {
             const double x = X[j * ldx + a.f[dd]];
@@ -199,6 +217,7 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
             const real ur = (real)u;
             ucoord[dd * N + j] = ur;
             const int b = base_cell_p(ur, a.m);
+            b3[dd] = b;
             if (b < 0 || b + a.W > a.ext[dd])
                 ok = false;
             t[dd] = b / a.tb[dd];
@@ -210,7 +229,10 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
             key[j] = 0;
             continue;
         }
-        const int k = t[0] + a.ntile[0] * (t[1] + a.ntile[1] * t[2]);
+        // cell key: tile-major, then the base cell inside the tile
+        const int tl = t[0] + a.ntile[0] * (t[1] + a.ntile[1] * t[2]);
+        const int c = (b3[0] - t[0] * a.tb[0]) + a.tb[0] * ((b3[1] - t[1] * a.tb[1]) + a.tb[1] * (b3[2] - t[2] * a.tb[2]));
+        const int k = tl * a.cpt + c;
         key[j] = k;
         atomicAdd(&hist[k], 1);
     }
@@ -601,12 +623,13 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         (e = hipMalloc(&w.perm, std::max<int64_t>(1, N) * sizeof(int32_t))) != hipSuccess)
         return fail(ADDK_ERR_OOM, "point arrays allocation failed");
     w.chunks.clear();
+    w.dense.clear();
     if (N == 0)
         return ADDK_OK;
     void *ucoord = nullptr;
     int32_t *key = nullptr, *hist = nullptr, *bad = nullptr;
     if ((e = hipMalloc(&ucoord, N * w.d * rs)) != hipSuccess || (e = hipMalloc(&key, N * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&hist, (w.ntiles + 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&hist, (w.ntiles * w.tb[0] * w.tb[1] * w.tb[2] + 1) * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&bad, sizeof(int32_t))) != hipSuccess)
         return fail(ADDK_ERR_OOM, "sort buffers allocation failed");
     KeyArgs ka;
@@ -616,6 +639,7 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     ka.m = m;
     ka.W = W;
     ka.invT = 1.0 / w.T;
+    ka.cpt = w.tb[0] * w.tb[1] * w.tb[2];
     for (int dd = 0; dd < 3; ++dd) {
         ka.f[dd] = dd < w.d ? w.feat[dd] : 0;
         ka.c[dd] = dd < w.d ? w.center[dd] : 0.0;
@@ -624,22 +648,25 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         ka.tb[dd] = w.tb[dd];
         ka.ntile[dd] = w.ntile[dd];
     }
-    // zero with small kernels (no memset nodes: the same code may be captured)
-    std::vector<int32_t> zeros(w.ntiles + 1, 0);
-    e = hipMemcpy(hist, zeros.data(), (w.ntiles + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    const int64_t cpt = (int64_t)w.tb[0] * w.tb[1] * w.tb[2];
+    const int64_t nkeys = w.ntiles * cpt;
+    {
+        std::vector<int32_t> zeros(1, 0);
         e = hipMemcpy(bad, zeros.data(), sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipMemcpy");
+        if (e == hipSuccess)
+            e = hipMemsetAsync(hist, 0, nkeys * sizeof(int32_t), st);  // plan set-up is never captured
+        if (e != hipSuccess)
+            return hip_fail(e, "clear histogram");
+    }
     const int nb = (int)std::min<int64_t>((N + 255) / 256, 4096);
     if (pl.precision == ADDK_FP32)
         hipLaunchKernelGGL(k_keys<float>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (float *)ucoord, key, hist, bad);
     else
         hipLaunchKernelGGL(k_keys<double>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (double *)ucoord, key, hist,
                            bad);
-    std::vector<int32_t> h(w.ntiles + 1);
+    std::vector<int32_t> h(nkeys);
     int32_t hbad = 0;
-    e = hipMemcpyAsync(h.data(), hist, w.ntiles * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(h.data(), hist, nkeys * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
@@ -648,13 +675,41 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         return hip_fail(e, "tile histogram");
     if (hbad)
         return fail(ADDK_ERR_INVALID_ARG, "internal: a point fell outside its grid box");
-    std::vector<int32_t> off(w.ntiles + 1, 0);
+    // Order inside a tile: points of sparsely populated cells first (one
+    // contiguous range, processed by the tile kernels), then each densely
+    // populated cell (processed by the dense-cell kernels).
+    const bool dense_ok = dense_width_ok(W) && !(pl.flags & kFlagNoDense);
+    std::vector<int32_t> off(nkeys, 0);
+    int64_t pos = 0;
+    w.ndense_pts = 0;
     for (int64_t t = 0; t < w.ntiles; ++t) {
-        off[t + 1] = off[t] + h[t];
-        for (int s = 0; s < h[t]; s += kChunk)
-            w.chunks.push_back({0, (int32_t)t, off[t] + s, std::min(kChunk, h[t] - s)});
+        const int64_t k0 = t * cpt;
+        const int64_t s0 = pos;
+        for (int64_t c = 0; c < cpt; ++c)
+            if (!(dense_ok && h[k0 + c] >= kDenseMin)) {
+                off[k0 + c] = (int32_t)pos;
+                pos += h[k0 + c];
+            }
+        for (int64_t s = s0; s < pos; s += kChunk)
+            w.chunks.push_back({0, (int32_t)t, (int32_t)s, (int32_t)std::min<int64_t>(kChunk, pos - s)});
+        const int tx = (int)(t % w.ntile[0]), ty = (int)((t / w.ntile[0]) % w.ntile[1]),
+                  tz = (int)(t / ((int64_t)w.ntile[0] * w.ntile[1]));
+        for (int64_t c = 0; c < cpt; ++c) {
+            const int cnt = h[k0 + c];
+            if (!(dense_ok && cnt >= kDenseMin))
+                continue;
+            off[k0 + c] = (int32_t)pos;
+            const int cx = (int)(c % w.tb[0]), cy = (int)((c / w.tb[0]) % w.tb[1]),
+                      cz = (int)(c / ((int64_t)w.tb[0] * w.tb[1]));
+            const int bx = tx * w.tb[0] + cx, by = ty * w.tb[1] + cy, bz = tz * w.tb[2] + cz;
+            const int packed = bx | (by << 10) | (bz << 20);
+            for (int s = 0; s < cnt; s += kDenseChunk)
+                w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
+            pos += cnt;
+            w.ndense_pts += cnt;
+        }
     }
-    e = hipMemcpy(hist, off.data(), w.ntiles * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(hist, off.data(), nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return hip_fail(e, "hipMemcpy(offsets)");
     if (pl.precision == ADDK_FP32)
@@ -739,7 +794,7 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
         return fail(ADDK_ERR_INVALID_ARG, "kernel must be ADDK_GAUSSIAN or ADDK_MATERN12");
     if (precision != ADDK_FP64 && precision != ADDK_FP32)
         return fail(ADDK_ERR_INVALID_ARG, "precision must be ADDK_FP64 or ADDK_FP32");
-    if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK))
+    if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK | ADDK_TILE_KERNELS_ONLY))
         return fail(ADDK_ERR_INVALID_ARG, "unknown flags");
     if (n < 4 || (n & 1))
         return fail(ADDK_ERR_INVALID_ARG, "n must be even and >= 4");
@@ -805,22 +860,49 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
             plan_release(pl);
             return fail(ADDK_ERR_OOM, "allocation of the point copy failed");
         }
-        const hipMemcpyKind kind = is_device_ptr(X) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        e = hipMemcpy2D(dX, D * sizeof(double), X, ldx * sizeof(double), D * sizeof(double), N, kind);
+        const bool dev = is_device_ptr(X);
+        if (ldx == D) {
+            e = hipMemcpy(dX, X, N * D * sizeof(double), dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+        } else if (dev) {
+            e = hipMemcpy2D(dX, D * sizeof(double), X, ldx * sizeof(double), D * sizeof(double), N,
+                            hipMemcpyDeviceToDevice);
+        } else {
+            std::vector<double> packed((size_t)N * D);
+            for (int64_t j = 0; j < N; ++j)
+                std::memcpy(&packed[(size_t)j * D], X + j * ldx, D * sizeof(double));
+            e = hipMemcpy(dX, packed.data(), N * D * sizeof(double), hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             (void)hipFree(dX);
             plan_release(pl);
             return hip_fail(e, "copy of the points");
         }
     }
+    double t0 = now_ms();
     for (int w = 0; w < P && s == ADDK_OK; ++w)
         s = plan_window(*pl, pl->wins[w], dX, D, dmax, st);
     if (dX)
         (void)hipFree(dX);
+    double t1 = now_ms();
     if (s == ADDK_OK)
         s = plan_compute_multipliers(*pl, st);
+    double t2 = now_ms();
     if (s == ADDK_OK)
         s = build_plan_engine(*pl);
+    double t3 = now_ms();
+    if (log_on() && s == ADDK_OK) {
+        std::fprintf(stderr, "[addk] plan N=%lld P=%d n=%d m=%d n_os=%d prec=%s: sort %.1f ms, multipliers %.1f ms, "
+                             "work lists %.1f ms\n",
+                     (long long)N, P, n, m, (int)nos, precision == ADDK_FP32 ? "fp32" : "fp64", t1 - t0, t2 - t1,
+                     t3 - t2);
+        for (int w = 0; w < P; ++w) {
+            const WinHost &wh = pl->wins[w];
+            std::fprintf(stderr, "[addk]   window %d: d=%d l=%g T=%.6g L=%.6g eta=%.3g box=%dx%dx%d tiles=%lld "
+                                 "sparse chunks=%zu dense items=%zu dense points=%lld\n",
+                         w, wh.d, wh.ell, wh.T, wh.L, wh.eta, wh.ext[0], wh.ext[1], wh.ext[2], (long long)wh.ntiles,
+                         wh.chunks.size(), wh.dense.size(), (long long)wh.ndense_pts);
+        }
+    }
     if (s != ADDK_OK) {
         plan_release(pl);
         return s;
@@ -892,6 +974,10 @@ addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_
         for (const WinHost &w : pl.wins)
             est = std::max(est, error_estimate(pl.kernel, w.L, w.T, w.ell, pl.n, pl.m, pl.sigma_os));
         info->err_estimate = est;
+        info->dense_points = 0;
+        for (const WinHost &w : pl.wins)
+            info->dense_points += w.ndense_pts;
+        info->tile_points = pl.N * pl.P - info->dense_points;
     }
     for (int w = 0; w < pl.P; ++w) {
         if (torus_period)

@@ -137,6 +137,32 @@ def test_chunked_dense_tile(A):
     assert relerr(Y, Yo) < 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_dense_cell_kernels_match_tile_kernels(A, prec, tol):
+    """Dense-cell kernels and tile kernels compute the same sums (different order)."""
+    p = WL.small_problem(20000, 6, [[0, 1, 2], [3, 4], [5]], seed=109, R=5, n=32, m=6, dist="normal")
+    _say("dense vs tile %s" % prec)
+    Yd = gpu_matvec(make_plan(A, p, prec), p.V)
+    Yt = gpu_matvec(make_plan(A, p, prec, dense_kernels=False), p.V)
+    assert relerr(Yd, Yt) < tol
+    Yo = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=np.arange(0, 20000, 97))
+    assert relerr(Yd[::97], Yo) < (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_dense_kernels_all_dims(A, m):
+    """Clustered points in d = 1, 2, 3 windows so that every dense kernel runs."""
+    rng = np.random.default_rng(110)
+    X = np.concatenate([rng.normal(0, 0.01, size=(6000, 6)), rng.uniform(-0.25, 0.25, size=(500, 6))])
+    V = rng.standard_normal((X.shape[0], 7))
+    wins = [[0], [1, 2], [3, 4, 5]]
+    _say("dense all dims m=%d" % m)
+    plan = A.Plan(X, wins, [0.1, 0.12, 0.15], [1.0, 0.8, 1.2], n=32, m=m)
+    Y = gpu_matvec(plan, V)
+    Yo = oracle_direct(X, wins, WL.GAUSSIAN, [0.1, 0.12, 0.15], [1.0, 0.8, 1.2], V, rows=np.arange(0, 6500, 13))
+    assert relerr(Y[::13], Yo) < (1e-10 if m == 6 else 1e-6)
+
+
 def test_single_point_and_identical_points(A):
     _say("degenerate")
     X1 = np.array([[0.1, -0.2, 0.05]])
