@@ -144,11 +144,12 @@ def main():
         from oracle.direct import oracle_direct, oracle_threads
         rng = np.random.default_rng(17345)
         log("cpu baseline (oracle)")
-        probe = rng.choice(N, 8, replace=False)
+        probe = rng.choice(N, 64, replace=False)
+        oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe[:8], want_derivs=True)  # threads up
         t0 = time.perf_counter()
         oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe, want_derivs=True)
         t_probe = time.perf_counter() - t0
-        nrows = int(min(max(8, 8 * args.cpu_seconds / max(t_probe, 1e-3)), 4096))
+        nrows = int(min(max(64, 64 * args.cpu_seconds / max(t_probe, 1e-3)), 8192))
         rows = rng.choice(N, nrows, replace=False)
         t0 = time.perf_counter()
         Yo, dlo, _ = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=rows, want_derivs=True)

@@ -72,6 +72,8 @@ typedef enum {
 #define ADDK_NO_ACCURACY_CHECK 4u /* do not refuse windows with eta < 1                       */
 #define ADDK_TILE_KERNELS_ONLY 8u /* route every point through the tile kernels (no dense-cell
                                      kernels); same results up to rounding, for comparison     */
+#define ADDK_VECTOR_ALU_ONLY 16u  /* FP32 plans: run the dense-cell kernels on the vector ALUs
+                                     instead of the matrix cores; for comparison              */
 
 typedef struct addk_plan_s *addk_plan;
 typedef struct addk_batch_s *addk_batch;

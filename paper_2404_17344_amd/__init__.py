@@ -69,7 +69,8 @@ class Plan:
 
     def __init__(self, X, windows: Sequence[Sequence[int]], ell, sigma, kernel="gaussian", n: int = 64,
                  m: int = 6, oversampling: float = 2.0, precision="fp64", coef: str = "analytic",
-                 torus: str = "auto", check_accuracy: bool = True, dense_kernels: bool = True, stream=None):
+                 torus: str = "auto", check_accuracy: bool = True, dense_kernels: bool = True, matrix_cores: bool = True,
+                 stream=None):
         lib = _lib.load()
         torch = _torch()
         if isinstance(X, torch.Tensor):
@@ -103,6 +104,8 @@ class Plan:
             flags |= ADDK_NO_ACCURACY_CHECK
         if not dense_kernels:
             flags |= _lib.ADDK_TILE_KERNELS_ONLY
+        if not matrix_cores:
+            flags |= _lib.ADDK_VECTOR_ALU_ONLY
         h = ctypes.c_void_p()
         st = _stream(stream) if torch.cuda.is_available() else ctypes.c_void_p(0)
         _lib.check(lib.addk_plan_create(ctypes.byref(h), N, D, xptr, D, self.P, off_a, feat_a, _KERNELS[kernel],

@@ -35,6 +35,7 @@ constexpr int kMaxNos = 128;     // maximal oversampled grid per dimension
 constexpr int kLdsBudget = 64 * 1024;
 constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
 constexpr int kDenseChunk = 256; // maximal points per dense work item
+constexpr int kMfmaMinR = 8;     // fewest RHS for which the matrix-core dense kernels are used
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).
@@ -130,6 +131,7 @@ struct Engine {
     int ndense[4][2] = {};
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
+    bool no_mfma = false;          // use the vector-ALU dense kernels only
     LineGroup *d_groups[ST_COUNT] = {};
     int ngroups[ST_COUNT] = {};
     int maxvol[4] = {0, 0, 0, 0};  // largest tile sub-grid volume per d
@@ -193,6 +195,10 @@ void launch_spread_dense(Engine &E, int D, int wi, int R, IoArgs io, hipStream_t
 void launch_interp_dense(Engine &E, int D, int wi, int R, int nout, hipStream_t st);
 bool dense_width_ok(int W);
 bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st);
+
+// mfma.hip (FP32 matrix-core variants of the dense-cell kernels, d = 3)
+bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
+bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
 
 // plan.hip
 addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);

@@ -269,6 +269,8 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
         pd.Y = Y[p];
         pd.ldy = ldy[p];
     }
+    for (int p = 0; p < nprob; ++p)
+        E.no_mfma = E.no_mfma || (((Plan *)plans[p])->flags & ADDK_VECTOR_ALU_ONLY);
     addk_status s = engine_build_device(E, prec);
     if (s == ADDK_OK)
         s = engine_ensure_workspace(E, R);

@@ -1060,6 +1060,8 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
             if (!E.ndense[d][wi])
                 continue;
             StageTimer t(E, PS_SPREAD_DENSE, st);
+            if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_spread_mfma(E, wi, R, io, st))
+                continue;
             launch_spread_dense(E, d, wi, R, io, st);
         }
     FftCall fc{npair, nout, modes_sel};
@@ -1106,6 +1108,8 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
                     if (!E.ndense[d][wi])
                         continue;
                     StageTimer t(E, PS_INTERP_DENSE, st);
+                    if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_interp_mfma(E, wi, R, nout, st))
+                        continue;
                     launch_interp_dense(E, d, wi, R, nout, st);
                 }
         }

@@ -545,6 +545,7 @@ static addk_status build_plan_engine(Plan &pl)
         E.wlocal[w] = w;
     }
     E.dirty = true;
+    E.no_mfma = (pl.flags & ADDK_VECTOR_ALU_ONLY) != 0;
     return engine_build_device(E, pl.precision);
 }
 
@@ -794,7 +795,8 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
         return fail(ADDK_ERR_INVALID_ARG, "kernel must be ADDK_GAUSSIAN or ADDK_MATERN12");
     if (precision != ADDK_FP64 && precision != ADDK_FP32)
         return fail(ADDK_ERR_INVALID_ARG, "precision must be ADDK_FP64 or ADDK_FP32");
-    if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK | ADDK_TILE_KERNELS_ONLY))
+    if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK | ADDK_TILE_KERNELS_ONLY |
+                  ADDK_VECTOR_ALU_ONLY))
         return fail(ADDK_ERR_INVALID_ARG, "unknown flags");
     if (n < 4 || (n & 1))
         return fail(ADDK_ERR_INVALID_ARG, "n must be even and >= 4");

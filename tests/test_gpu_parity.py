@@ -150,6 +150,29 @@ def test_dense_cell_kernels_match_tile_kernels(A, prec, tol):
 
 
 @pytest.mark.parametrize("m", [4, 6])
+@pytest.mark.parametrize("R", [8, 16, 21])
+def test_matrix_core_kernels_match_vector_kernels(A, m, R):
+    """FP32 dense-cell kernels on the matrix cores agree with the vector-ALU ones,
+    the tile kernels and the oracle (RHS counts that fill, underfill and spill a
+    16-wide block)."""
+    rng = np.random.default_rng(111)
+    X = np.concatenate([rng.normal(0, 0.02, size=(30000, 3)), rng.uniform(-0.25, 0.25, size=(700, 3))])
+    V = rng.standard_normal((X.shape[0], R))
+    _say("mfma vs valu m=%d R=%d" % (m, R))
+    mk = lambda **kw: A.Plan(X, [[0, 1, 2]], [0.1], [1.0], n=32, m=m, precision="fp32", **kw)  # noqa: E731
+    pm = mk()
+    Ym, dlm, _ = pm.dmatvec(torch.from_numpy(V).cuda())
+    Yv, dlv, _ = mk(matrix_cores=False).dmatvec(torch.from_numpy(V).cuda())
+    Yt, dlt, _ = mk(dense_kernels=False).dmatvec(torch.from_numpy(V).cuda())
+    assert pm.query()["dense_points"] > 20000
+    for a, b in [(Ym, Yv), (Ym, Yt), (dlm[0], dlv[0]), (dlm[0], dlt[0])]:
+        assert relerr(a.cpu().numpy(), b.cpu().numpy()) < 3e-6
+    rows = np.arange(0, X.shape[0], 61)
+    Yo = oracle_direct(X, [[0, 1, 2]], WL.GAUSSIAN, [0.1], [1.0], V, rows=rows)
+    assert relerr(Ym.cpu().numpy()[rows], Yo) < (1e-5 if m == 6 else 2e-5)
+
+
+@pytest.mark.parametrize("m", [4, 6])
 def test_dense_kernels_all_dims(A, m):
     """Clustered points in d = 1, 2, 3 windows so that every dense kernel runs."""
     rng = np.random.default_rng(110)
