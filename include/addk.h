@@ -196,12 +196,12 @@ addk_status addk_batch_destroy(addk_batch batch);
  * read, and clears them.  Stage ids: see addk_stage_name (0 .. ADDK_NSTAGES-1).
  * Errors: INVALID_ARG (NULL plan), HIP.
  */
-#define ADDK_NSTAGES 12
+#define ADDK_NSTAGES 13
 addk_status addk_plan_profile(addk_plan plan, int32_t enable);
 addk_status addk_plan_profile_read(addk_plan plan, double *total_ms, int32_t *launches);
 /* "zero", "spread", "fft_x_fwd", "fft_y_fwd", "fft_fused", "fft_y_inv",
- * "fft_x_inv", "interp", "combine", "mode_dot", "spread_dense", "interp_dense";
- * NULL for other ids.  Spreading and interpolation run in two kernels: tile
+ * "fft_x_inv", "interp", "combine", "mode_dot", "spread_dense", "interp_dense",
+ * "gather"; NULL for other ids.  Spreading and interpolation run in two kernels: tile
  * kernels for sparsely populated cells and dense-cell kernels. */
 const char *addk_stage_name(int32_t stage);
 

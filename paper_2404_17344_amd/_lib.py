@@ -30,7 +30,7 @@ ADDK_TORUS_PAPER = 2
 ADDK_NO_ACCURACY_CHECK = 4
 ADDK_TILE_KERNELS_ONLY = 8
 ADDK_VECTOR_ALU_ONLY = 16
-ADDK_NSTAGES = 12
+ADDK_NSTAGES = 13
 
 
 class AddkPlanInfo(ctypes.Structure):

@@ -59,7 +59,9 @@ struct WinDev {
     double *Yw;     // [2][Rcap][N]
     int64_t Rcap;
     int npair_cap;
-    int pad_;
+    int nbase[3];        // base cells per dimension: ext - 2m + 1 (unit for unused dims)
+    const int2 *dmap;    // base cell -> {first, count} of its dense items in the engine's
+                         // matrix-core item list (d = 3 only), or nullptr
 };
 
 // Problem-level input/output pointers (one per plan inside a batch).
@@ -109,7 +111,7 @@ struct WinHost {
 struct Plan;
 
 enum ProfStage { PS_ZERO = 0, PS_SPREAD, PS_FFT_X_FWD, PS_FFT_Y_FWD, PS_FFT_FUSED, PS_FFT_Y_INV, PS_FFT_X_INV,
-                 PS_INTERP, PS_COMBINE, PS_MODE_DOT, PS_SPREAD_DENSE, PS_INTERP_DENSE, PS_COUNT };
+                 PS_INTERP, PS_COMBINE, PS_MODE_DOT, PS_SPREAD_DENSE, PS_INTERP_DENSE, PS_GATHER, PS_COUNT };
 
 struct ProfRec {
     int stage;
@@ -132,6 +134,11 @@ struct Engine {
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
     bool no_mfma = false;          // use the vector-ALU dense kernels only
+    int2 *d_dmap[2] = {nullptr, nullptr};        // base-cell maps of all windows (per 2m = 8, 12)
+    LineGroup *d_gtiles[2] = {nullptr, nullptr};  // output tiles of the dense block gather
+    int ngtiles[2] = {0, 0};
+    float *scratch[2] = {nullptr, nullptr};       // per-item dense spread blocks
+    int64_t scratch_cap[2] = {0, 0};              // floats
     LineGroup *d_groups[ST_COUNT] = {};
     int ngroups[ST_COUNT] = {};
     int maxvol[4] = {0, 0, 0, 0};  // largest tile sub-grid volume per d
@@ -199,6 +206,8 @@ bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st);
 // mfma.hip (FP32 matrix-core variants of the dense-cell kernels, d = 3)
 bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
+void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st);
+bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st);
 
 // plan.hip
 addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);

@@ -214,7 +214,7 @@ const char *addk_stage_name(int32_t stage)
 {
     static const char *names[PS_COUNT] = {"zero",      "spread",    "fft_x_fwd", "fft_y_fwd",    "fft_fused",
                                           "fft_y_inv", "fft_x_inv", "interp",    "combine",      "mode_dot",
-                                          "spread_dense", "interp_dense"};
+                                          "spread_dense", "interp_dense", "gather"};
     if (stage < 0 || stage >= PS_COUNT)
         return nullptr;
     return names[stage];

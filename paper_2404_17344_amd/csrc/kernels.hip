@@ -788,6 +788,11 @@ void engine_free(Engine &E)
     free_dev(E.yw);
     free_dev(E.d_probs);
     free_dev(E.d_partial);
+    for (int wi = 0; wi < 2; ++wi) {
+        free_dev(E.d_dmap[wi]);
+        free_dev(E.d_gtiles[wi]);
+        free_dev(E.scratch[wi]);
+    }
     for (const ProfRec &r : E.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -867,6 +872,66 @@ addk_status engine_build_device(Engine &E, int precision)
                     return hip_fail(e, "hipMemcpy(dense items)");
             }
         }
+    // base-cell maps and gather tiles for the matrix-core dense spread (d = 3)
+    for (WinDev &d : E.wdev)
+        d.dmap = nullptr;
+    for (int wi = 0; wi < 2; ++wi) {
+        free_dev(E.d_dmap[wi]);
+        free_dev(E.d_gtiles[wi]);
+        E.d_dmap[wi] = nullptr;
+        E.d_gtiles[wi] = nullptr;
+        E.ngtiles[wi] = 0;
+        const std::vector<Chunk> &items = dn[3][wi];
+        if (items.empty())
+            continue;
+        std::vector<int64_t> moff(E.wdev.size(), -1);
+        int64_t mtot = 0;
+        for (size_t w = 0; w < E.wdev.size(); ++w) {
+            WinDev &d = E.wdev[w];
+            if (d.d != 3 || d.W != (wi == 0 ? 8 : 12))
+                continue;
+            for (int a = 0; a < 3; ++a)
+                d.nbase[a] = d.ext[a] - d.W + 1;
+            moff[w] = mtot;
+            mtot += (int64_t)d.nbase[0] * d.nbase[1] * d.nbase[2];
+        }
+        std::vector<int2> map(mtot, make_int2(0, 0));
+        std::vector<std::vector<char>> mark(E.wdev.size());
+        for (size_t i = 0; i < items.size(); ++i) {
+            const Chunk &c = items[i];
+            const WinDev &d = E.wdev[c.win];
+            const int bx = c.tile & 1023, by = (c.tile >> 10) & 1023, bz = c.tile >> 20;
+            int2 &e = map[moff[c.win] + ((int64_t)bz * d.nbase[1] + by) * d.nbase[0] + bx];
+            if (e.y == 0)
+                e.x = (int)i;
+            e.y += 1;
+            const int nt0 = (d.ext[0] + 3) / 4, nt1 = (d.ext[1] + 3) / 4, nt2 = (d.ext[2] + 3) / 4;
+            if (mark[c.win].empty())
+                mark[c.win].assign((size_t)nt0 * nt1 * nt2, 0);
+            for (int tz = bz / 4; tz <= (bz + d.W - 1) / 4 && tz < nt2; ++tz)
+                for (int ty = by / 4; ty <= (by + d.W - 1) / 4 && ty < nt1; ++ty)
+                    for (int tx = bx / 4; tx <= (bx + d.W - 1) / 4 && tx < nt0; ++tx)
+                        mark[c.win][((size_t)tz * nt1 + ty) * nt0 + tx] = 1;
+        }
+        std::vector<LineGroup> tiles;
+        for (size_t w = 0; w < E.wdev.size(); ++w)
+            for (size_t t = 0; t < mark[w].size(); ++t)
+                if (mark[w][t])
+                    tiles.push_back({(int)w, (int)t});
+        hipError_t e = hipMalloc(&E.d_dmap[wi], std::max<int64_t>(1, mtot) * sizeof(int2));
+        if (e == hipSuccess)
+            e = hipMemcpy(E.d_dmap[wi], map.data(), mtot * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMalloc(&E.d_gtiles[wi], std::max<size_t>(1, tiles.size()) * sizeof(LineGroup));
+        if (e == hipSuccess && !tiles.empty())
+            e = hipMemcpy(E.d_gtiles[wi], tiles.data(), tiles.size() * sizeof(LineGroup), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_fail(e, "dense block maps");
+        E.ngtiles[wi] = (int)tiles.size();
+        for (size_t w = 0; w < E.wdev.size(); ++w)
+            if (moff[w] >= 0)
+                E.wdev[w].dmap = E.d_dmap[wi] + moff[w];
+    }
     for (int s = 0; s < ST_COUNT; ++s) {
         E.ngroups[s] = (int)gr[s].size();
         free_dev(E.d_groups[s]);
@@ -928,6 +993,23 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     }
     E.ws_bytes = bytes;
     E.yw_bytes = ybytes;
+    // per-item blocks of the matrix-core dense spread: items x RHS blocks x (2m)^3 x 16
+    for (int wi = 0; wi < 2; ++wi) {
+        const int W = wi == 0 ? 8 : 12;
+        const int64_t need = (int64_t)E.ndense[3][wi] * ((rcap + 15) / 16) * W * W * W * 16;
+        free_dev(E.scratch[wi]);
+        E.scratch[wi] = nullptr;
+        E.scratch_cap[wi] = 0;
+        if (need > 0 && E.precision == ADDK_FP32 && !E.no_mfma) {
+            e = hipMalloc(&E.scratch[wi], need * sizeof(float));
+            if (e != hipSuccess) {
+                set_error("dense spread scratch allocation failed");
+                return ADDK_ERR_OOM;
+            }
+            E.scratch_cap[wi] = need;
+            E.ws_bytes += need * (int64_t)sizeof(float);
+        }
+    }
     char *p = (char *)E.ws;
     double *yp = E.yw;
     for (WinDev &w : E.wdev) {
@@ -1059,9 +1141,16 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         for (int wi = 0; wi < 2; ++wi) {
             if (!E.ndense[d][wi])
                 continue;
-            StageTimer t(E, PS_SPREAD_DENSE, st);
-            if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_spread_mfma(E, wi, R, io, st))
+            if (d == 3 && R >= kMfmaMinR && !E.no_mfma && E.scratch[wi]) {
+                {
+                    StageTimer t(E, PS_SPREAD_DENSE, st);
+                    launch_spread_mfma(E, wi, R, io, st);
+                }
+                StageTimer t(E, PS_GATHER, st);
+                launch_gather_blocks(E, wi, R, st);
                 continue;
+            }
+            StageTimer t(E, PS_SPREAD_DENSE, st);
             launch_spread_dense(E, d, wi, R, io, st);
         }
     FftCall fc{npair, nout, modes_sel};
@@ -1099,6 +1188,8 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
                 if (!E.nchunks[d])
                     continue;
                 StageTimer t(E, PS_INTERP, st);
+                if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_interp_tile_mfma(E, R, nout, st))
+                    continue;
                 if (d == 1) launch_interp<real, 1>(E, R, nout, st);
                 if (d == 2) launch_interp<real, 2>(E, R, nout, st);
                 if (d == 3) launch_interp<real, 3>(E, R, nout, st);

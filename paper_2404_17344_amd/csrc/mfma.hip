@@ -44,6 +44,44 @@ __device__ __forceinline__ void unpack_cell_m(int packed, int &bx, int &by, int 
 
 __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
 
+// Products of one z-slab for the first NG point groups of a wave, with the NG
+// accumulator chains interleaved so that one B fragment feeds NG MFMAs.
+template <int SW, int NT, int SX, int NG>
+__device__ __forceinline__ void slab_products(f4 (&acc)[4], const float (&wxq)[4][NT], const float (&wy)[4][SW],
+                                              const float (&wz)[4], const float (*sl)[16], int ny, int q, int mrow)
+{
+#pragma unroll
+    for (int oy = 0; oy < SW; ++oy) {
+        if (oy >= ny)
+            break;
+        float wyz[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            wyz[g] = wy[g][oy] * wz[g];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float b = sl[oy * SX + 4 * t + q][mrow];
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(wyz[g] * wxq[g][t], b, acc[g], 0, 0, 0);
+        }
+    }
+}
+
+template <int SW, int NT, int SX>
+__device__ __forceinline__ void slab_products_n(int ng, f4 (&acc)[4], const float (&wxq)[4][NT],
+                                                const float (&wy)[4][SW], const float (&wz)[4], const float (*sl)[16],
+                                                int ny, int q, int mrow)
+{
+    switch (ng) {
+    case 1: slab_products<SW, NT, SX, 1>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
+    case 2: slab_products<SW, NT, SX, 2>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
+    case 3: slab_products<SW, NT, SX, 3>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
+    case 4: slab_products<SW, NT, SX, 4>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
+    default: break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
@@ -67,15 +105,14 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
     const float *coords = (const float *)w.coords;
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
 
-    // window values of the lane's point (A row) in each of the wave's four groups
+    // the item's 16-point groups are dealt round-robin to the four waves
+    const int ngrp = (it.count + 15) >> 4;
+    const int nmine = ngrp > wave ? (ngrp - wave + 3) >> 2 : 0;
     float wxq[4][NT], wy[4][W], uz[4];
-    bool gact[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        const int gbase = wave * 64 + g * 16;
-        gact[g] = gbase < it.count;
-        const int p = gbase + mrow;
-        const bool act = p < it.count;
+        const int p = (wave + 4 * g) * 16 + mrow;
+        const bool act = g < nmine && p < it.count;
         const int j = it.start + (act ? p : 0);
         const float ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
@@ -134,21 +171,12 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
         if (oz + 1 < W)
             load(oz + 1);  // in flight during this slab's products
         const int cur = oz & 1;
+        if (nmine > 0) {
+            float wz[4];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            if (!gact[g])
-                continue;
-            const float wz = kb_psi_f(uz[g] - (float)(bz + oz), mm, kb, ie);
-#pragma unroll
-            for (int oy = 0; oy < W; ++oy) {
-                const float wyz = wy[g][oy] * wz;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const float a = wyz * wxq[g][t];
-                    const float b = slab[cur][oy * W + 4 * t + q][mrow];
-                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[g], 0, 0, 0);
-                }
-            }
+            for (int g = 0; g < 4; ++g)
+                wz[g] = kb_psi_f(uz[g] - (float)(bz + oz), mm, kb, ie);
+            slab_products_n<W, NT, W>(nmine, acc, wxq, wy, wz, slab[cur], W, q, mrow);
         }
         if (oz + 1 < W)
             store((oz + 1) & 1);
@@ -160,9 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
     double *dst = w.Yw + ((int64_t)o * w.Rcap + r0 + mrow) * w.N;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
+        if (g >= nmine)
+            break;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int p = wave * 64 + g * 16 + 4 * q + i;
+            const int p = (wave + 4 * g) * 16 + 4 * q + i;
             if (p < it.count)
                 dst[w.perm[it.start + p]] = (double)acc[g][i];
         }
@@ -172,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
 // ---------------------------------------------------------------------------
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                        IoArgs io, int R)
+                                                        IoArgs io, int R, float *__restrict__ scratch)
 {
     constexpr int WW = W * W;
     constexpr int MT = WW / 16;  // M tiles per z-slab
@@ -283,14 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         buf ^= 1;
     }
 
-    // flush: transpose each slab through LDS so that consecutive lanes add to
-    // consecutive grid cells of one complex grid
+    // write the item's block [oz][oy][ox][16 RHS] to its scratch slot (plain
+    // stores; the blocks of all items are summed by k_gather_blocks)
     float *fl = (float *)lds + wave * FL;
-    float *G = (float *)w.G;
-    const int ex = w.ext[0], ey = w.ext[1];
-    const int nr = min(16, R - r0);
-    const int np2 = (nr + 1) >> 1;
-    const int pbase = r0 >> 1;
+    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * (W * WW * 16);
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int oz = wave + 4 * s;
@@ -302,18 +328,229 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int idx = lane; idx < np2 * WW; idx += 64) {
-            const int pi = idx / WW, tap = idx - pi * WW;
-            const int ox = tap % W, oy = tap / W;
-            const int64_t cell = ((int64_t)(bz + oz) * ey + by + oy) * ex + bx + ox;
-            float *gp = G + ((int64_t)(pbase + pi) * w.szG + cell) * 2;
-            unsafeAtomicAdd(gp, fl[tap * 17 + 2 * pi]);
-            if (2 * pi + 1 < nr)
-                unsafeAtomicAdd(gp + 1, fl[tap * 17 + 2 * pi + 1]);
+        float *ds = dst + (int64_t)oz * WW * 16;
+        for (int idx = lane; idx < WW * 4; idx += 64) {
+            const int tap = idx >> 2, r4 = (idx & 3) * 4;
+            const float *src = fl + tap * 17 + r4;
+            *(f4 *)(ds + tap * 16 + r4) = f4{src[0], src[1], src[2], src[3]};
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sum the per-item blocks into the spread grid.  A block owns a 4 x 4 x 4 tile
+// of grid cells and 16 RHS; it visits, in a fixed order, every base cell whose
+// (2m)^3 window block overlaps the tile and adds the overlapping part of each
+// of its items' blocks.  Every grid value is written by exactly one thread, so
+// no atomics are needed and the sum order is fixed.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restrict__ wins,
+                                                          const LineGroup *__restrict__ tiles,
+                                                          const float *__restrict__ scratch, int R)
+{
+    constexpr int WW = W * W;
+    __shared__ f4 red[3][64][4];
+    const LineGroup tg = tiles[blockIdx.x];
+    const WinDev &w = wins[tg.win];
+    const int rb = blockIdx.y;
+    const int r0 = rb * 16;
+    if (r0 >= R)
+        return;
+    const int nrb = gridDim.y;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    const int nt0 = (ex + 3) / 4, nt1 = (ey + 3) / 4;
+    const int tx = tg.grp % nt0, ty = (tg.grp / nt0) % nt1, tz = tg.grp / (nt0 * nt1);
+    // lane = grid cell of the tile (all 16 RHS); the four waves split the base cells
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gx = tx * 4 + (lane & 3), gy = ty * 4 + ((lane >> 2) & 3), gz = tz * 4 + (lane >> 4);
+    const int nb0 = w.nbase[0], nb1 = w.nbase[1], nb2 = w.nbase[2];
+    const int2 *map = w.dmap;
+    f4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+    const int z0 = max(0, tz * 4 - (W - 1)), z1 = min(nb2 - 1, tz * 4 + 3);
+    const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
+    const int x0 = max(0, tx * 4 - (W - 1)), x1 = min(nb0 - 1, tx * 4 + 3);
+    for (int bz = z0 + wave; bz <= z1; bz += 4) {
+        const int oz = gz - bz;
+        for (int by = y0; by <= y1; ++by) {
+            const int oy = gy - by;
+            const int2 *mrow = map + ((int64_t)bz * nb1 + by) * nb0;
+            for (int bx = x0; bx <= x1; ++bx) {
+                const int2 it = mrow[bx];
+                if (it.y == 0)
+                    continue;
+                const int ox = gx - bx;
+                if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W && (unsigned)oz < (unsigned)W) {
+                    const int tap = (oz * W + oy) * W + ox;
+                    for (int i = it.x; i < it.x + it.y; ++i) {
+                        const f4 *src = (const f4 *)(scratch + (((int64_t)i * nrb + rb) * (W * WW) + tap) * 16);
+                        acc[0] += src[0];
+                        acc[1] += src[1];
+                        acc[2] += src[2];
+                        acc[3] += src[3];
+                    }
+                }
+            }
+        }
+    }
+    // fixed-order reduction over the four waves
+    if (wave > 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            red[wave - 1][lane][i] = acc[i];
+    }
+    __syncthreads();
+    if (wave > 0)
+        return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc[i] += red[k][lane][i];
+    if (gx >= ex || gy >= ey || gz >= ez)
+        return;
+    float *G = (float *)w.G;
+    const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + i;
+        if (r < R)
+            G[((int64_t)(r >> 1) * w.szG + c) * 2 + (r & 1)] += acc[i >> 2][i & 3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interp for the sparsely populated cells of one tile on the matrix cores: the
+// tile's sub-grid (tile + window halo, x padded to 16) plays the role of the
+// dense cell's window block; weights outside a point's support are zero.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
+                                                             const Chunk *__restrict__ chunks, int R)
+{
+    constexpr int SX = 16;         // padded sub-grid x extent (tb = 4, 2m <= 12)
+    constexpr int SY = 3 + W;      // maximal sub-grid y/z extent (tb + 2m - 1)
+    __shared__ __align__(16) float slab[2][SY * SX][16];
+
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int r0 = blockIdx.y * 16;
+    if (r0 >= R)
+        return;
+    const int o = blockIdx.z;
+    const int nr = min(16, R - r0);
+    int tl = ch.tile;
+    const int tx = tl % w.ntile[0];
+    tl /= w.ntile[0];
+    const int ty = tl % w.ntile[1];
+    const int tz = tl / w.ntile[1];
+    const int x0 = tx * w.tb[0], y0 = ty * w.tb[1], z0 = tz * w.tb[2];
+    const int S0 = w.S[0], S1 = w.S[1], S2 = w.S[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, mrow = lane & 15;
+    const float *coords = (const float *)w.coords;
+    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    const float *H = (const float *)w.H;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    const int p0 = r0 >> 1;
+    const int np = (nr + 1) >> 1;
+    constexpr int SL = (8 * SY * SX + kBlock - 1) / kBlock;
+    float2 pre[SL];
+    auto load = [&](int oz) {
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int idx = threadIdx.x + k * kBlock;
+            const int pi = idx / (SY * SX), c = idx - pi * (SY * SX);
+            const int ox = c % SX, oy = c / SX;
+            float2 v = {0.f, 0.f};
+            const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
+            if (idx < 8 * SY * SX && pi < np && ox < S0 && oy < S1 && gx < ex && gy < ey && gz < ez) {
+                const int64_t off = ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
+                v = *(const float2 *)(H + off);
+            }
+            pre[k] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int idx = threadIdx.x + k * kBlock;
+            if (idx < 8 * SY * SX) {
+                const int pi = idx / (SY * SX), c = idx - pi * (SY * SX);
+                slab[buf][c][2 * pi] = pre[k].x;
+                slab[buf][c][2 * pi + 1] = (2 * pi + 1 < nr) ? pre[k].y : 0.f;
+            }
+        }
+    };
+
+    for (int pass = 0; pass < ch.count; pass += 256) {
+        // window values of the lane's point (A row) on the sub-grid; the pass's
+        // 16-point groups are dealt round-robin to the four waves
+        const int npass = min(256, ch.count - pass);
+        const int ngrp = (npass + 15) >> 4;
+        const int nmine = ngrp > wave ? (ngrp - wave + 3) >> 2 : 0;
+        float wxq[4][4], wys[4][SY], uz[4];
+        int lbz[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int p = pass + (wave + 4 * g) * 16 + mrow;
+            const bool act = g < nmine && p < ch.count;
+            const int j = ch.start + (act ? p : 0);
+            const float ux = coords[j], uy = coords[w.N + j];
+            uz[g] = coords[2 * w.N + j];
+            const int lx = (int)floorf(ux) - w.m + 1 - x0, ly = (int)floorf(uy) - w.m + 1 - y0;
+            lbz[g] = (int)floorf(uz[g]) - w.m + 1 - z0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ox = 4 * t + q;
+                wxq[g][t] = (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_f(ux - (float)(x0 + ox), mm, kb, ie) : 0.f;
+            }
+#pragma unroll
+            for (int oy = 0; oy < SY; ++oy)
+                wys[g][oy] = ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+        }
+        f4 acc[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+        load(0);
+        store(0);
+        __syncthreads();
+        for (int oz = 0; oz < S2; ++oz) {
+            if (oz + 1 < S2)
+                load(oz + 1);
+            const int cur = oz & 1;
+            if (nmine > 0) {
+                float wz[4];
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    wz[g] = ((unsigned)(oz - lbz[g]) < (unsigned)W) ? kb_psi_f(uz[g] - (float)(z0 + oz), mm, kb, ie)
+                                                                    : 0.f;
+                slab_products_n<SY, 4, SX>(nmine, acc, wxq, wys, wz, slab[cur], S1, q, mrow);
+            }
+            if (oz + 1 < S2)
+                store((oz + 1) & 1);
+            __syncthreads();
+        }
+        if (mrow < nr) {
+            double *dst = w.Yw + ((int64_t)o * w.Rcap + r0 + mrow) * w.N;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (g >= nmine)
+                    break;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
+                    if (p < ch.count)
+                        dst[w.perm[ch.start + p]] = (double)acc[g][i];
+                }
+            }
+        }
     }
 }
 
@@ -334,13 +571,44 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
 
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
-    if (E.precision != ADDK_FP32 || !E.ndense[3][wi])
+    if (E.precision != ADDK_FP32 || !E.ndense[3][wi] || !E.scratch[wi])
         return false;
     dim3 grid(E.ndense[3][wi], (R + 15) / 16);
     if (wi == 0)
-        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R);
+        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R,
+                           E.scratch[wi]);
     else
-        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R);
+        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R,
+                           E.scratch[wi]);
+    return true;
+}
+
+void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st)
+{
+    if (!E.ngtiles[wi])
+        return;
+    dim3 grid(E.ngtiles[wi], (R + 15) / 16);
+    if (wi == 0)
+        hipLaunchKernelGGL(k_gather_blocks<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], E.scratch[wi], R);
+    else
+        hipLaunchKernelGGL(k_gather_blocks<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], E.scratch[wi],
+                           R);
+}
+
+}  // namespace addk
+
+namespace addk {
+
+bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st)
+{
+    const int W = E.tile_w[3];
+    if (E.precision != ADDK_FP32 || !E.nchunks[3] || (W != 8 && W != 12))
+        return false;
+    dim3 grid(E.nchunks[3], (R + 15) / 16, nout);
+    if (W == 8)
+        hipLaunchKernelGGL(k_interp_tile_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_chunks[3], R);
+    else
+        hipLaunchKernelGGL(k_interp_tile_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_chunks[3], R);
     return true;
 }
 
