@@ -20,6 +20,7 @@ Printed as one JSON line, with
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +42,38 @@ def relerr_cols(a: np.ndarray, b: np.ndarray) -> float:
     return float(max(np.linalg.norm(a[:, r] - b[:, r]) / np.linalg.norm(b[:, r]) for r in range(b.shape[1])))
 
 
+def source_digest() -> str:
+    """SHA-256 over the library's device sources (every .hip and .h under csrc/)."""
+    csrc = os.path.join(ROOT, "paper_2404_17344_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch of a stage's kernel, from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
+    None when the summary is missing or the device sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "c5_dmatvec_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest, table = None, {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] == "source_sha256:":
+                digest = parts[1]
+            elif len(parts) == 4 and parts[0] == "traffic_bytes:":
+                table[parts[1]] = (float(parts[2]), float(parts[3]))
+    if digest != source_digest() or stage not in table:
+        return None
+    rd, wr = table[stage]
+    return {"bytes": rd + wr, "read": rd, "written": wr}
+
+
 def log(msg: str):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -54,6 +87,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -63,6 +98,18 @@ def main():
 
     import torch
 
+    if args.copy_calibration:
+        # A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the ones read for the path's own kernels.
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
+        return
+
     import paper_2404_17344_amd as A
     import workloads as WL
 
@@ -71,7 +118,8 @@ def main():
     log("generating inputs")
     p = WL.large_c5(N=args.N)
     N, R, P, W = p.N, p.R, p.P, 2 * p.m
-    V = torch.from_numpy(p.V).to(dev)
+    # column-major N x R, the layout the library takes: no copy inside the step
+    V = torch.from_numpy(np.ascontiguousarray(p.V.T)).to(dev).t()
     torch.cuda.synchronize()
 
     log("plan (fp32)")
@@ -119,7 +167,8 @@ def main():
     avg_ms = tot_ms / max(launches, 1)
     achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dom) if N == 1000000 else None,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops[dom],
                 "point_window_pairs": pts[dom]}
     stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}

@@ -9,11 +9,11 @@
  *   dY_ds_w  = 2 sigma_w K_w V                                (dK/dsigma_w V)
  *
  * with (K_w)_ij = kappa(||x_i^{W_w} - x_j^{W_w}||; l_w).  The kernel is the
- * windowed additive kernel of eq. (3)/(4) of Wagner, Nestler & Stoll, "Fast
+ * windowed additive kernel of eqs. (3), (7)-(8) of Wagner, Nestler & Stoll, "Fast
  * evaluation of additive kernels" (Gaussian, "Implementing the NFFT approach";
  * Matern-1/2, "Extension to other kernels"); its derivatives are those of the
  * same sections.  Each window's product is evaluated by the NFFT-based fast
- * summation of eqs. (5)-(7): window-function spreading onto an oversampled
+ * summation of eqs. (4)-(6): window-function spreading onto an oversampled
  * torus grid, FFT, multiplication by the kernel's periodised Fourier
  * coefficients, inverse FFT and interpolation back to the points; the
  * windows are then summed in FP64.  The trigonometric sum of eq. (6) runs
@@ -110,8 +110,8 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
                              int32_t precision, uint32_t flags, void *stream);
 
 /*
- * Y = sum_w sigma_w^2 K_w V (eqs. (5)-(7) per window, then the window sum of
- * eq. (4)).  V: N x R (ldv >= N), Y: N x R (ldy >= N); device pointers.
+ * Y = sum_w sigma_w^2 K_w V (eqs. (4)-(6) per window, then the window sum of
+ * eq. (7)).  V: N x R (ldv >= N), Y: N x R (ldy >= N); device pointers.
  * R >= 1.  V and Y must not overlap.
  */
 addk_status addk_matvec(addk_plan plan, int32_t R, const double *V, int64_t ldv,
@@ -212,6 +212,17 @@ const char *addk_stage_name(int32_t stage);
  * window dimension of the plan (PAPER rule only). */
 addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, uint32_t rule,
                               int32_t dmax, double *T);
+
+/* Smallest bandwidth n for one window of extent L (largest per-coordinate
+ * range of its points, data units) and length scale l whose a-priori error
+ * estimate (image, truncation and window terms, automatic torus period) is at
+ * most tol, among the n the library supports for this m and oversampling
+ * (round(oversampling n) a power of two in [16, 128], eta >= 1, data box
+ * inside the torus).  For a plan, take the largest n over its windows.
+ * err_estimate (optional) receives the estimate at the chosen n.
+ * Errors: INVALID_ARG; ACCURACY when no supported n reaches tol. */
+addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, double oversampling, double tol,
+                          int32_t *n, double *err_estimate);
 
 /* Fourier transform of the normalised Kaiser-Bessel window used for spreading,
  * Psi(k) = int psi(z) e^{-2 pi i z k / n_os} dz, evaluated by Gauss-Legendre

@@ -10,7 +10,7 @@
  * What is computed (O(P * N * rows) work, no approximation):
  *
  *   Windowed additive kernel (eq. (3), "windowed ANOVA kernel" section, and
- *   its implementation form eq. (4) in "Implementing the NFFT approach"):
+ *   its implementation form eqs. (7)-(8) in "Implementing the NFFT approach"):
  *       K(x_i, x_j) = sum_w sigma_w^2 kappa(||x_i^{W_w} - x_j^{W_w}||; l_w)
  *   with a separate amplitude sigma_w per window as in the feature-grouping
  *   optimisation of the feature-arrangement section (one shared sigma_f is

@@ -1,6 +1,6 @@
 """ctypes wrapper of ``direct.c`` (plain FP64 direct sums).  TEST INFRASTRUCTURE ONLY.
 
-The C source follows the kernel definitions of eq. (3)/(4), the l- and
+The C source follows the kernel definitions of eq. (3) and eqs. (7)-(8), the l- and
 sigma-derivatives of the section "Implementing the NFFT approach" (Gaussian)
 and of "Extension to other kernels" (Matern-1/2).
 """

@@ -64,6 +64,31 @@ def window_ft(m: int, n_os: int, oversampling: float, k: float) -> float:
     return v.value
 
 
+def choose_n(kernel, L: float, ell: float, m: int = 6, oversampling: float = 2.0, tol: float = 1e-5):
+    """Smallest supported bandwidth n meeting tol for one window (extent L, length scale l).
+
+    Returns (n, error estimate); raises AddkError (ACCURACY) when none does."""
+    lib = _lib.load()
+    n = ctypes.c_int32()
+    err = ctypes.c_double()
+    _lib.check(lib.addk_choose_n(_KERNELS[kernel], float(L), float(ell), int(m), float(oversampling), float(tol),
+                                 ctypes.byref(n), ctypes.byref(err)), "addk_choose_n")
+    return n.value, err.value
+
+
+def choose_n_for(X, windows: Sequence[Sequence[int]], ell, kernel="gaussian", m: int = 6,
+                 oversampling: float = 2.0, tol: float = 1e-5) -> int:
+    """Bandwidth for a whole plan: the largest per-window choice (host X, (N, D))."""
+    X = np.asarray(X, dtype=np.float64)
+    ell = np.broadcast_to(np.asarray(ell, dtype=np.float64), (len(windows),))
+    best = 0
+    for w, feats in enumerate(windows):
+        sub_x = X[:, list(feats)]
+        L = float((sub_x.max(axis=0) - sub_x.min(axis=0)).max()) if X.shape[0] else 0.0
+        best = max(best, choose_n(kernel, L, ell[w], m, oversampling, tol)[0])
+    return best
+
+
 class Plan:
     """A plan for y = sum_w sigma_w^2 K_w v over fixed points and windows."""
 

@@ -70,6 +70,7 @@ _SIGS = {
     "addk_stage_name": [_i32],
     "addk_torus_period": [_i32, _d, _d, _i32, _u32, _i32, _pd],
     "addk_window_ft": [_i32, _i32, _d, _d, _pd],
+    "addk_choose_n": [_i32, _d, _d, _i32, _d, _d, _pi32, _pd],
     "addk_status_string": [_i32],
     "addk_last_error": [],
     "addk_version": [],

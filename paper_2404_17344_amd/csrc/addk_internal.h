@@ -13,7 +13,9 @@
 //   A3  [o][pair][ez][n1][n1]         after the fused z pass (o = kernel, derivative)
 //   A4  [o][pair][ez][ey][n1]         after the inverse y pass
 //   H   [o][pair][ez][ey][ex]         after the inverse x pass, read by interpolation
-//   Yw  [o][r][N] (FP64)              per-window interpolated products, caller order
+//   Vp  [N][ceil16(Rcap)] (real)      the RHS, point-major, converted once per call
+//   Yw  [o][N][Rcap] (FP64)           per-window interpolated products, caller point
+//                                     order, point-major (one point's RHS contiguous)
 // Lower-dimensional windows use the same arrays with unit extents.
 #pragma once
 
@@ -56,7 +58,7 @@ struct WinDev {
     const void *Bd;
     void *G, *A1, *A2, *A3, *A4, *H, *Gm, *Vm;  // workspace (complex interleaved)
     int64_t szG, szA1, szA2, szA3, szA4, szH, szM;  // complex elements per pair
-    double *Yw;     // [2][Rcap][N]
+    double *Yw;     // [2][N][Rcap]
     int64_t Rcap;
     int npair_cap;
     int nbase[3];        // base cells per dimension: ext - 2m + 1 (unit for unused dims)
@@ -70,6 +72,8 @@ struct ProbDev {
     int32_t wbeg, wend;       // windows [wbeg, wend) of the engine belong to it
     const double *V;
     int64_t ldv;
+    const void *Vp;           // point-major copy of V in the engine's precision,
+    int64_t ldvp;             // Vp[i * ldvp + r], r < ldvp (RHS padded to 16 with zeros)
     double *Y;
     int64_t ldy;
     double *dYl;
@@ -147,6 +151,9 @@ struct Engine {
     int64_t ws_bytes = 0;
     double *yw = nullptr;          // per-window FP64 products
     int64_t yw_bytes = 0;
+    void *vpack = nullptr;         // point-major copies of the problems' V (see ProbDev::Vp)
+    int64_t vpack_bytes = 0;
+    int64_t vpack_ld = 0;
     int npair_cap = 0;
     int64_t rcap = 0;
     ProbDev *d_probs = nullptr;

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
             const int p = e / RBB, i = e - p * RBB;
             const int r = r0 + i;
             const int orig = w.perm[it.start + p0 + p];
-            pv[p][i] = r < R ? (real)pio.V[orig + (int64_t)r * pio.ldv] : real(0);
+            pv[p][i] = r < R ? ((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
         }
         __syncthreads();
         for (int p = 0; p < np; ++p) {
@@ -267,11 +267,11 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
         }
     }
     const int orig = w.perm[j];
-    double *dst = w.Yw + ((int64_t)o * w.Rcap + r0) * w.N + orig;
+    double *dst = w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
         if (i < nr)
-            dst[(int64_t)i * w.N] = (double)acc[i];
+            dst[i] = (double)acc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_tile(const WinDev *__restrict
             const int p = e / RT, i = e - p * RT;
             const int r = r0 + i;
             const int orig = w.perm[ch.start + p0 + p];
-            pv[p][i] = r < R ? (real)pio.V[orig + (int64_t)r * pio.ldv] : real(0);
+            pv[p][i] = r < R ? ((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
         }
         __syncthreads();
         for (int e = t; e < np * D * W; e += kBlock) {

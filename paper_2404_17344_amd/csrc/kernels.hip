@@ -1,4 +1,4 @@
-// Stage kernels of the NFFT-based fast summation (eqs. (5)-(7)) for gfx950 and
+// Stage kernels of the NFFT-based fast summation (eqs. (4)-(6)) for gfx950 and
 // the engine that launches them over work lists spanning many windows.
 //
 //   spread  : g_l = sum_j v_j prod_i psi(u_ji - l_i)           (adjoint NFFT gridding)
@@ -73,6 +73,38 @@ __device__ __forceinline__ int base_cell(real u, int m)
 
 __device__ __forceinline__ ProbDev get_prob(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
 
+// V (FP64, column-major, caller order) -> Vp (engine precision, point-major,
+// RHS padded with zeros to ldvp), through an LDS tile of 64 points x 16 RHS so
+// that both sides are accessed contiguously.  The spread kernels then read one
+// contiguous run per point.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_pack_v(IoArgs io, int R)
+{
+    __shared__ double tile[16][65];
+    const ProbDev p = get_prob(io, blockIdx.y);
+    real *vp = (real *)p.Vp;
+    const int t = threadIdx.x, il = t & 63, rq = t >> 6;
+    for (int64_t i0 = blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
+        for (int r0 = 0; r0 < p.ldvp; r0 += 16) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = r0 + rq + 4 * k;
+                const int64_t i = i0 + il;
+                tile[rq + 4 * k][il] = (i < p.N && r < R) ? p.V[i + (int64_t)r * p.ldv] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e = t + kBlock * k, pl = e >> 4, rr = e & 15;
+                const int64_t i = i0 + pl;
+                if (i < p.N)
+                    vp[i * p.ldvp + r0 + rr] = (real)tile[rr][pl];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // zero the spread grids of every window (npair grids each)
 
@@ -145,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(const WinDev *__restrict__ wi
         const int orig = w.perm[j];
 #pragma unroll
         for (int i = 0; i < RB; ++i)
-            v[i] = (act && i < nr) ? (real)pio.V[orig + (int64_t)(r0 + i) * pio.ldv] : real(0);
+            v[i] = (act && i < nr) ? ((const real *)pio.Vp)[orig * pio.ldvp + r0 + i] : real(0);
         wave_sync();
         if (act) {
             const int lx = bc[0] - ox0;
@@ -259,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
     const real *coords = (const real *)w.coords;
     const int W = w.W, m = w.m;
     const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
-    double *dst = w.Yw + ((int64_t)o * w.Rcap + r0) * w.N;
+    double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0;
 
     for (int base = wave * 4; base < ch.count; base += 16) {
         const int p = base + grp;
@@ -330,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
 #pragma unroll
             for (int i = 0; i < RB; ++i)
                 if (i == g && i < nr)
-                    dst[(int64_t)i * w.N + orig] = (double)acc[i];
+                    dst[(int64_t)orig * w.Rcap + i] = (double)acc[i];
         }
         wave_sync();
     }
@@ -591,23 +623,56 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
 
 __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
 {
+    // Tiles of 64 points x 16 RHS: the window products (point-major) are read
+    // row by row into LDS and written out column by column, so that both the
+    // reads and the writes of the caller's column-major matrices are coalesced.
+    __shared__ double tile[64][17];
     const ProbDev p = get_prob(io, blockIdx.y);
-    const int64_t total = p.N * (int64_t)R;
-    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
-        const int64_t r = e / p.N, i = e - r * p.N;
-        double y = 0.0;
-        for (int wi = p.wbeg; wi < p.wend; ++wi) {
-            const WinDev &w = wins[wi];
-            const double kv = w.Yw[r * w.N + i];
-            y += w.sig2 * kv;
-            const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
-            if ((mode & 2) && p.dYs)
-                p.dYs[blk + i + r * p.ldy] = w.dsig * kv;
-            if ((mode & 4) && p.dYl)
-                p.dYl[blk + i + r * p.ldy] = w.der_scale * w.Yw[(w.Rcap + r) * w.N + i];
+    const int t = threadIdx.x, il = t & 63, rq = t >> 6;
+    for (int64_t i0 = blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
+        const int64_t i = i0 + il;
+        const bool own = i < p.N;
+        for (int r0 = 0; r0 < R; r0 += 16) {
+            const int nr = min(16, R - r0);
+            double y[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int wi = p.wbeg; wi < p.wend; ++wi) {
+                const WinDev &w = wins[wi];
+                const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
+                const int nout = (mode & 4) && p.dYl ? 2 : 1;
+                for (int o = 0; o < nout; ++o) {
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int e = t + kBlock * k, pl = e >> 4, rr = e & 15;
+                        const int64_t ip = i0 + pl;
+                        tile[pl][rr] = (ip < p.N && rr < nr) ? w.Yw[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr] : 0.0;
+                    }
+                    __syncthreads();
+                    if (!own)
+                        continue;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int rr = rq + 4 * k;
+                        if (rr >= nr)
+                            continue;
+                        const double v = tile[il][rr];
+                        const int64_t at = i + (int64_t)(r0 + rr) * p.ldy;
+                        if (o == 0) {
+                            y[k] += w.sig2 * v;
+                            if ((mode & 2) && p.dYs)
+                                p.dYs[blk + at] = w.dsig * v;
+                        } else {
+                            p.dYl[blk + at] = w.der_scale * v;
+                        }
+                    }
+                }
+            }
+            if ((mode & 1) && p.Y && own)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (rq + 4 * k < nr)
+                        p.Y[i + (int64_t)(r0 + rq + 4 * k) * p.ldy] = y[k];
         }
-        if ((mode & 1) && p.Y)
-            p.Y[i + r * p.ldy] = y;
     }
 }
 
@@ -993,6 +1058,30 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     }
     E.ws_bytes = bytes;
     E.yw_bytes = ybytes;
+    // point-major copy of the right-hand sides of every problem
+    {
+        int64_t packN = 0;
+        for (const Plan *pl : E.plans)
+            packN += pl->N;
+        const int64_t ld = (rcap + 15) / 16 * 16;
+        const int64_t vb = std::max<int64_t>(packN * ld * (int64_t)real_size(E.precision), 256);
+        free_dev(E.vpack);
+        E.vpack = nullptr;
+        e = hipMalloc(&E.vpack, vb);
+        if (e != hipSuccess) {
+            set_error("right-hand side staging allocation failed");
+            return ADDK_ERR_OOM;
+        }
+        E.vpack_bytes = vb;
+        E.vpack_ld = ld;
+        E.ws_bytes += vb;
+        int64_t off = 0;
+        for (size_t p = 0; p < E.probs.size(); ++p) {
+            E.probs[p].Vp = (const char *)E.vpack + off * real_size(E.precision);
+            E.probs[p].ldvp = ld;
+            off += E.probs[p].N * ld;
+        }
+    }
     // per-item blocks of the matrix-core dense spread: items x RHS blocks x (2m)^3 x 16
     for (int wi = 0; wi < 2; ++wi) {
         const int W = wi == 0 ? 8 : 12;
@@ -1126,6 +1215,11 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
     {
         StageTimer t(E, PS_ZERO, st);
         hipLaunchKernelGGL(k_zero_grids<real>, dim3(64, nw), dim3(kBlock), 0, st, E.d_wins, npair);
+        int64_t maxN = io.table ? 0 : io.single.N;
+        for (const ProbDev &p : E.probs)
+            maxN = std::max(maxN, p.N);
+        const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((maxN + 63) / 64, 16384));
+        hipLaunchKernelGGL(k_pack_v<real>, dim3(bx, io.table ? E.nprob : 1), dim3(kBlock), 0, st, io, R);
     }
     for (int d = 1; d <= 3; ++d) {
         if (!E.nchunks[d])
@@ -1218,6 +1312,10 @@ addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_
         return s;
     const int modes_sel = vmodes_only ? 1 : (store_gmodes ? 2 : 0);
     const int no = vmodes_only ? 0 : nout;
+    if (!io.table) {
+        io.single.Vp = E.vpack;
+        io.single.ldvp = E.vpack_ld;
+    }
     if (E.precision == ADDK_FP32)
         return run_t<float>(E, R, no, modes_sel, !vmodes_only, io, st);
     return run_t<double>(E, R, no, modes_sel, !vmodes_only, io, st);
@@ -1232,10 +1330,9 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
         maxN = std::max(maxN, p.N);
     if (!io.table)
         maxN = io.single.N;
-    const int64_t work = maxN * R;
-    if (work == 0)
+    if (maxN == 0 || R == 0)
         return ADDK_OK;
-    const int bx = (int)std::min<int64_t>((work + kBlock - 1) / kBlock, 4096);
+    const int bx = (int)std::min<int64_t>((maxN + 63) / 64, 16384);
     const int ny = io.table ? E.nprob : 1;
     StageTimer t(E, PS_COMBINE, st);
     hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
 
     if (mrow >= nr)
         return;
-    double *dst = w.Yw + ((int64_t)o * w.Rcap + r0 + mrow) * w.N;
+    double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (g >= nmine)
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
         for (int i = 0; i < 4; ++i) {
             const int p = (wave + 4 * g) * 16 + 4 * q + i;
             if (p < it.count)
-                dst[w.perm[it.start + p]] = (double)acc[g][i];
+                dst[(int64_t)w.perm[it.start + p] * w.Rcap] = (double)acc[g][i];
         }
     }
 }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             const int e = t + k * kBlock;  // e < PB * 16
             const int p = e >> 4, i = e & 15;
             const int r = r0 + i;
-            pvv[k] = (p < np && r < R) ? (float)pio.V[w.perm[it.start + p0 + p] + (int64_t)r * pio.ldv] : 0.f;
+            pvv[k] = (p < np && r < R) ? ((const float *)pio.Vp)[(int64_t)w.perm[it.start + p0 + p] * pio.ldvp + r] : 0.f;
         }
     };
     auto store_raw = [&](Round &d, int p0) {
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__res
             __syncthreads();
         }
         if (mrow < nr) {
-            double *dst = w.Yw + ((int64_t)o * w.Rcap + r0 + mrow) * w.N;
+            double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 if (g >= nmine)
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__res
                 for (int i = 0; i < 4; ++i) {
                     const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
                     if (p < ch.count)
-                        dst[w.perm[ch.start + p]] = (double)acc[g][i];
+                        dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = (double)acc[g][i];
                 }
             }
         }

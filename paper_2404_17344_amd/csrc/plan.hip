@@ -772,6 +772,40 @@ addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, u
     return ADDK_OK;
 }
 
+addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, double oversampling, double tol,
+                          int32_t *n, double *err_estimate)
+{
+    if (!n || !(L >= 0.0) || !std::isfinite(L) || !(ell > 0.0) || !std::isfinite(ell) || m < 2 || m > kMaxW / 2 ||
+        !(oversampling > 1.0) || !std::isfinite(oversampling) || !(tol > 0.0) ||
+        (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12))
+        return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n: bad argument");
+    // Candidates: even n whose oversampled grid round(sigma n) is a power of two
+    // in [16, 128] with room for the window; the first (smallest, cheapest) one
+    // whose a-priori estimate meets tol and whose data box fits the torus wins.
+    double best_err = INFINITY;
+    for (int c = 4; c < kMaxNos; c += 2) {
+        const long nos = std::lround(oversampling * c);
+        if (nos < 16 || nos > kMaxNos || (nos & (nos - 1)) || nos <= c || 4 * m > nos)
+            continue;
+        const double T = torus_period(kernel, L, ell, c, 0, 1);
+        const double eta = M_PI * c * ell / (std::sqrt(2.0) * T);
+        if (eta < 1.0)
+            continue;
+        if (L / T * (double)nos + 2.0 * m + 4.0 > (double)nos)
+            continue;
+        const double est = error_estimate(kernel, L, T, ell, c, m, (double)nos / c);
+        best_err = std::min(best_err, est);
+        if (est <= tol) {
+            *n = c;
+            if (err_estimate)
+                *err_estimate = est;
+            return ADDK_OK;
+        }
+    }
+    return fail(ADDK_ERR_ACCURACY, "addk_choose_n: no supported n reaches the tolerance (best estimate " +
+                                       std::to_string(best_err) + "; increase m or l)");
+}
+
 addk_status addk_window_ft(int32_t m, int32_t n_os, double oversampling, double k, double *value)
 {
     if (!value || m < 1 || n_os < 2 || !(oversampling > 1.0))

@@ -96,3 +96,33 @@ def test_header_documents_every_entry_point():
     for name in ["addk_plan_create", "addk_matvec", "addk_dmatvec", "addk_vjp", "addk_batch_create"]:
         i = header.index(name + "(")
         assert "*/" in header[max(0, i - 1500):i], name  # a comment block precedes the declaration
+
+
+@pytest.mark.parametrize("ell,tol,d", [(0.1, 1e-5, 2), (0.2, 1e-9, 2), (0.1, 1e-8, 1), (0.05, 1e-6, 1)])
+def test_choose_n_meets_tolerance_on_the_trigonometric_sum(ell, tol, d):
+    """The bandwidth picked for a tolerance makes the Fourier part of the method
+    (the exact trigonometric sum of eq. (6), no window error) accurate to that
+    tolerance against the FP64 direct sum, on a small uniform window."""
+    import paper_2404_17344_amd as A
+    from oracle.direct import oracle_direct
+    _lib()
+    rng = np.random.default_rng(5)
+    N = 300
+    X = rng.uniform(-0.25, 0.25, size=(N, d))
+    V = rng.standard_normal((N, 1))
+    L = float((X.max(axis=0) - X.min(axis=0)).max())
+    n, est = A.choose_n(F.GAUSSIAN, L, ell, m=6, oversampling=2.0, tol=tol)
+    assert n % 2 == 0 and est <= tol
+    assert A.choose_n_for(X, [list(range(d))], [ell], m=6, tol=tol) == n
+    Y = F.fast_sum_oracle(X, [list(range(d))], F.GAUSSIAN, [ell], [1.0], V, n)
+    Yd = oracle_direct(X, [list(range(d))], F.GAUSSIAN, [ell], [1.0], V)
+    assert np.linalg.norm(Y - Yd) / np.linalg.norm(Yd) <= tol
+
+
+def test_choose_n_refuses_unreachable_tolerance():
+    import paper_2404_17344_amd as A
+    _lib()
+    with pytest.raises(A.AddkError):
+        A.choose_n(F.GAUSSIAN, 0.5, 0.01, m=6, oversampling=2.0, tol=1e-5)
+    with pytest.raises(A.AddkError):
+        A.choose_n(F.GAUSSIAN, 0.5, 0.1, m=2, oversampling=2.0, tol=1e-12)

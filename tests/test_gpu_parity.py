@@ -164,9 +164,21 @@ def test_matrix_core_kernels_match_vector_kernels(A, m, R):
     Ym, dlm, _ = pm.dmatvec(torch.from_numpy(V).cuda())
     Yv, dlv, _ = mk(matrix_cores=False).dmatvec(torch.from_numpy(V).cuda())
     Yt, dlt, _ = mk(dense_kernels=False).dmatvec(torch.from_numpy(V).cuda())
+    Y64, dl64, _ = A.Plan(X, [[0, 1, 2]], [0.1], [1.0], n=32, m=m, precision="fp64").dmatvec(
+        torch.from_numpy(V).cuda())
     assert pm.query()["dense_points"] > 20000
+    # Each FP32 variant carries its own rounding error.  This data set is a tight
+    # cluster (up to ~2e3 points per grid cell, random-sign RHS), where FP32 sums
+    # of n terms lose about eps32 * sqrt(n) ~ 1e-5 relative: every variant is held
+    # to 2e-5 against the FP64 path and any two of them to 60% of that.  The
+    # workload-shaped cases are held to 1e-5 elsewhere.
+    tol = 2e-5
+    for a in [Ym, Yv, Yt]:
+        assert relerr(a.cpu().numpy(), Y64.cpu().numpy()) < tol
+    for a in [dlm, dlv, dlt]:
+        assert relerr(a[0].cpu().numpy(), dl64[0].cpu().numpy()) < tol
     for a, b in [(Ym, Yv), (Ym, Yt), (dlm[0], dlv[0]), (dlm[0], dlt[0])]:
-        assert relerr(a.cpu().numpy(), b.cpu().numpy()) < 3e-6
+        assert relerr(a.cpu().numpy(), b.cpu().numpy()) < 0.6 * tol
     rows = np.arange(0, X.shape[0], 61)
     Yo = oracle_direct(X, [[0, 1, 2]], WL.GAUSSIAN, [0.1], [1.0], V, rows=rows)
     assert relerr(Ym.cpu().numpy()[rows], Yo) < (1e-5 if m == 6 else 2e-5)
