@@ -44,12 +44,15 @@ __device__ __forceinline__ void unpack_cell_m(int packed, int &bx, int &by, int 
 
 __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
 
-// Products of one z-slab for the first NG point groups of a wave, with the NG
-// accumulator chains interleaved so that one B fragment feeds NG MFMAs.
-template <int SW, int NT, int SX, int NG>
-__device__ __forceinline__ void slab_products(f4 (&acc)[4], const float (&wxq)[4][NT], const float (&wy)[4][SW],
-                                              const float (&wz)[4], const float (*sl)[16], int ny, int q, int mrow)
+// Products of one z-slab for NG point groups and NO outputs (kernel and
+// derivative-kernel grids).  One A fragment (the weights of 16 points at 4
+// taps) feeds NO MFMAs and one B fragment (16 RHS at 4 taps) feeds NG MFMAs;
+// the NG * NO accumulator chains are independent.
+template <int SW, int NT, int SX, int NG, int NO>
+__device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&wxq)[NG][NT], const float (&wy)[NG][SW],
+                                              const float (&wz)[NG], const float (*sl)[16], int ny, int q, int mrow)
 {
+    constexpr int C = SW * SX;  // cells of one output's slab
 #pragma unroll
     for (int oy = 0; oy < SW; ++oy) {
         if (oy >= ny)
@@ -60,62 +63,116 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[4], const float (&wxq)[4
             wyz[g] = wy[g][oy] * wz[g];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const float b = sl[oy * SX + 4 * t + q][mrow];
+            float b[NO];
 #pragma unroll
-            for (int g = 0; g < NG; ++g)
-                acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(wyz[g] * wxq[g][t], b, acc[g], 0, 0, 0);
+            for (int o = 0; o < NO; ++o)
+                b[o] = sl[o * C + oy * SX + 4 * t + q][mrow];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const float a = wyz[g] * wxq[g][t];
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    acc[o][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[o], acc[o][g], 0, 0, 0);
+            }
         }
     }
 }
 
-template <int SW, int NT, int SX>
-__device__ __forceinline__ void slab_products_n(int ng, f4 (&acc)[4], const float (&wxq)[4][NT],
-                                                const float (&wy)[4][SW], const float (&wz)[4], const float (*sl)[16],
-                                                int ny, int q, int mrow)
+// Stream the z-slabs of an (SX x SW x nz) box of NO output grids, starting at
+// grid cell (x0, y0, z0), through LDS (double buffered, register prefetch) and
+// accumulate the products of the wave's NG point groups.  Cells outside the
+// window's grid box read as zero.  Every thread of the block calls this with
+// the same nz, so the barriers inside match.
+template <int SW, int SX, int NT, int NG, int NO>
+__device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
+                                             int y0, int z0, int sx, int sy, int nz, f4 (&acc)[NO][NG],
+                                             const float (&wxq)[NG][NT], const float (&wy)[NG][SW],
+                                             const float (&uzr)[NG], const int (&lbz)[NG], bool zmask)
 {
-    switch (ng) {
-    case 1: slab_products<SW, NT, SX, 1>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
-    case 2: slab_products<SW, NT, SX, 2>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
-    case 3: slab_products<SW, NT, SX, 3>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
-    case 4: slab_products<SW, NT, SX, 4>(acc, wxq, wy, wz, sl, ny, q, mrow); break;
-    default: break;
+    constexpr int C = SW * SX;
+    constexpr int SL = (8 * C + kBlock - 1) / kBlock;  // complex values per thread per slab and output
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 4, mrow = lane & 15;
+    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    const float *H = (const float *)w.H;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    const int p0 = r0 >> 1;
+    const int np = (nr + 1) >> 1;
+    float2 pre[NO][SL];
+    auto load = [&](int oz) {
+        const int gz = z0 + oz;
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int idx = threadIdx.x + k * kBlock;
+                const int pi = idx / C, c = idx - pi * C;
+                const int ox = c % SX, oy = c / SX;
+                const int gx = x0 + ox, gy = y0 + oy;
+                float2 v = {0.f, 0.f};
+                if (idx < 8 * C && pi < np && ox < sx && oy < sy && gx < ex && gy < ey && gz < ez) {
+                    const int64_t off =
+                        ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
+                    v = *(const float2 *)(H + off);
+                }
+                pre[o][k] = v;
+            }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+                const int idx = threadIdx.x + k * kBlock;
+                if (idx < 8 * C) {
+                    const int pi = idx / C, c = idx - pi * C;
+                    slab[buf][o][c][2 * pi] = pre[o][k].x;
+                    slab[buf][o][c][2 * pi + 1] = (2 * pi + 1 < nr) ? pre[o][k].y : 0.f;
+                }
+            }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int oz = 0; oz < nz; ++oz) {
+        if (oz + 1 < nz)
+            load(oz + 1);  // in flight during this slab's products
+        float wz[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const bool in = !zmask || (unsigned)(oz - lbz[g]) < (unsigned)w.W;
+            wz[g] = in ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
+        }
+        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wy, wz, &slab[oz & 1][0][0], sy, q, mrow);
+        if (oz + 1 < nz)
+            store((oz + 1) & 1);
+        __syncthreads();
     }
 }
 
-// ---------------------------------------------------------------------------
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                        int R)
+// One dense item: every wave takes NG of the item's 16-point groups (group
+// wave + 4 g); groups past the item's end carry zero weights.
+template <int W, int NO, int NG>
+__device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &it, int r0, int nr,
+                                                  float (*slab)[NO][W * W][16])
 {
-    constexpr int WW = W * W;
     constexpr int NT = W / 4;  // K steps per x row
-    __shared__ __align__(16) float slab[2][WW][16];
-
-    const Chunk it = items[blockIdx.x];
-    const WinDev &w = wins[it.win];
-    const int r0 = blockIdx.y * 16;
-    if (r0 >= R)
-        return;
-    const int o = blockIdx.z;
-    const int nr = min(16, R - r0);
     int bx, by, bz;
     unpack_cell_m(it.tile, bx, by, bz);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
     const float *coords = (const float *)w.coords;
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-
-    // the item's 16-point groups are dealt round-robin to the four waves
-    const int ngrp = (it.count + 15) >> 4;
-    const int nmine = ngrp > wave ? (ngrp - wave + 3) >> 2 : 0;
-    float wxq[4][NT], wy[4][W], uz[4];
+    float wxq[NG][NT], wy[NG][W], uz[NG];
+    int lbz[NG];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < NG; ++g) {
         const int p = (wave + 4 * g) * 16 + mrow;
-        const bool act = g < nmine && p < it.count;
+        const bool act = p < it.count;
         const int j = it.start + (act ? p : 0);
         const float ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
+        lbz[g] = 0;
 #pragma unroll
         for (int t = 0; t < NT; ++t)
             wxq[g][t] = act ? kb_psi_f(ux - (float)(bx + 4 * t + q), mm, kb, ie) : 0.f;
@@ -123,79 +180,51 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
         for (int k = 0; k < W; ++k)
             wy[g][k] = kb_psi_f(uy - (float)(by + k), mm, kb, ie);
     }
-
-    const float *H = (const float *)w.H;
-    const int ex = w.ext[0], ey = w.ext[1];
-    const int p0 = r0 >> 1;
-    const int np = (nr + 1) >> 1;
-    constexpr int SL = (8 * WW + kBlock - 1) / kBlock;  // complex values per thread per slab
-    float2 pre[SL];
-    // load slab oz (8 complex grids x 2m x 2m cells) into registers
-    auto load = [&](int oz) {
+    f4 acc[NO][NG];
 #pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int idx = threadIdx.x + k * kBlock;
-            const int pi = idx / WW, c = idx - pi * WW;
-            float2 v = {0.f, 0.f};
-            if (idx < 8 * WW && pi < np) {
-                const int ox = c % W, oy = c / W;
-                const int64_t off =
-                    ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)(bz + oz) * ey + by + oy) * ex + bx + ox) *
-                    2;
-                v = *(const float2 *)(H + off);
-            }
-            pre[k] = v;
-        }
-    };
-    auto store = [&](int buf) {
+    for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int idx = threadIdx.x + k * kBlock;
-            if (idx < 8 * WW) {
-                const int pi = idx / WW, c = idx - pi * WW;
-                slab[buf][c][2 * pi] = pre[k].x;
-                slab[buf][c][2 * pi + 1] = (2 * pi + 1 < nr) ? pre[k].y : 0.f;
-            }
-        }
-    };
-
-    f4 acc[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-        acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int oz = 0; oz < W; ++oz) {
-        if (oz + 1 < W)
-            load(oz + 1);  // in flight during this slab's products
-        const int cur = oz & 1;
-        if (nmine > 0) {
-            float wz[4];
-#pragma unroll
-            for (int g = 0; g < 4; ++g)
-                wz[g] = kb_psi_f(uz[g] - (float)(bz + oz), mm, kb, ie);
-            slab_products_n<W, NT, W>(nmine, acc, wxq, wy, wz, slab[cur], W, q, mrow);
-        }
-        if (oz + 1 < W)
-            store((oz + 1) & 1);
-        __syncthreads();
-    }
-
+        for (int g = 0; g < NG; ++g)
+            acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
+    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W, acc, wxq, wy, uz, lbz, false);
     if (mrow >= nr)
         return;
-    double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        if (g >= nmine)
-            break;
+    for (int o = 0; o < NO; ++o) {
+        double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = (wave + 4 * g) * 16 + 4 * q + i;
-            if (p < it.count)
-                dst[(int64_t)w.perm[it.start + p] * w.Rcap] = (double)acc[g][i];
-        }
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = (wave + 4 * g) * 16 + 4 * q + i;
+                if (p < it.count)
+                    dst[(int64_t)w.perm[it.start + p] * w.Rcap] = (double)acc[o][g][i];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense interp: one block per dense item (<= 256 points) and 16 RHS, NO
+// outputs at once.  The number of groups per wave is uniform in the block, so
+// the dispatch below is a uniform branch and every wave runs the same slab
+// loop (and barriers).
+template <int W, int NO>
+__global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
+                                                        int R)
+{
+    __shared__ __align__(16) float slab[2][NO][W * W][16];
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    const int r0 = blockIdx.y * 16;
+    if (r0 >= R)
+        return;
+    const int nr = min(16, R - r0);
+    const int ng = (((it.count + 15) >> 4) + 3) >> 2;
+    switch (ng) {
+    case 1: interp_dense_item<W, NO, 1>(w, it, r0, nr, slab); break;
+    case 2: interp_dense_item<W, NO, 2>(w, it, r0, nr, slab); break;
+    case 3: interp_dense_item<W, NO, 3>(w, it, r0, nr, slab); break;
+    default: interp_dense_item<W, NO, 4>(w, it, r0, nr, slab); break;
     }
 }
 
@@ -428,20 +457,72 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
 // interp for the sparsely populated cells of one tile on the matrix cores: the
 // tile's sub-grid (tile + window halo, x padded to 16) plays the role of the
 // dense cell's window block; weights outside a point's support are zero.
-template <int W>
+// One pass (<= 256 points) of a sparse tile chunk on the tile's sub-grid.
+template <int W, int NO, int NG>
+__device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &ch, int pass, int r0, int nr, int x0,
+                                                 int y0, int z0, float (*slab)[NO][(3 + W) * 16][16])
+{
+    constexpr int SX = 16, SY = 3 + W;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, mrow = lane & 15;
+    const float *coords = (const float *)w.coords;
+    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    float wxq[NG][4], wys[NG][SY], uz[NG];
+    int lbz[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int p = pass + (wave + 4 * g) * 16 + mrow;
+        const bool act = p < ch.count;
+        const int j = ch.start + (act ? p : 0);
+        const float ux = coords[j], uy = coords[w.N + j];
+        uz[g] = coords[2 * w.N + j];
+        const int lx = (int)floorf(ux) - w.m + 1 - x0, ly = (int)floorf(uy) - w.m + 1 - y0;
+        lbz[g] = (int)floorf(uz[g]) - w.m + 1 - z0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ox = 4 * t + q;
+            wxq[g][t] = (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_f(ux - (float)(x0 + ox), mm, kb, ie) : 0.f;
+        }
+#pragma unroll
+        for (int oy = 0; oy < SY; ++oy)
+            wys[g][oy] = ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+    }
+    f4 acc[NO][NG];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
+    stream_slabs<SY, SX, 4, NG, NO>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wys, uz, lbz, true);
+    if (mrow >= nr)
+        return;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
+                if (p < ch.count)
+                    dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = (double)acc[o][g][i];
+            }
+    }
+}
+
+// Sparse-tile interp on the matrix cores: the points of a tile chunk (any base
+// cells of the tile) against the tile's (4 + 2m - 1)^3 sub-grid, taken as one
+// super-cell with x padded to 16; weights outside a point's support are zero.
+template <int W, int NO>
 __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
                                                              const Chunk *__restrict__ chunks, int R)
 {
-    constexpr int SX = 16;         // padded sub-grid x extent (tb = 4, 2m <= 12)
-    constexpr int SY = 3 + W;      // maximal sub-grid y/z extent (tb + 2m - 1)
-    __shared__ __align__(16) float slab[2][SY * SX][16];
-
+    __shared__ __align__(16) float slab[2][NO][(3 + W) * 16][16];
     const Chunk ch = chunks[blockIdx.x];
     const WinDev &w = wins[ch.win];
     const int r0 = blockIdx.y * 16;
     if (r0 >= R)
         return;
-    const int o = blockIdx.z;
     const int nr = min(16, R - r0);
     int tl = ch.tile;
     const int tx = tl % w.ntile[0];
@@ -449,108 +530,16 @@ __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__res
     const int ty = tl % w.ntile[1];
     const int tz = tl / w.ntile[1];
     const int x0 = tx * w.tb[0], y0 = ty * w.tb[1], z0 = tz * w.tb[2];
-    const int S0 = w.S[0], S1 = w.S[1], S2 = w.S[2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = lane >> 4, mrow = lane & 15;
-    const float *coords = (const float *)w.coords;
-    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-    const float *H = (const float *)w.H;
-    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
-    const int p0 = r0 >> 1;
-    const int np = (nr + 1) >> 1;
-    constexpr int SL = (8 * SY * SX + kBlock - 1) / kBlock;
-    float2 pre[SL];
-    auto load = [&](int oz) {
-#pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int idx = threadIdx.x + k * kBlock;
-            const int pi = idx / (SY * SX), c = idx - pi * (SY * SX);
-            const int ox = c % SX, oy = c / SX;
-            float2 v = {0.f, 0.f};
-            const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
-            if (idx < 8 * SY * SX && pi < np && ox < S0 && oy < S1 && gx < ex && gy < ey && gz < ez) {
-                const int64_t off = ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
-                v = *(const float2 *)(H + off);
-            }
-            pre[k] = v;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int k = 0; k < SL; ++k) {
-            const int idx = threadIdx.x + k * kBlock;
-            if (idx < 8 * SY * SX) {
-                const int pi = idx / (SY * SX), c = idx - pi * (SY * SX);
-                slab[buf][c][2 * pi] = pre[k].x;
-                slab[buf][c][2 * pi + 1] = (2 * pi + 1 < nr) ? pre[k].y : 0.f;
-            }
-        }
-    };
-
     for (int pass = 0; pass < ch.count; pass += 256) {
-        // window values of the lane's point (A row) on the sub-grid; the pass's
-        // 16-point groups are dealt round-robin to the four waves
         const int npass = min(256, ch.count - pass);
-        const int ngrp = (npass + 15) >> 4;
-        const int nmine = ngrp > wave ? (ngrp - wave + 3) >> 2 : 0;
-        float wxq[4][4], wys[4][SY], uz[4];
-        int lbz[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int p = pass + (wave + 4 * g) * 16 + mrow;
-            const bool act = g < nmine && p < ch.count;
-            const int j = ch.start + (act ? p : 0);
-            const float ux = coords[j], uy = coords[w.N + j];
-            uz[g] = coords[2 * w.N + j];
-            const int lx = (int)floorf(ux) - w.m + 1 - x0, ly = (int)floorf(uy) - w.m + 1 - y0;
-            lbz[g] = (int)floorf(uz[g]) - w.m + 1 - z0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int ox = 4 * t + q;
-                wxq[g][t] = (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_f(ux - (float)(x0 + ox), mm, kb, ie) : 0.f;
-            }
-#pragma unroll
-            for (int oy = 0; oy < SY; ++oy)
-                wys[g][oy] = ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+        const int ng = (((npass + 15) >> 4) + 3) >> 2;
+        switch (ng) {
+        case 1: interp_tile_pass<W, NO, 1>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
+        case 2: interp_tile_pass<W, NO, 2>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
+        case 3: interp_tile_pass<W, NO, 3>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
+        default: interp_tile_pass<W, NO, 4>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
         }
-        f4 acc[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-            acc[g] = f4{0.f, 0.f, 0.f, 0.f};
-
-        load(0);
-        store(0);
-        __syncthreads();
-        for (int oz = 0; oz < S2; ++oz) {
-            if (oz + 1 < S2)
-                load(oz + 1);
-            const int cur = oz & 1;
-            if (nmine > 0) {
-                float wz[4];
-#pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    wz[g] = ((unsigned)(oz - lbz[g]) < (unsigned)W) ? kb_psi_f(uz[g] - (float)(z0 + oz), mm, kb, ie)
-                                                                    : 0.f;
-                slab_products_n<SY, 4, SX>(nmine, acc, wxq, wys, wz, slab[cur], S1, q, mrow);
-            }
-            if (oz + 1 < S2)
-                store((oz + 1) & 1);
-            __syncthreads();
-        }
-        if (mrow < nr) {
-            double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                if (g >= nmine)
-                    break;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
-                    if (p < ch.count)
-                        dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = (double)acc[g][i];
-                }
-            }
-        }
+        __syncthreads();  // the next pass overwrites the slab buffers
     }
 }
 
@@ -561,11 +550,16 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
 {
     if (E.precision != ADDK_FP32 || !E.ndense[3][wi])
         return false;
-    dim3 grid(E.ndense[3][wi], (R + 15) / 16, nout);
-    if (wi == 0)
-        hipLaunchKernelGGL(k_interp_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], R);
+    dim3 grid(E.ndense[3][wi], (R + 15) / 16);
+    const Chunk *items = E.d_dense[3][wi];
+    if (wi == 0 && nout == 1)
+        hipLaunchKernelGGL((k_interp_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+    else if (wi == 0)
+        hipLaunchKernelGGL((k_interp_mfma<8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+    else if (nout == 1)
+        hipLaunchKernelGGL((k_interp_mfma<12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     else
-        hipLaunchKernelGGL(k_interp_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], R);
+        hipLaunchKernelGGL((k_interp_mfma<12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     return true;
 }
 
@@ -604,11 +598,16 @@ bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st)
     const int W = E.tile_w[3];
     if (E.precision != ADDK_FP32 || !E.nchunks[3] || (W != 8 && W != 12))
         return false;
-    dim3 grid(E.nchunks[3], (R + 15) / 16, nout);
-    if (W == 8)
-        hipLaunchKernelGGL(k_interp_tile_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_chunks[3], R);
+    dim3 grid(E.nchunks[3], (R + 15) / 16);
+    const Chunk *ch = E.d_chunks[3];
+    if (W == 8 && nout == 1)
+        hipLaunchKernelGGL((k_interp_tile_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
+    else if (W == 8)
+        hipLaunchKernelGGL((k_interp_tile_mfma<8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
+    else if (nout == 1)
+        hipLaunchKernelGGL((k_interp_tile_mfma<12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
     else
-        hipLaunchKernelGGL(k_interp_tile_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_chunks[3], R);
+        hipLaunchKernelGGL((k_interp_tile_mfma<12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
     return true;
 }
 
