@@ -152,6 +152,16 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv,
 addk_status addk_plan_update_params(addk_plan plan, const double *ell, const double *sigma,
                                     void *stream);
 
+/*
+ * Kernel-variant knobs (FP32 plans): which stages run on the matrix cores
+ * (v_mfma_f32_16x16x4f32) instead of the vector ALUs.  Both variants compute
+ * the same products; they differ in speed and in FP32 summation order.
+ */
+#define ADDK_KNOB_SPREAD_MFMA 1u       /* dense-cell spreading (d = 3)      */
+#define ADDK_KNOB_INTERP_DENSE_MFMA 2u /* dense-cell interpolation (d = 3)  */
+#define ADDK_KNOB_INTERP_TILE_MFMA 4u  /* sparse-tile interpolation (d = 3) */
+#define ADDK_KNOB_ALL_MFMA 7u
+
 /* Plan facts.  Arrays are host memory with room for P entries (any may be NULL). */
 typedef struct {
     int64_t N;
@@ -161,6 +171,8 @@ typedef struct {
     double err_estimate;        /* a-priori relative error estimate (max over windows) */
     int64_t dense_points;       /* point-window pairs handled by the dense-cell kernels */
     int64_t tile_points;        /* point-window pairs handled by the tile kernels       */
+    uint32_t knobs;             /* ADDK_KNOB_* in effect                                 */
+    int32_t tuned;              /* 1 once addk_plan_autotune chose the knobs             */
 } addk_plan_info;
 addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_period,
                             double *eta, int32_t *window_dim);
@@ -181,6 +193,19 @@ addk_status addk_plan_destroy(addk_plan plan);
 addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *plans, int32_t R,
                               const double *const *V, const int64_t *ldv,
                               double *const *Y, const int64_t *ldy, void *stream);
+/*
+ * Autotuner.  Times every applicable combination of ADDK_KNOB_* on this plan
+ * (products of R right-hand sides; nout = 1: addk_matvec, 2: addk_dmatvec
+ * with K V and dK/dl V) or on this batch (graph replays), `reps` timed runs
+ * each after one warm-up, keeps the fastest combination and returns it in
+ * *knobs (may be NULL).  Temporary inputs are allocated and freed inside.
+ * Synchronous.  FP64 plans have nothing to tune (knobs = 0).
+ * Errors: INVALID_ARG, OOM, HIP.
+ */
+addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs,
+                               void *stream);
+addk_status addk_batch_autotune(addk_batch batch, int32_t reps, uint32_t *knobs, void *stream);
+
 /* Y[p] = K_p V[p] for all p: replays the captured graph on the stream. */
 addk_status addk_batch_launch(addk_batch batch, void *stream);
 /* The same products, launched eagerly (no graph); for comparison and debugging. */

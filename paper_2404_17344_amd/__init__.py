@@ -17,9 +17,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, AddkError,  # noqa: F401
-                   ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK)
+                   ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK, ADDK_KNOB_SPREAD_MFMA,
+                   ADDK_KNOB_INTERP_DENSE_MFMA, ADDK_KNOB_INTERP_TILE_MFMA, ADDK_KNOB_ALL_MFMA)
 
-__all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "KernelMatvec"]
+__all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "choose_n", "choose_n_for",
+           "KernelMatvec"]
 
 _KERNELS = {"gaussian": ADDK_GAUSSIAN, "matern12": ADDK_MATERN12, ADDK_GAUSSIAN: ADDK_GAUSSIAN,
             ADDK_MATERN12: ADDK_MATERN12}
@@ -169,7 +171,15 @@ class Plan:
         return {"N": info.N, "P": info.P, "n": info.n, "m": info.m, "n_os": info.n_os,
                 "precision": info.precision, "kernel": info.kernel, "workspace_bytes": info.workspace_bytes,
                 "err_estimate": info.err_estimate, "T": list(T), "eta": list(eta), "d": list(dims),
-                "dense_points": info.dense_points, "tile_points": info.tile_points}
+                "dense_points": info.dense_points, "tile_points": info.tile_points,
+                "knobs": info.knobs, "tuned": bool(info.tuned)}
+
+    def autotune(self, R: int, nout: int = 1, reps: int = 3, stream=None) -> int:
+        """Time the kernel-variant combinations on this plan and keep the fastest (ADDK_KNOB_* mask)."""
+        k = ctypes.c_uint32()
+        _lib.check(self._lib.addk_plan_autotune(self._h, int(R), int(nout), int(reps), ctypes.byref(k),
+                                                _stream(stream)), "addk_plan_autotune")
+        return k.value
 
     def update_params(self, ell, sigma, stream=None):
         ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))
@@ -262,6 +272,13 @@ class Batch:
 
     def launch(self, stream=None):
         _lib.check(self._lib.addk_batch_launch(self._h, _stream(stream)), "addk_batch_launch")
+
+    def autotune(self, reps: int = 3, stream=None) -> int:
+        """Time the kernel-variant combinations on the graph, keep (and re-capture) the fastest."""
+        k = ctypes.c_uint32()
+        _lib.check(self._lib.addk_batch_autotune(self._h, int(reps), ctypes.byref(k), _stream(stream)),
+                   "addk_batch_autotune")
+        return k.value
 
     def run_eager(self, stream=None):
         _lib.check(self._lib.addk_batch_run_eager(self._h, _stream(stream)), "addk_batch_run_eager")

@@ -31,13 +31,18 @@ ADDK_NO_ACCURACY_CHECK = 4
 ADDK_TILE_KERNELS_ONLY = 8
 ADDK_VECTOR_ALU_ONLY = 16
 ADDK_NSTAGES = 13
+ADDK_KNOB_SPREAD_MFMA = 1
+ADDK_KNOB_INTERP_DENSE_MFMA = 2
+ADDK_KNOB_INTERP_TILE_MFMA = 4
+ADDK_KNOB_ALL_MFMA = 7
 
 
 class AddkPlanInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("P", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("n_os", ctypes.c_int32), ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("err_estimate", ctypes.c_double),
-                ("dense_points", ctypes.c_int64), ("tile_points", ctypes.c_int64)]
+                ("dense_points", ctypes.c_int64), ("tile_points", ctypes.c_int64),
+                ("knobs", ctypes.c_uint32), ("tuned", ctypes.c_int32)]
 
 
 _lib = None
@@ -63,6 +68,8 @@ _SIGS = {
     "addk_batch_create": [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _pi64,
                           ctypes.POINTER(_vp), _pi64, _vp],
     "addk_batch_launch": [_vp, _vp],
+    "addk_plan_autotune": [_vp, _i32, _i32, _i32, ctypes.POINTER(_u32), _vp],
+    "addk_batch_autotune": [_vp, _i32, ctypes.POINTER(_u32), _vp],
     "addk_batch_run_eager": [_vp, _vp],
     "addk_batch_destroy": [_vp],
     "addk_plan_profile": [_vp, _i32],

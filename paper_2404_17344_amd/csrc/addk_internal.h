@@ -138,6 +138,8 @@ struct Engine {
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
     bool no_mfma = false;          // use the vector-ALU dense kernels only
+    uint32_t knobs = ADDK_KNOB_ALL_MFMA;  // matrix-core variant per stage (ADDK_KNOB_*)
+    bool tuned = false;            // knobs chosen by measurement: no R threshold
     int2 *d_dmap[2] = {nullptr, nullptr};        // base-cell maps of all windows (per 2m = 8, 12)
     LineGroup *d_gtiles[2] = {nullptr, nullptr};  // output tiles of the dense block gather
     int ngtiles[2] = {0, 0};
@@ -202,6 +204,7 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
 addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st);
 addk_status engine_upload(Engine &E);
 void engine_free(Engine &E);
+bool use_mfma(const Engine &E, uint32_t knob, int R);
 addk_status engine_profile_read(Engine &E, double *ms, int32_t *count);
 
 // dense.hip

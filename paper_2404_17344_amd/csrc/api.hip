@@ -75,6 +75,83 @@ static addk_status batch_enqueue(Batch &b, hipStream_t st)
     return s;
 }
 
+// (Re)capture the batch's stage sequence into a graph on its private stream.
+static addk_status batch_capture(Batch &b)
+{
+    hipError_t e;
+    if (b.exec) {
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    if (b.graph) {
+        (void)hipGraphDestroy(b.graph);
+        b.graph = nullptr;
+    }
+    e = hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    addk_status s2 = batch_enqueue(b, b.cap_stream);
+    e = hipStreamEndCapture(b.cap_stream, &b.graph);
+    if (s2 != ADDK_OK)
+        return s2;
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGraphInstantiate");
+    return ADDK_OK;
+}
+
+// Time `reps` runs of fn (after one warm-up) on the stream; average ms.
+template <typename Fn>
+static addk_status time_runs(Fn fn, int reps, hipStream_t st, double *ms)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    addk_status s = fn();
+    if (s == ADDK_OK && (e = hipEventRecord(a, st)) != hipSuccess)
+        s = hip_fail(e, "hipEventRecord");
+    for (int r = 0; r < reps && s == ADDK_OK; ++r)
+        s = fn();
+    if (s == ADDK_OK && (e = hipEventRecord(b, st)) != hipSuccess)
+        s = hip_fail(e, "hipEventRecord");
+    if (s == ADDK_OK && (e = hipEventSynchronize(b)) != hipSuccess)
+        s = hip_fail(e, "hipEventSynchronize");
+    float t = 0.f;
+    if (s == ADDK_OK && (e = hipEventElapsedTime(&t, a, b)) != hipSuccess)
+        s = hip_fail(e, "hipEventElapsedTime");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t / std::max(reps, 1);
+    return s;
+}
+
+// Candidate knob sets of an engine: every subset of the matrix-core stages
+// that the engine has work for (others are left on, they have no effect).
+static std::vector<uint32_t> knob_candidates(const Engine &E)
+{
+    if (E.precision != ADDK_FP32 || E.no_mfma)
+        return {0u};
+    bool dense = false, tile = false;
+    for (int wi = 0; wi < 2; ++wi)
+        dense = dense || E.ndense[3][wi] > 0;
+    tile = E.nchunks[3] > 0 && (E.tile_w[3] == 8 || E.tile_w[3] == 12);
+    std::vector<uint32_t> out;
+    for (uint32_t k = 0; k <= ADDK_KNOB_ALL_MFMA; ++k) {
+        if (!dense && (k & (ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA)) !=
+                          (ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA))
+            continue;
+        if (!tile && !(k & ADDK_KNOB_INTERP_TILE_MFMA))
+            continue;
+        out.push_back(k);
+    }
+    return out;
+}
+
 }  // namespace addk
 
 using namespace addk;
@@ -287,24 +364,8 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
         if (e != hipSuccess)
             s = hip_fail(e, "hipStreamCreate");
     }
-    if (s == ADDK_OK) {
-        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess)
-            s = hip_fail(e, "hipStreamBeginCapture");
-        else {
-            addk_status s2 = batch_enqueue(*b, b->cap_stream);
-            e = hipStreamEndCapture(b->cap_stream, &b->graph);
-            if (s2 != ADDK_OK)
-                s = s2;
-            else if (e != hipSuccess)
-                s = hip_fail(e, "hipStreamEndCapture");
-        }
-    }
-    if (s == ADDK_OK) {
-        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess)
-            s = hip_fail(e, "hipGraphInstantiate");
-    }
+    if (s == ADDK_OK)
+        s = batch_capture(*b);
     if (s != ADDK_OK) {
         addk_batch_destroy((addk_batch)b);
         return s;
@@ -312,6 +373,110 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
     (void)stream;
     *out = (addk_batch)b;
     return ADDK_OK;
+}
+
+addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    if (R < 1 || (nout != 1 && nout != 2) || reps < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, "autotune: R >= 1, nout in {1, 2} and reps >= 1 required");
+    Plan &pl = *(Plan *)plan;
+    Engine &E = pl.eng;
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<uint32_t> cand = knob_candidates(E);
+    if (cand.size() <= 1 || pl.N == 0) {
+        E.knobs = cand.empty() ? 0u : cand[0];
+        E.tuned = true;
+        if (knobs)
+            *knobs = E.knobs;
+        return ADDK_OK;
+    }
+    double *V = nullptr, *Y = nullptr, *dl = nullptr;
+    const int64_t n = pl.N * (int64_t)R;
+    hipError_t e = hipMalloc(&V, n * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMalloc(&Y, n * sizeof(double));
+    if (e == hipSuccess && nout == 2)
+        e = hipMalloc(&dl, n * pl.P * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemsetAsync(V, 0, n * sizeof(double), st);  // timing does not depend on the values
+    addk_status s = e == hipSuccess ? ADDK_OK : fail2(ADDK_ERR_OOM, "autotune buffers");
+    const uint32_t saved = E.knobs;
+    const bool saved_tuned = E.tuned;
+    double best = INFINITY;
+    uint32_t best_k = saved;
+    for (size_t c = 0; c < cand.size() && s == ADDK_OK; ++c) {
+        E.knobs = cand[c];
+        E.tuned = true;
+        double ms = 0.0;
+        s = time_runs(
+            [&]() {
+                return nout == 1 ? addk_matvec(plan, R, V, pl.N, Y, pl.N, stream)
+                                 : addk_dmatvec(plan, R, V, pl.N, dl, nullptr, Y, pl.N, stream);
+            },
+            reps, st, &ms);
+        if (s == ADDK_OK && ms < best) {
+            best = ms;
+            best_k = cand[c];
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(V);
+    (void)hipFree(Y);
+    (void)hipFree(dl);
+    if (s != ADDK_OK) {
+        E.knobs = saved;
+        E.tuned = saved_tuned;
+        return s;
+    }
+    E.knobs = best_k;
+    E.tuned = true;
+    if (knobs)
+        *knobs = best_k;
+    return ADDK_OK;
+}
+
+addk_status addk_batch_autotune(addk_batch batch, int32_t reps, uint32_t *knobs, void *stream)
+{
+    if (!batch)
+        return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
+    if (reps < 1)
+        return fail2(ADDK_ERR_INVALID_ARG, "autotune: reps >= 1 required");
+    Batch &b = *(Batch *)batch;
+    Engine &E = b.eng;
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<uint32_t> cand = knob_candidates(E);
+    const uint32_t saved = E.knobs;
+    const bool saved_tuned = E.tuned;
+    double best = INFINITY;
+    uint32_t best_k = saved;
+    addk_status s = ADDK_OK;
+    for (size_t c = 0; c < cand.size() && s == ADDK_OK && cand.size() > 1; ++c) {
+        E.knobs = cand[c];
+        E.tuned = true;
+        s = batch_capture(b);
+        double ms = 0.0;
+        if (s == ADDK_OK)
+            s = time_runs(
+                [&]() {
+                    hipError_t e = hipGraphLaunch(b.exec, st);
+                    return e == hipSuccess ? ADDK_OK : hip_fail(e, "hipGraphLaunch");
+                },
+                reps, st, &ms);
+        if (s == ADDK_OK && ms < best) {
+            best = ms;
+            best_k = cand[c];
+        }
+    }
+    E.knobs = s == ADDK_OK ? (cand.size() > 1 ? best_k : (cand.empty() ? 0u : cand[0])) : saved;
+    E.tuned = s == ADDK_OK ? true : saved_tuned;
+    addk_status s2 = batch_capture(b);  // the graph of the chosen knobs
+    if (s == ADDK_OK)
+        s = s2;
+    if (s == ADDK_OK && knobs)
+        *knobs = E.knobs;
+    return s;
 }
 
 addk_status addk_batch_launch(addk_batch batch, void *stream)

@@ -26,24 +26,27 @@ namespace addk {
 template <typename real>
 __device__ __forceinline__ real kb_psi_d(real z, real m, real b, real inv_e2bm)
 {
-    real s2 = m * m - z * z;
-    s2 = s2 > real(0) ? s2 : real(0);
-    real s = sqrt(s2);
-    s = s > real(1e-6) ? s : real(1e-6);
-    return m * (exp(b * (s - m)) - exp(-b * (s + m))) * inv_e2bm / s;
+    const real z2 = z * z;
+    real s2 = m * m - z2;
+    s2 = s2 > real(1e-12) ? s2 : real(1e-12);
+    const real s = sqrt(s2);
+    return m * exp(-b * z2 / (s + m)) * (real(1) - exp(real(-2) * b * s)) * inv_e2bm / s;
 }
 
-// FP32: hardware exp2 and reciprocal (a few ulp), ample for the FP32 path.
+// FP32: the exponent b (s - m) is formed as -b z^2 / (s + m), which is small
+// and accurate where psi is large; hardware sqrt, exp2 and reciprocal (about
+// 1 ulp each) are ample for the FP32 path.
 template <>
 __device__ __forceinline__ float kb_psi_d<float>(float z, float m, float b, float inv_e2bm)
 {
-    float s2 = m * m - z * z;
-    s2 = s2 > 0.f ? s2 : 0.f;
-    float s = __builtin_sqrtf(s2);
-    s = s > 1e-6f ? s : 1e-6f;
-    const float l2e = 1.4426950408889634f;
-    return m * (__builtin_amdgcn_exp2f(b * (s - m) * l2e) - __builtin_amdgcn_exp2f(-b * (s + m) * l2e)) * inv_e2bm *
-           __builtin_amdgcn_rcpf(s);
+    const float z2 = z * z;
+    float s2 = m * m - z2;
+    s2 = s2 > 1e-12f ? s2 : 1e-12f;
+    const float s = __builtin_amdgcn_sqrtf(s2);
+    const float bl = b * 1.4426950408889634f;
+    const float e1 = __builtin_amdgcn_exp2f(-bl * z2 * __builtin_amdgcn_rcpf(s + m));
+    const float e2 = __builtin_amdgcn_exp2f(-2.f * bl * s);
+    return m * e1 * (1.f - e2) * inv_e2bm * __builtin_amdgcn_rcpf(s);
 }
 
 __device__ __forceinline__ void unpack_cell(int packed, int &bx, int &by, int &bz)

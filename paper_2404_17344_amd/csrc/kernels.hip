@@ -53,15 +53,16 @@ __device__ __forceinline__ void gbl_add(double *p, double v) { unsafeAtomicAdd(p
 
 // Normalised Kaiser-Bessel window in grid units (psi(0) = 1):
 //   psi(z) = (m / sinh(b m)) sinh(b s) / s,  s = sqrt(m^2 - z^2),  |z| <= m,
-// written with exponentials that stay finite in FP32.
+// written as m e^{-b z^2/(s+m)} (1 - e^{-2bs}) / ((1 - e^{-2bm}) s): finite in
+// FP32, with a small (hence accurate) exponent where psi is large.
 template <typename real>
 __device__ __forceinline__ real kb_psi(real z, real m, real b, real inv_e2bm)
 {
-    real s2 = m * m - z * z;
-    s2 = s2 > real(0) ? s2 : real(0);
-    real s = sqrt(s2);
-    s = s > real(1e-6) ? s : real(1e-6);
-    return m * (exp(b * (s - m)) - exp(-b * (s + m))) * inv_e2bm / s;
+    const real z2 = z * z;
+    real s2 = m * m - z2;
+    s2 = s2 > real(1e-12) ? s2 : real(1e-12);
+    const real s = sqrt(s2);
+    return m * exp(-b * z2 / (s + m)) * (real(1) - exp(real(-2) * b * s)) * inv_e2bm / s;
 }
 
 // First tap of a point at grid coordinate u: taps are base .. base + 2m - 1.
@@ -1235,7 +1236,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         for (int wi = 0; wi < 2; ++wi) {
             if (!E.ndense[d][wi])
                 continue;
-            if (d == 3 && R >= kMfmaMinR && !E.no_mfma && E.scratch[wi]) {
+            if (d == 3 && use_mfma(E, ADDK_KNOB_SPREAD_MFMA, R) && E.scratch[wi]) {
                 {
                     StageTimer t(E, PS_SPREAD_DENSE, st);
                     launch_spread_mfma(E, wi, R, io, st);
@@ -1282,7 +1283,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
                 if (!E.nchunks[d])
                     continue;
                 StageTimer t(E, PS_INTERP, st);
-                if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_interp_tile_mfma(E, R, nout, st))
+                if (d == 3 && use_mfma(E, ADDK_KNOB_INTERP_TILE_MFMA, R) && launch_interp_tile_mfma(E, R, nout, st))
                     continue;
                 if (d == 1) launch_interp<real, 1>(E, R, nout, st);
                 if (d == 2) launch_interp<real, 2>(E, R, nout, st);
@@ -1293,7 +1294,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
                     if (!E.ndense[d][wi])
                         continue;
                     StageTimer t(E, PS_INTERP_DENSE, st);
-                    if (d == 3 && R >= kMfmaMinR && !E.no_mfma && launch_interp_mfma(E, wi, R, nout, st))
+                    if (d == 3 && use_mfma(E, ADDK_KNOB_INTERP_DENSE_MFMA, R) && launch_interp_mfma(E, wi, R, nout, st))
                         continue;
                     launch_interp_dense(E, d, wi, R, nout, st);
                 }
@@ -1303,6 +1304,16 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
     if (e != hipSuccess)
         return hip_fail(e, "stage kernel launch");
     return ADDK_OK;
+}
+
+// Matrix-core variant of a stage: off on FP64 engines and with
+// ADDK_VECTOR_ALU_ONLY; otherwise the knob decides, and untuned engines also
+// require enough RHS to fill most of a 16-wide block.
+bool use_mfma(const Engine &E, uint32_t knob, int R)
+{
+    if (E.no_mfma || E.precision != ADDK_FP32 || !(E.knobs & knob))
+        return false;
+    return E.tuned || R >= kMfmaMinR;
 }
 
 addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io, hipStream_t st)

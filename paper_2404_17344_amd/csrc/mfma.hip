@@ -24,15 +24,20 @@ namespace addk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// psi(z) = m sinh(b s) / (sinh(b m) s), s = sqrt(m^2 - z^2), evaluated as
+//   m e^{-b z^2 / (s + m)} (1 - e^{-2 b s}) / ((1 - e^{-2 b m}) s),
+// using b (s - m) = -b z^2 / (s + m): the exponent is then small, and accurate
+// to a few ulp, where psi is large.  Hardware sqrt / exp2 / rcp (about 1 ulp).
 __device__ __forceinline__ float kb_psi_f(float z, float m, float b, float inv_e2bm)
 {
-    float s2 = m * m - z * z;
-    s2 = s2 > 0.f ? s2 : 0.f;
-    float s = __builtin_sqrtf(s2);
-    s = s > 1e-6f ? s : 1e-6f;
-    const float l2e = 1.4426950408889634f;
-    return m * (__builtin_amdgcn_exp2f(b * (s - m) * l2e) - __builtin_amdgcn_exp2f(-b * (s + m) * l2e)) * inv_e2bm *
-           __builtin_amdgcn_rcpf(s);
+    const float z2 = z * z;
+    float s2 = m * m - z2;
+    s2 = s2 > 1e-12f ? s2 : 1e-12f;
+    const float s = __builtin_amdgcn_sqrtf(s2);
+    const float bl = b * 1.4426950408889634f;
+    const float e1 = __builtin_amdgcn_exp2f(-bl * z2 * __builtin_amdgcn_rcpf(s + m));
+    const float e2 = __builtin_amdgcn_exp2f(-2.f * bl * s);
+    return m * e1 * (1.f - e2) * inv_e2bm * __builtin_amdgcn_rcpf(s);
 }
 
 __device__ __forceinline__ void unpack_cell_m(int packed, int &bx, int &by, int &bz)
@@ -49,7 +54,7 @@ __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return 
 // taps) feeds NO MFMAs and one B fragment (16 RHS at 4 taps) feeds NG MFMAs;
 // the NG * NO accumulator chains are independent.
 template <int SW, int NT, int SX, int NG, int NO>
-__device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&wxq)[NG][NT], const float (&wy)[NG][SW],
+__device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&wxq)[NG][NT], const float *wyl,
                                               const float (&wz)[NG], const float (*sl)[16], int ny, int q, int mrow)
 {
     constexpr int C = SW * SX;  // cells of one output's slab
@@ -60,7 +65,7 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
         float wyz[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            wyz[g] = wy[g][oy] * wz[g];
+            wyz[g] = wyl[(g * SW + oy) * 16 + mrow] * wz[g];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             float b[NO];
@@ -86,7 +91,7 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
 template <int SW, int SX, int NT, int NG, int NO>
 __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
                                              int y0, int z0, int sx, int sy, int nz, f4 (&acc)[NO][NG],
-                                             const float (&wxq)[NG][NT], const float (&wy)[NG][SW],
+                                             const float (&wxq)[NG][NT], const float *wyl,
                                              const float (&uzr)[NG], const int (&lbz)[NG], bool zmask)
 {
     constexpr int C = SW * SX;
@@ -98,6 +103,9 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     const int p0 = r0 >> 1;
     const int np = (nr + 1) >> 1;
+    // Thread element idx covers RHS pair idx % 8 of cell idx / 8: the LDS
+    // stores are then consecutive 8-byte words (no bank conflicts), and the
+    // global loads read 64-byte runs of 8 cells in each pair's grid.
     float2 pre[NO][SL];
     auto load = [&](int oz) {
         const int gz = z0 + oz;
@@ -106,7 +114,7 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
 #pragma unroll
             for (int k = 0; k < SL; ++k) {
                 const int idx = threadIdx.x + k * kBlock;
-                const int pi = idx / C, c = idx - pi * C;
+                const int pi = idx & 7, c = idx >> 3;
                 const int ox = c % SX, oy = c / SX;
                 const int gx = x0 + ox, gy = y0 + oy;
                 float2 v = {0.f, 0.f};
@@ -125,9 +133,9 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
             for (int k = 0; k < SL; ++k) {
                 const int idx = threadIdx.x + k * kBlock;
                 if (idx < 8 * C) {
-                    const int pi = idx / C, c = idx - pi * C;
-                    slab[buf][o][c][2 * pi] = pre[o][k].x;
-                    slab[buf][o][c][2 * pi + 1] = (2 * pi + 1 < nr) ? pre[o][k].y : 0.f;
+                    const int pi = idx & 7, c = idx >> 3;
+                    *(float2 *)&slab[buf][o][c][2 * pi] =
+                        float2{pre[o][k].x, (2 * pi + 1 < nr) ? pre[o][k].y : 0.f};
                 }
             }
     };
@@ -143,7 +151,7 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
             const bool in = !zmask || (unsigned)(oz - lbz[g]) < (unsigned)w.W;
             wz[g] = in ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
         }
-        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wy, wz, &slab[oz & 1][0][0], sy, q, mrow);
+        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, &slab[oz & 1][0][0], sy, q, mrow);
         if (oz + 1 < nz)
             store((oz + 1) & 1);
         __syncthreads();
@@ -154,7 +162,7 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
 // wave + 4 g); groups past the item's end carry zero weights.
 template <int W, int NO, int NG>
 __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &it, int r0, int nr,
-                                                  float (*slab)[NO][W * W][16])
+                                                  float (*slab)[NO][W * W][16], float *wy_lds)
 {
     constexpr int NT = W / 4;  // K steps per x row
     int bx, by, bz;
@@ -163,7 +171,11 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
     const int q = lane >> 4, mrow = lane & 15;
     const float *coords = (const float *)w.coords;
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-    float wxq[NG][NT], wy[NG][W], uz[NG];
+    // x weights stay in registers (lane q holds taps 4t + q); the y weights of
+    // the wave's points go to its LDS area [g][oy][16 points], each lane
+    // computing the taps 4t + q of its point
+    float *wyl = wy_lds + wave * (4 * W * 16);
+    float wxq[NG][NT], uz[NG];
     int lbz[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -174,19 +186,21 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
         uz[g] = coords[2 * w.N + j];
         lbz[g] = 0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t) {
             wxq[g][t] = act ? kb_psi_f(ux - (float)(bx + 4 * t + q), mm, kb, ie) : 0.f;
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-            wy[g][k] = kb_psi_f(uy - (float)(by + k), mm, kb, ie);
+            wyl[(g * W + 4 * t + q) * 16 + mrow] = kb_psi_f(uy - (float)(by + 4 * t + q), mm, kb, ie);
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     f4 acc[NO][NG];
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W, acc, wxq, wy, uz, lbz, false);
+    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W, acc, wxq, wyl, uz, lbz, false);
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -213,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
                                                         int R)
 {
     __shared__ __align__(16) float slab[2][NO][W * W][16];
+    __shared__ __align__(16) float wy_lds[4 * 4 * W * 16];
     const Chunk it = items[blockIdx.x];
     const WinDev &w = wins[it.win];
     const int r0 = blockIdx.y * 16;
@@ -221,10 +236,10 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict
     const int nr = min(16, R - r0);
     const int ng = (((it.count + 15) >> 4) + 3) >> 2;
     switch (ng) {
-    case 1: interp_dense_item<W, NO, 1>(w, it, r0, nr, slab); break;
-    case 2: interp_dense_item<W, NO, 2>(w, it, r0, nr, slab); break;
-    case 3: interp_dense_item<W, NO, 3>(w, it, r0, nr, slab); break;
-    default: interp_dense_item<W, NO, 4>(w, it, r0, nr, slab); break;
+    case 1: interp_dense_item<W, NO, 1>(w, it, r0, nr, slab, wy_lds); break;
+    case 2: interp_dense_item<W, NO, 2>(w, it, r0, nr, slab, wy_lds); break;
+    case 3: interp_dense_item<W, NO, 3>(w, it, r0, nr, slab, wy_lds); break;
+    default: interp_dense_item<W, NO, 4>(w, it, r0, nr, slab, wy_lds); break;
     }
 }
 
@@ -460,14 +475,15 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
 // One pass (<= 256 points) of a sparse tile chunk on the tile's sub-grid.
 template <int W, int NO, int NG>
 __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &ch, int pass, int r0, int nr, int x0,
-                                                 int y0, int z0, float (*slab)[NO][(3 + W) * 16][16])
+                                                 int y0, int z0, float (*slab)[NO][(3 + W) * 16][16], float *wy_lds)
 {
     constexpr int SX = 16, SY = 3 + W;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
     const float *coords = (const float *)w.coords;
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-    float wxq[NG][4], wys[NG][SY], uz[NG];
+    float *wyl = wy_lds + wave * (4 * SY * 16);  // [g][oy][16 points]
+    float wxq[NG][4], uz[NG];
     int lbz[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -484,16 +500,23 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
             wxq[g][t] = (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_f(ux - (float)(x0 + ox), mm, kb, ie) : 0.f;
         }
 #pragma unroll
-        for (int oy = 0; oy < SY; ++oy)
-            wys[g][oy] = ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+        for (int t = 0; t < (SY + 3) / 4; ++t) {
+            const int oy = 4 * t + q;
+            if (oy < SY)
+                wyl[(g * SY + oy) * 16 + mrow] =
+                    ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     f4 acc[NO][NG];
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<SY, SX, 4, NG, NO>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wys, uz, lbz, true);
+    stream_slabs<SY, SX, 4, NG, NO>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz, lbz, true);
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -518,6 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__res
                                                              const Chunk *__restrict__ chunks, int R)
 {
     __shared__ __align__(16) float slab[2][NO][(3 + W) * 16][16];
+    __shared__ __align__(16) float wy_lds[4 * 4 * (3 + W) * 16];
     const Chunk ch = chunks[blockIdx.x];
     const WinDev &w = wins[ch.win];
     const int r0 = blockIdx.y * 16;
@@ -534,10 +558,10 @@ __global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__res
         const int npass = min(256, ch.count - pass);
         const int ng = (((npass + 15) >> 4) + 3) >> 2;
         switch (ng) {
-        case 1: interp_tile_pass<W, NO, 1>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
-        case 2: interp_tile_pass<W, NO, 2>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
-        case 3: interp_tile_pass<W, NO, 3>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
-        default: interp_tile_pass<W, NO, 4>(w, ch, pass, r0, nr, x0, y0, z0, slab); break;
+        case 1: interp_tile_pass<W, NO, 1>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        case 2: interp_tile_pass<W, NO, 2>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        case 3: interp_tile_pass<W, NO, 3>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        default: interp_tile_pass<W, NO, 4>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
         }
         __syncthreads();  // the next pass overwrites the slab buffers
     }

@@ -1014,6 +1014,8 @@ addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_
         for (const WinHost &w : pl.wins)
             info->dense_points += w.ndense_pts;
         info->tile_points = pl.N * pl.P - info->dense_points;
+        info->knobs = (pl.precision == ADDK_FP32 && !pl.eng.no_mfma) ? pl.eng.knobs : 0u;
+        info->tuned = pl.eng.tuned ? 1 : 0;
     }
     for (int w = 0; w < pl.P; ++w) {
         if (torus_period)
