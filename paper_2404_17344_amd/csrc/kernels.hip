@@ -627,39 +627,55 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
     // Tiles of 64 points x 16 RHS: the window products (point-major) are read
     // row by row into LDS and written out column by column, so that both the
     // reads and the writes of the caller's column-major matrices are coalesced.
+    // The (window, output) blocks of a tile are software pipelined: the next
+    // block's loads are in flight while the current one goes through LDS.
     __shared__ double tile[64][17];
     const ProbDev p = get_prob(io, blockIdx.y);
     const int t = threadIdx.x, il = t & 63, rq = t >> 6;
+    const int nout = (mode & 4) && p.dYl ? 2 : 1;
+    const int nblk = (p.wend - p.wbeg) * nout;
     for (int64_t i0 = blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
         const int64_t i = i0 + il;
         const bool own = i < p.N;
         for (int r0 = 0; r0 < R; r0 += 16) {
             const int nr = min(16, R - r0);
+            auto load = [&](int k, double (&v)[4]) {
+                const WinDev &w = wins[p.wbeg + k / nout];
+                const int o = k % nout;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = t + kBlock * q, pl = e >> 4, rr = e & 15;
+                    const int64_t ip = i0 + pl;
+                    v[q] = (ip < p.N && rr < nr) ? w.Yw[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr] : 0.0;
+                }
+            };
             double y[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int wi = p.wbeg; wi < p.wend; ++wi) {
+            double cur[4], nxt[4] = {0.0, 0.0, 0.0, 0.0};
+            if (nblk > 0)
+                load(0, cur);
+            for (int k = 0; k < nblk; ++k) {
+                if (k + 1 < nblk)
+                    load(k + 1, nxt);
+                const int wi = p.wbeg + k / nout, o = k % nout;
                 const WinDev &w = wins[wi];
                 const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
-                const int nout = (mode & 4) && p.dYl ? 2 : 1;
-                for (int o = 0; o < nout; ++o) {
-                    __syncthreads();
+                __syncthreads();
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int e = t + kBlock * k, pl = e >> 4, rr = e & 15;
-                        const int64_t ip = i0 + pl;
-                        tile[pl][rr] = (ip < p.N && rr < nr) ? w.Yw[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr] : 0.0;
-                    }
-                    __syncthreads();
-                    if (!own)
-                        continue;
+                for (int q = 0; q < 4; ++q) {
+                    const int e = t + kBlock * q;
+                    tile[e >> 4][e & 15] = cur[q];
+                }
+                __syncthreads();
+                if (own) {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int rr = rq + 4 * k;
+                    for (int q = 0; q < 4; ++q) {
+                        const int rr = rq + 4 * q;
                         if (rr >= nr)
                             continue;
                         const double v = tile[il][rr];
                         const int64_t at = i + (int64_t)(r0 + rr) * p.ldy;
                         if (o == 0) {
-                            y[k] += w.sig2 * v;
+                            y[q] += w.sig2 * v;
                             if ((mode & 2) && p.dYs)
                                 p.dYs[blk + at] = w.dsig * v;
                         } else {
@@ -667,12 +683,15 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                         }
                     }
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cur[q] = nxt[q];
             }
             if ((mode & 1) && p.Y && own)
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (rq + 4 * k < nr)
-                        p.Y[i + (int64_t)(r0 + rq + 4 * k) * p.ldy] = y[k];
+                for (int q = 0; q < 4; ++q)
+                    if (rq + 4 * q < nr)
+                        p.Y[i + (int64_t)(r0 + rq + 4 * q) * p.ldy] = y[q];
         }
     }
 }

@@ -277,14 +277,20 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
     const int t = threadIdx.x;
 
-    // prefetch registers: thread t < 3*PB holds one coordinate, every thread two RHS values
-    float pc = 0.f;
+    // prefetch registers: the coordinates behind this thread's window values
+    // (entry e = p * 3W + dd * W + o of the round's table, e = t + k * kBlock)
+    // and two RHS values; all threads then share the window evaluations
+    constexpr int NWE = PB * 3 * W;
+    constexpr int KW = (NWE + kBlock - 1) / kBlock;
+    float pcs[KW];
     float pvv[2] = {0.f, 0.f};
     auto load = [&](int p0) {
         const int np = min(PB, it.count - p0);
-        if (t < 3 * PB) {
-            const int p = t / 3, dd = t - 3 * (t / 3);
-            pc = p < np ? coords[dd * w.N + it.start + p0 + p] : 0.f;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int e = t + k * kBlock;
+            const int p = e / (3 * W), dd = (e / W) % 3;
+            pcs[k] = (e < NWE && p < np) ? coords[dd * w.N + it.start + p0 + p] : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -296,12 +302,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     };
     auto store_raw = [&](Round &d, int p0) {
         const int np = min(PB, it.count - p0);
-        if (t < 3 * PB) {
-            const int p = t / 3, dd = t - 3 * (t / 3);
-            const int b0 = dd == 0 ? bx : (dd == 1 ? by : bz);
+        float *pw = &d.pw[0][0][0];
 #pragma unroll
-            for (int o = 0; o < W; ++o)
-                d.pw[p][dd][o] = p < np ? kb_psi_f(pc - (float)(b0 + o), mm, kb, ie) : 0.f;
+        for (int k = 0; k < KW; ++k) {
+            const int e = t + k * kBlock;
+            if (e < NWE) {
+                const int p = e / (3 * W), dd = (e / W) % 3, o = e % W;
+                const int b0 = dd == 0 ? bx : (dd == 1 ? by : bz);
+                pw[e] = p < np ? kb_psi_f(pcs[k] - (float)(b0 + o), mm, kb, ie) : 0.f;
+            }
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -397,6 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
 {
     constexpr int WW = W * W;
     __shared__ f4 red[3][64][4];
+    __shared__ int2 cand[(W + 3) * (W + 3) * (W + 3)];  // base-cell map of the candidate region
     const LineGroup tg = tiles[blockIdx.x];
     const WinDev &w = wins[tg.win];
     const int rb = blockIdx.y;
@@ -419,16 +429,24 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     const int z0 = max(0, tz * 4 - (W - 1)), z1 = min(nb2 - 1, tz * 4 + 3);
     const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
     const int x0 = max(0, tx * 4 - (W - 1)), x1 = min(nb0 - 1, tx * 4 + 3);
-    for (int bz = z0 + wave; bz <= z1; bz += 4) {
-        const int oz = gz - bz;
-        for (int by = y0; by <= y1; ++by) {
-            const int oy = gy - by;
-            const int2 *mrow = map + ((int64_t)bz * nb1 + by) * nb0;
-            for (int bx = x0; bx <= x1; ++bx) {
-                const int2 it = mrow[bx];
+    const bool any = x1 >= x0 && y1 >= y0 && z1 >= z0;
+    const int nx = any ? x1 - x0 + 1 : 0, ny = any ? y1 - y0 + 1 : 0, nz = any ? z1 - z0 + 1 : 0;
+    // stage the base-cell map of the candidate region in LDS (coalesced rows)
+    for (int idx = threadIdx.x; idx < nx * ny * nz; idx += kBlock) {
+        const int dx = idx % nx, dy = (idx / nx) % ny, dz = idx / (nx * ny);
+        cand[idx] = map[((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx];
+    }
+    __syncthreads();
+    for (int dz = wave; dz < nz; dz += 4) {
+        const int bz = z0 + dz, oz = gz - bz;
+        for (int dy = 0; dy < ny; ++dy) {
+            const int by = y0 + dy, oy = gy - by;
+            const int2 *crow = cand + (dz * ny + dy) * nx;
+            for (int dx = 0; dx < nx; ++dx) {
+                const int2 it = crow[dx];
                 if (it.y == 0)
                     continue;
-                const int ox = gx - bx;
+                const int ox = gx - x0 - dx;
                 if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W && (unsigned)oz < (unsigned)W) {
                     const int tap = (oz * W + oy) * W + ox;
                     for (int i = it.x; i < it.x + it.y; ++i) {
