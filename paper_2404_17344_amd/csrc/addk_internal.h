@@ -64,6 +64,7 @@ struct WinDev {
     int nbase[3];        // base cells per dimension: ext - 2m + 1 (unit for unused dims)
     const int2 *dmap;    // base cell -> {first, count} of its dense items in the engine's
                          // matrix-core item list (d = 3 only), or nullptr
+    const void *tw;      // twiddles e^{2 pi i q / nos}, q < nos / 2 (complex real)
 };
 
 // Problem-level input/output pointers (one per plan inside a batch).
@@ -153,6 +154,7 @@ struct Engine {
     int64_t ws_bytes = 0;
     double *yw = nullptr;          // per-window FP64 products
     int64_t yw_bytes = 0;
+    void *d_tw = nullptr;          // twiddle tables for n_os = 16, 32, 64, 128 (engine precision)
     void *vpack = nullptr;         // point-major copies of the problems' V (see ProbDev::Vp)
     int64_t vpack_bytes = 0;
     int64_t vpack_ld = 0;

@@ -372,13 +372,16 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
 // ---------------------------------------------------------------------------
 // line FFTs in LDS (radix-2 Stockham), pruned to the box and to the kept modes
 
+// Each wave transforms its own L / 4 lines, so the passes only need the
+// wave to be in step (no block barrier between passes).
 template <typename real>
 __device__ cpx<real> *fft_lines(cpx<real> *a, cpx<real> *b, const cpx<real> *tw, int nos, int L, real sign)
 {
     const int h = nos >> 1;
+    const int lane = threadIdx.x & 63, lpw = L / (kBlock / 64), l0 = (threadIdx.x >> 6) * lpw;
     for (int Ns = 1; Ns < nos; Ns <<= 1) {
-        for (int t = threadIdx.x; t < L * h; t += kBlock) {
-            const int l = t / h, j = t - l * h;
+        for (int t = lane; t < lpw * h; t += 64) {
+            const int l = l0 + t / h, j = t - (t / h) * h;
             const cpx<real> x0 = a[l * nos + j], x1 = a[l * nos + j + h];
             const int k = j & (Ns - 1);
             const cpx<real> c = tw[k * (h / Ns)];
@@ -388,7 +391,7 @@ __device__ cpx<real> *fft_lines(cpx<real> *a, cpx<real> *b, const cpx<real> *tw,
             b[l * nos + idx] = cadd(x0, y1);
             b[l * nos + idx + Ns] = csub(x0, y1);
         }
-        __syncthreads();
+        wave_sync();
         cpx<real> *s = a;
         a = b;
         b = s;
@@ -484,11 +487,8 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     C *buf0 = tw + kMaxNos / 2;
     C *buf1 = buf0 + L * kMaxNos;
     C *buf2 = buf1 + L * kMaxNos;
-    for (int q = threadIdx.x; q < nos / 2; q += kBlock) {
-        double s, c;
-        sincospi(2.0 * q / nos, &s, &c);
-        tw[q] = {(real)c, (real)s};
-    }
+    for (int q = threadIdx.x; q < nos / 2; q += kBlock)
+        tw[q] = ((const C *)w.tw)[q];
 
     // lines of this group: coordinates (a, b) of the two non-transform axes
     const int *dims = sa.din;
@@ -538,6 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     __syncthreads();
     const real sgn = MODE == 1 ? real(1) : real(-1);
     C *res = fft_lines<real>(buf0, buf1, tw, nos, L, sgn);
+    __syncthreads();  // results are read across waves below
 
     if (MODE == 0 || MODE == 1) {
         for (int t = threadIdx.x; t < L * Lout; t += kBlock) {
@@ -596,6 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
         }
         __syncthreads();
         C *r2 = fft_lines<real>(x0, x1, tw, nos, L, real(1));
+        __syncthreads();
         C *out = sa.out + (int64_t)oo * w.npair_cap * w.szH * (AXIS == 0) +
                  (int64_t)oo * w.npair_cap * w.szA3 * (AXIS != 0);
         for (int t = threadIdx.x; t < L * Lout; t += kBlock) {
@@ -878,6 +880,8 @@ void engine_free(Engine &E)
         free_dev(E.d_gtiles[wi]);
         free_dev(E.scratch[wi]);
     }
+    free_dev(E.vpack);
+    free_dev(E.d_tw);
     for (const ProfRec &r : E.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -889,9 +893,56 @@ void engine_free(Engine &E)
 
 // Device work lists for the engine's windows (descriptors are uploaded by
 // engine_ensure_workspace, which knows the workspace pointers).
+// Twiddle tables e^{2 pi i q / nos}, q < nos / 2, for nos = 16 .. 128, computed
+// in FP64 on the host and rounded once; offset of the table of nos, in entries.
+static int tw_offset(int nos)
+{
+    int off = 0;
+    for (int s = 16; s < nos; s <<= 1)
+        off += s / 2;
+    return off;
+}
+
+static addk_status build_twiddles(Engine &E)
+{
+    free_dev(E.d_tw);
+    E.d_tw = nullptr;
+    const int total = tw_offset(2 * kMaxNos);
+    std::vector<double> re(total), im(total);
+    for (int nos = 16; nos <= kMaxNos; nos <<= 1)
+        for (int q = 0; q < nos / 2; ++q) {
+            re[tw_offset(nos) + q] = std::cos(2.0 * M_PI * q / nos);
+            im[tw_offset(nos) + q] = std::sin(2.0 * M_PI * q / nos);
+        }
+    const size_t rs = real_size(E.precision);
+    std::vector<unsigned char> host(total * 2 * rs);
+    for (int i = 0; i < total; ++i) {
+        if (E.precision == ADDK_FP32) {
+            const float v[2] = {(float)re[i], (float)im[i]};
+            std::memcpy(&host[i * 2 * rs], v, sizeof(v));
+        } else {
+            const double v[2] = {re[i], im[i]};
+            std::memcpy(&host[i * 2 * rs], v, sizeof(v));
+        }
+    }
+    hipError_t e = hipMalloc(&E.d_tw, host.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(E.d_tw, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_fail(e, "twiddle tables");
+    for (WinDev &w : E.wdev)
+        w.tw = (const char *)E.d_tw + (size_t)tw_offset(w.nos) * 2 * rs;
+    return ADDK_OK;
+}
+
 addk_status engine_build_device(Engine &E, int precision)
 {
     E.precision = precision;
+    {
+        addk_status s = build_twiddles(E);
+        if (s != ADDK_OK)
+            return s;
+    }
     const int L = lines_per_group(precision);
     std::vector<Chunk> ch[4];
     std::vector<Chunk> dn[4][2];
