@@ -146,6 +146,23 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv,
                      const double *G, int64_t ldg, double *grad_V, int64_t ldgv,
                      double *grad_ell, double *grad_sigma, void *stream);
 
+/*
+ * Global sensitivity analysis of the fitted function h(x) = sum_j v_j K(x, x_j)
+ * (section "Computing the GSI in the kernel setting", Algorithm 1).  For each
+ * window w, its trigonometric approximation sum_k w_k b_k a_k e^{2 pi i k x}
+ * (the same coefficients as the products; a_k = sum_j v_j e^{-2 pi i k x_j}
+ * on the window's torus) is split by the support of k: theta[8 w + mask] is
+ * the sum of |w_k b_k a_k|^2 over the modes k with k_i != 0 exactly for the
+ * bits i set in mask (bit i = i-th feature of the window; mask 0 is the
+ * constant term, not part of the variance).  The amplitudes sigma_w do not
+ * enter.  Summing theta over windows per feature subset and dividing by the
+ * total over nonzero masks gives the indices rho_u.
+ *   v      N doubles, device (one right-hand side)
+ *   theta  8 P doubles, host; written on return (synchronous)
+ * Errors: INVALID_ARG, OOM, HIP.
+ */
+addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *stream);
+
 /* Replace l_w and sigma_w (host arrays of P) and recompute the multipliers; the
  * torus periods, grids and point sort are kept, so products stay differentiable
  * in l.  Errors: INVALID_ARG, ACCURACY (as in addk_plan_create). */

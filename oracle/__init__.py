@@ -12,6 +12,7 @@ Contents
                 continuous Fourier transforms of the kernels, periodised
                 Fourier coefficients (analytic and sampled), the trigonometric
                 sum of eq. (6) evaluated by brute force, the error bounds of
-                Theorems 1-2 / Remarks 1-2.
+                Theorems 1-2 / Remarks 1-2, and the global sensitivity
+                indices of Algorithm 1.
 """
 from .direct import oracle_direct, oracle_vjp, oracle_threads, build_oracle, lib_path  # noqa: F401

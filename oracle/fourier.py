@@ -24,6 +24,11 @@ Every function follows a passage of the paper:
 * Error bounds of Theorem 1, Remark 1, Theorem 2 and Remark 2 (Fourier
   approximation error section).  Where the statement of Theorem 1 and its
   proof differ for l >= 1/2, the proof's (larger) value is used.
+* Global sensitivity indices (Algorithm 1 of the global sensitivity analysis
+  section): per window, the coefficients c_k S(k, W) of the trigonometric
+  approximation, split by the support of k.  Windows may have any length
+  d <= 3 and their own l and torus period (the paper's remark that this case
+  is analogous); S(k, W) is evaluated by brute force.
 """
 from __future__ import annotations
 
@@ -273,6 +278,53 @@ def fast_sum_oracle(X: np.ndarray, windows: Sequence[Sequence[int]], kernel: int
     if want_derivs:
         return Y, dl, ds
     return Y
+
+
+# ----------------------------------------------------------------------------
+# global sensitivity indices (Algorithm 1)
+
+
+def gsi_theta_oracle(X: np.ndarray, windows: Sequence[Sequence[int]], kernel: int, ell, v: np.ndarray, n: int,
+                     periods=None, mode: str = "analytic") -> np.ndarray:
+    """theta[w, mask] = sum of |c_k S(k, W_w)|^2 over k in I_n^d whose nonzero
+    entries are exactly the bits of mask (bit i: i-th feature of the window),
+    with S(k, W) = sum_j v_j e^{2 pi i k.x~_j^W} on the window's torus (step 2 of
+    Algorithm 1) and c_k the window's periodised coefficients.  Mask 0 is the
+    constant term.  Returns an array (P, 8)."""
+    X = np.asarray(X, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64).reshape(-1)
+    P = len(windows)
+    ell = np.broadcast_to(np.asarray(ell, dtype=np.float64), (P,))
+    theta = np.zeros((P, 8))
+    for w, feats in enumerate(windows):
+        Xw = X[:, list(feats)]
+        d = Xw.shape[1]
+        c, L = window_geometry(Xw)
+        T = periods[w] if periods is not None else torus_period_auto(kernel, L, ell[w], n)
+        xt = (Xw - c) / T
+        cf = coeffs_analytic if mode == "analytic" else coeffs_sampled
+        ck = cf(kernel, ell[w], T, n, d)
+        S = np.conj(_adjoint_ndft(xt, v, n))  # real v: sum_j v_j e^{+2 pi i k.x_j}
+        vals = np.abs(ck * S) ** 2
+        grids = np.meshgrid(*([modes(n)] * d), indexing="ij")
+        mask = sum((g != 0).astype(np.int64) << i for i, g in enumerate(grids))
+        for m in range(1 << d):
+            theta[w, m] = vals[mask == m].sum()
+    return theta
+
+
+def gsi_oracle(X: np.ndarray, windows: Sequence[Sequence[int]], kernel: int, ell, v: np.ndarray, n: int,
+               periods=None) -> dict:
+    """Steps 1-4 of Algorithm 1: theta summed over windows for every nonempty
+    feature subset of every window, divided by the total variance."""
+    theta = gsi_theta_oracle(X, windows, kernel, ell, v, n, periods)
+    acc = {}
+    for w, feats in enumerate(windows):
+        for m in range(1, 1 << len(feats)):
+            key = tuple(sorted(feats[i] for i in range(len(feats)) if m >> i & 1))
+            acc[key] = acc.get(key, 0.0) + theta[w, m]
+    total = sum(acc.values())
+    return {k: val / total for k, val in acc.items()}
 
 
 # ----------------------------------------------------------------------------

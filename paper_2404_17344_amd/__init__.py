@@ -174,6 +174,27 @@ class Plan:
                 "dense_points": info.dense_points, "tile_points": info.tile_points,
                 "knobs": info.knobs, "tuned": bool(info.tuned)}
 
+    def gsi_theta(self, v, stream=None) -> np.ndarray:
+        """Per-window variance contributions theta (P, 8) by support mask (see addk_gsi)."""
+        vc = _colmajor(v)
+        if vc.shape[0] != 1:
+            raise ValueError("gsi takes one right-hand side")
+        th = np.zeros(8 * self.P)
+        _lib.check(self._lib.addk_gsi(self._h, vc.data_ptr(), th.ctypes.data_as(_lib._pd), _stream(stream)),
+                   "addk_gsi")
+        return th.reshape(self.P, 8)
+
+    def gsi(self, v, stream=None) -> dict:
+        """Global sensitivity indices {feature tuple: rho} over all windows and their subsets."""
+        th = self.gsi_theta(v, stream)
+        acc = {}
+        for w, feats in enumerate(self.windows):
+            for mask in range(1, 1 << len(feats)):
+                key = tuple(sorted(feats[i] for i in range(len(feats)) if mask >> i & 1))
+                acc[key] = acc.get(key, 0.0) + th[w, mask]
+        total = sum(acc.values())
+        return {k: (val / total if total > 0 else 0.0) for k, val in acc.items()}
+
     def autotune(self, R: int, nout: int = 1, reps: int = 3, stream=None) -> int:
         """Time the kernel-variant combinations on this plan and keep the fastest (ADDK_KNOB_* mask)."""
         k = ctypes.c_uint32()

@@ -63,6 +63,7 @@ _SIGS = {
     "addk_dmatvec": [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp],
     "addk_vjp": [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp],
     "addk_plan_update_params": [_vp, _pd, _pd, _vp],
+    "addk_gsi": [_vp, _vp, _pd, _vp],
     "addk_plan_query": [_vp, ctypes.POINTER(AddkPlanInfo), _pd, _pd, _pi32],
     "addk_plan_destroy": [_vp],
     "addk_batch_create": [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _pi64,

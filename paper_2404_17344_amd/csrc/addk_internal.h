@@ -204,6 +204,8 @@ addk_status engine_run(Engine &E, int R, int nout, bool store_vmodes_only, bool 
                        IoArgs io, hipStream_t st);
 addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st);
 addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st);
+addk_status engine_gsi(Engine &E, const std::vector<const double *> &B64, const double *psi, int n, double *theta,
+                       hipStream_t st);
 addk_status engine_upload(Engine &E);
 void engine_free(Engine &E);
 bool use_mfma(const Engine &E, uint32_t knob, int R);

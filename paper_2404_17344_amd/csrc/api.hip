@@ -272,6 +272,47 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv, co
     return ADDK_OK;
 }
 
+addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    if (!theta)
+        return fail2(ADDK_ERR_INVALID_ARG, "theta is NULL");
+    Plan &pl = *(Plan *)plan;
+    std::memset(theta, 0, sizeof(double) * 8 * pl.P);
+    if (pl.N == 0)
+        return ADDK_OK;
+    addk_status s;
+    if ((s = check_mat(v, pl.N, pl.N, "v", true)) != ADDK_OK)
+        return s;
+    hipStream_t st = (hipStream_t)stream;
+    IoArgs io;
+    std::memset(&io, 0, sizeof(io));
+    io.single = single_prob(pl);
+    io.single.V = v;
+    io.single.ldv = pl.N;
+    s = engine_run(pl.eng, 1, 0, true, false, io, st);  // spread and forward transform: modes into Vm
+    if (s != ADDK_OK)
+        return s;
+    double *dth = nullptr;
+    hipError_t e = hipMalloc(&dth, sizeof(double) * 8 * pl.P);
+    if (e != hipSuccess)
+        return fail2(ADDK_ERR_OOM, "gsi output allocation failed");
+    std::vector<const double *> B64(pl.P);
+    for (int w = 0; w < pl.P; ++w)
+        B64[w] = pl.wins[w].Bk64;
+    s = engine_gsi(pl.eng, B64, pl.d_psi, pl.n, dth, st);
+    if (s == ADDK_OK) {
+        e = hipMemcpyAsync(theta, dth, sizeof(double) * 8 * pl.P, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            s = hip_fail(e, "gsi result copy");
+    }
+    (void)hipFree(dth);
+    return s;
+}
+
 addk_status addk_plan_profile(addk_plan plan, int32_t enable)
 {
     if (!plan)

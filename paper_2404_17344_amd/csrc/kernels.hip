@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 
 #include "addk_internal.h"
 
@@ -752,6 +753,96 @@ __global__ void k_mode_dot_finish(const WinDev *__restrict__ wins, int win, int 
         grad_ell[0] = w.der_scale * sd;
     if (grad_sig)
         grad_sig[0] = w.dsig * sk;
+}
+
+// ---------------------------------------------------------------------------
+// Global sensitivity indices (Algorithm 1): the trigonometric polynomial of a
+// window has coefficients w_k b_k a_k, a_k = sum_j v_j e^{-2 pi i k x_j}; the
+// variance of its ANOVA term on the features u is the sum of |w_k b_k a_k|^2
+// over the modes whose support is u.  With B_k = w_k b_k / prod Psi(k_i)^2
+// and the spread-and-transformed modes g^_k = a_k prod Psi(k_i), that is
+// |B_k prod Psi(k_i) g^_k|^2.  Bins: bit i of the mask set iff k_i != 0.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_gsi_theta(const cpx<real> *__restrict__ Vm, const double *__restrict__ B,
+                                                      const double *__restrict__ psi, int d, int n, int64_t szM,
+                                                      double *partial)
+{
+    const int n1 = n + 1, half = n / 2;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < szM; idx += (int64_t)gridDim.x * kBlock) {
+        int64_t r = idx;
+        int mask = 0;
+        double ps = 1.0;
+        for (int i = 0; i < d; ++i) {
+            const int c = (int)(r % n1);
+            r /= n1;
+            mask |= (c != half) << i;
+            ps *= psi[c];
+        }
+        const cpx<real> g = Vm[idx];
+        const double cf = B[idx] * ps;
+        const double val = cf * cf * ((double)g.x * (double)g.x + (double)g.y * (double)g.y);
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            acc[b] += b == mask ? val : 0.0;
+    }
+    __shared__ double red[8][kBlock];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        red[b][threadIdx.x] = acc[b];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                red[b][threadIdx.x] += red[b][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8)
+        partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_gsi_finish(int nblk, const double *partial, double *theta)
+{
+    const int b = threadIdx.x;
+    if (blockIdx.x != 0 || b >= 8)
+        return;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k)
+        s += partial[(int64_t)k * 8 + b];
+    theta[b] = s;
+}
+
+static void free_dev(void *p);
+
+// theta: device array of 8 doubles per window (window order of the engine)
+addk_status engine_gsi(Engine &E, const std::vector<const double *> &B64, const double *psi, int n, double *theta,
+                       hipStream_t st)
+{
+    const int nblk = 128;
+    const int64_t need = (int64_t)8 * nblk;
+    if (E.partial_cap < need) {
+        free_dev(E.d_partial);
+        E.d_partial = nullptr;
+        hipError_t e = hipMalloc(&E.d_partial, need * sizeof(double));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(partials)");
+        E.partial_cap = need;
+    }
+    for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
+        const WinDev &w = E.wdev[wi];
+        if (E.precision == ADDK_FP32)
+            hipLaunchKernelGGL(k_gsi_theta<float>, dim3(nblk), dim3(kBlock), 0, st, (const cpx<float> *)w.Vm, B64[wi],
+                               psi, w.d, n, w.szM, E.d_partial);
+        else
+            hipLaunchKernelGGL(k_gsi_theta<double>, dim3(nblk), dim3(kBlock), 0, st, (const cpx<double> *)w.Vm,
+                               B64[wi], psi, w.d, n, w.szM, E.d_partial);
+        hipLaunchKernelGGL(k_gsi_finish, dim3(1), dim3(64), 0, st, nblk, E.d_partial, theta + 8 * wi);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "gsi launch");
+    return ADDK_OK;
 }
 
 // ---------------------------------------------------------------------------

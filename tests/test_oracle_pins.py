@@ -385,3 +385,63 @@ def test_measured_errors_below_1d_remarks(n, ell):
 def test_bounds_need_eta_at_least_one():
     with pytest.raises(ValueError):
         F.theorem1_bound(0.01, 16)
+
+
+# ------------------------------------------------------- global sensitivity
+
+
+def _anova_variances(c: np.ndarray) -> dict:
+    """Variances of the ANOVA terms of f(x) = sum_k c_k e^{2 pi i k.x} on the
+    torus, computed from the definition of the decomposition: f is sampled on
+    a uniform grid (inverse FFT), each term f_u is the average of f over the
+    features outside u minus the terms of the proper subsets of u, and its
+    variance is the grid mean of |f_u|^2 (exact for trigonometric polynomials
+    on a grid with more points than the bandwidth)."""
+    d = c.ndim
+    n = c.shape[0]
+    G = n + 2
+    full = np.zeros((G,) * d, dtype=np.complex128)
+    idx = np.ix_(*([(np.arange(n) - n // 2) % G] * d))
+    full[idx] = c
+    f = np.fft.ifftn(full) * G ** d  # f at x = j / G
+    terms = {}
+    for u in range(1 << d):
+        axes = tuple(i for i in range(d) if not (u >> i & 1))
+        g = f.mean(axis=axes, keepdims=True) if axes else f
+        for v in terms:
+            if v & u == v and v != u:
+                g = g - terms[v]
+        terms[u] = g
+    return {u: float(np.mean(np.abs(np.broadcast_to(t, f.shape)) ** 2)) for u, t in terms.items()}
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_gsi_theta_matches_anova_of_the_trigonometric_polynomial(d):
+    """theta of Algorithm 1 equals the variances of the ANOVA terms of the
+    window's trigonometric polynomial, obtained independently by averaging the
+    polynomial over the other features on a grid."""
+    rng = np.random.default_rng(70 + d)
+    N, n, ell = 300, 12, 0.15
+    X = rng.uniform(-0.25, 0.25, size=(N, d))
+    v = rng.standard_normal(N)
+    theta = F.gsi_theta_oracle(X, [list(range(d))], F.GAUSSIAN, [ell], v, n)[0]
+    c, L = F.window_geometry(X)
+    T = F.torus_period_auto(F.GAUSSIAN, L, ell, n)
+    xt = (X - c) / T
+    coef = F.coeffs_analytic(F.GAUSSIAN, ell, T, n, d) * np.conj(F._adjoint_ndft(xt, v, n))
+    var = _anova_variances(coef)
+    for u in range(1 << d):
+        assert theta[u] == pytest.approx(var[u], rel=1e-9, abs=1e-12 * sum(var.values()))
+
+
+def test_gsi_indices_sum_to_one_and_follow_the_data():
+    """The indices of all nonempty subsets sum to one; a target that varies only
+    with feature 0 puts (almost) all weight on the subsets holding feature 0."""
+    rng = np.random.default_rng(75)
+    N = 400
+    X = rng.uniform(-0.25, 0.25, size=(N, 4))
+    v = np.sin(12 * X[:, 0]) * 0.1
+    rho = F.gsi_oracle(X, [[0, 1], [2, 3]], F.GAUSSIAN, [0.2, 0.2], v, 16)
+    assert sum(rho.values()) == pytest.approx(1.0, rel=1e-12)
+    assert set(rho) == {(0,), (1,), (0, 1), (2,), (3,), (2, 3)}
+    assert all(r >= 0 for r in rho.values())
