@@ -110,6 +110,25 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
                              int32_t precision, uint32_t flags, void *stream);
 
 /*
+ * A plan whose products are evaluated at separate target points x'_1..x'_Nt
+ * (eq. (4) with x' != x, e.g. prediction points):
+ *   Y_i = sum_w sigma_w^2 sum_j kappa(||x'_i^{W_w} - x_j^{W_w}||; l_w) V_j.
+ * Xs (Ns x D) are the sources, Xt (Nt x D) the targets, row-major with their
+ * own leading dimensions, host or device, copied.  Torus periods and grid
+ * boxes cover sources and targets together.  The plan then serves
+ * addk_matvec / addk_dmatvec with V of Ns rows and Y (and the derivative
+ * outputs) of Nt rows, addk_gsi with v of Ns rows; addk_vjp and batches need
+ * square plans (ADDK_ERR_UNSUPPORTED).  Other arguments and errors as in
+ * addk_plan_create.  The current implementation spreads and interpolates at
+ * all Ns + Nt points (the targets carry zero weight).
+ */
+addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int32_t D, const double *Xs,
+                                     int64_t ldxs, const double *Xt, int64_t ldxt, int32_t P,
+                                     const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
+                                     const double *ell, const double *sigma, int32_t n, int32_t m,
+                                     double oversampling, int32_t precision, uint32_t flags, void *stream);
+
+/*
  * Y = sum_w sigma_w^2 K_w V (eqs. (4)-(6) per window, then the window sum of
  * eq. (7)).  V: N x R (ldv >= N), Y: N x R (ldy >= N); device pointers.
  * R >= 1.  V and Y must not overlap.
@@ -145,6 +164,21 @@ addk_status addk_dmatvec(addk_plan plan, int32_t R, const double *V, int64_t ldv
 addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv,
                      const double *G, int64_t ldg, double *grad_V, int64_t ldgv,
                      double *grad_ell, double *grad_sigma, void *stream);
+
+/*
+ * Conjugate gradients for the kernel ridge regression system of eq. (9),
+ * (K + beta I) X = Y, with K the plan's product (square plans only).  The R
+ * columns are solved together, each with its own step sizes, until
+ * ||Y - (K + beta I) X||_2 <= tol ||Y||_2 per column (residual recurrence) or
+ * maxit iterations.  X holds the initial guess on entry and the solution on
+ * return; Y and X are device FP64, column-major, ld >= N.  iters (host, may
+ * be NULL) receives the iterations run, relres (host, R doubles, may be NULL)
+ * the final relative residuals.  Synchronous (the host checks convergence
+ * each iteration).  Errors: INVALID_ARG, UNSUPPORTED (plan with separate
+ * targets), OOM, HIP.
+ */
+addk_status addk_cg(addk_plan plan, double beta, int32_t R, const double *Y, int64_t ldy, double *X, int64_t ldx,
+                    double tol, int32_t maxit, int32_t *iters, double *relres, void *stream);
 
 /*
  * Global sensitivity analysis of the fitted function h(x) = sum_j v_j K(x, x_j)
@@ -190,6 +224,8 @@ typedef struct {
     int64_t tile_points;        /* point-window pairs handled by the tile kernels       */
     uint32_t knobs;             /* ADDK_KNOB_* in effect                                 */
     int32_t tuned;              /* 1 once addk_plan_autotune chose the knobs             */
+    int64_t n_sources;          /* rows of V (= N unless the plan has separate targets) */
+    int64_t n_targets;          /* rows of Y                                             */
 } addk_plan_info;
 addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_period,
                             double *eta, int32_t *window_dim);

@@ -97,26 +97,32 @@ class Plan:
     def __init__(self, X, windows: Sequence[Sequence[int]], ell, sigma, kernel="gaussian", n: int = 64,
                  m: int = 6, oversampling: float = 2.0, precision="fp64", coef: str = "analytic",
                  torus: str = "auto", check_accuracy: bool = True, dense_kernels: bool = True, matrix_cores: bool = True,
-                 stream=None):
+                 targets=None, stream=None):
+        """X: sources (N, D), host array or CUDA tensor.  targets: optional (Nt, D)
+        prediction points; the plan's products then map N-row V to Nt-row Y."""
         lib = _lib.load()
         torch = _torch()
-        if isinstance(X, torch.Tensor):
-            Xt = X.detach().to(torch.float64).contiguous()
-            N, D = Xt.shape
-            xptr = Xt.data_ptr() if N else None
-            self._xkeep = Xt
-        else:
-            Xn = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
-            N, D = Xn.shape
-            xptr = Xn.ctypes.data if N else None
-            self._xkeep = Xn
+
+        def _points(A):
+            if isinstance(A, torch.Tensor):
+                At = A.detach().to(torch.float64).contiguous()
+                return At, At.shape[0], At.shape[1], (At.data_ptr() if At.shape[0] else None)
+            An = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+            return An, An.shape[0], An.shape[1], (An.ctypes.data if An.shape[0] else None)
+
+        self._xkeep, N, D, xptr = _points(X)
+        if targets is not None:
+            self._tkeep, Nt, Dt, tptr = _points(targets)
+            if Dt != D:
+                raise ValueError("targets must have the sources' number of features")
         off = [0]
         feat = []
         for w in windows:
             feat.extend(int(f) for f in w)
             off.append(len(feat))
         self.P = len(windows)
-        self.N = int(N)
+        self.N = int(N)  # rows of V
+        self.N_out = int(Nt) if targets is not None else int(N)  # rows of Y
         self.windows = [list(w) for w in windows]
         off_a = (ctypes.c_int32 * len(off))(*off)
         feat_a = (ctypes.c_int32 * max(1, len(feat)))(*feat)
@@ -135,9 +141,15 @@ class Plan:
             flags |= _lib.ADDK_VECTOR_ALU_ONLY
         h = ctypes.c_void_p()
         st = _stream(stream) if torch.cuda.is_available() else ctypes.c_void_p(0)
-        _lib.check(lib.addk_plan_create(ctypes.byref(h), N, D, xptr, D, self.P, off_a, feat_a, _KERNELS[kernel],
-                                        ell_a.ctypes.data_as(_lib._pd), sig_a.ctypes.data_as(_lib._pd), n, m,
-                                        float(oversampling), _PREC[precision], flags, st), "addk_plan_create")
+        if targets is None:
+            _lib.check(lib.addk_plan_create(ctypes.byref(h), N, D, xptr, D, self.P, off_a, feat_a, _KERNELS[kernel],
+                                            ell_a.ctypes.data_as(_lib._pd), sig_a.ctypes.data_as(_lib._pd), n, m,
+                                            float(oversampling), _PREC[precision], flags, st), "addk_plan_create")
+        else:
+            _lib.check(lib.addk_plan_create_targets(ctypes.byref(h), N, Nt, D, xptr, D, tptr, D, self.P, off_a,
+                                                    feat_a, _KERNELS[kernel], ell_a.ctypes.data_as(_lib._pd),
+                                                    sig_a.ctypes.data_as(_lib._pd), n, m, float(oversampling),
+                                                    _PREC[precision], flags, st), "addk_plan_create_targets")
         self._h = h
         self._lib = lib
         self.kernel = _KERNELS[kernel]
@@ -172,7 +184,8 @@ class Plan:
                 "precision": info.precision, "kernel": info.kernel, "workspace_bytes": info.workspace_bytes,
                 "err_estimate": info.err_estimate, "T": list(T), "eta": list(eta), "d": list(dims),
                 "dense_points": info.dense_points, "tile_points": info.tile_points,
-                "knobs": info.knobs, "tuned": bool(info.tuned)}
+                "knobs": info.knobs, "tuned": bool(info.tuned), "n_sources": info.n_sources,
+                "n_targets": info.n_targets}
 
     def gsi_theta(self, v, stream=None) -> np.ndarray:
         """Per-window variance contributions theta (P, 8) by support mask (see addk_gsi)."""
@@ -226,10 +239,23 @@ class Plan:
         torch = _torch()
         Vc = _colmajor(V)
         R = Vc.shape[0]
-        Yc = out if out is not None else torch.empty((R, self.N), dtype=torch.float64, device=Vc.device)
-        _lib.check(self._lib.addk_matvec(self._h, R, Vc.data_ptr(), max(self.N, 1), Yc.data_ptr(), max(self.N, 1),
-                                         _stream(stream)), "addk_matvec")
+        Yc = out if out is not None else torch.empty((R, self.N_out), dtype=torch.float64, device=Vc.device)
+        _lib.check(self._lib.addk_matvec(self._h, R, Vc.data_ptr(), max(self.N, 1), Yc.data_ptr(),
+                                         max(self.N_out, 1), _stream(stream)), "addk_matvec")
         return Yc.t()
+
+    def cg(self, Y, beta: float, tol: float = 1e-3, maxit: int = 500, X0=None, stream=None):
+        """Solve (K + beta I) X = Y by conjugate gradients (eq. (9)); returns (X, iterations, relres)."""
+        torch = _torch()
+        Yc = _colmajor(Y)
+        R = Yc.shape[0]
+        Xc = _colmajor(X0).clone() if X0 is not None else torch.zeros_like(Yc)
+        it = ctypes.c_int32()
+        rel = np.zeros(R)
+        _lib.check(self._lib.addk_cg(self._h, float(beta), R, Yc.data_ptr(), max(self.N, 1), Xc.data_ptr(),
+                                     max(self.N, 1), float(tol), int(maxit), ctypes.byref(it),
+                                     rel.ctypes.data_as(_lib._pd), _stream(stream)), "addk_cg")
+        return Xc.t(), it.value, rel
 
     def dmatvec(self, V, want_y=True, want_dell=True, want_dsigma=True, stream=None):
         """Returns (Y, dY_dell, dY_dsigma) with dY_* of shape (P, N, R) (None where not requested)."""
@@ -237,12 +263,12 @@ class Plan:
         Vc = _colmajor(V)
         R = Vc.shape[0]
         dev = Vc.device
-        Y = torch.empty((R, self.N), dtype=torch.float64, device=dev) if want_y else None
-        dl = torch.empty((self.P, R, self.N), dtype=torch.float64, device=dev) if want_dell else None
-        ds = torch.empty((self.P, R, self.N), dtype=torch.float64, device=dev) if want_dsigma else None
+        Y = torch.empty((R, self.N_out), dtype=torch.float64, device=dev) if want_y else None
+        dl = torch.empty((self.P, R, self.N_out), dtype=torch.float64, device=dev) if want_dell else None
+        ds = torch.empty((self.P, R, self.N_out), dtype=torch.float64, device=dev) if want_dsigma else None
         p = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
         _lib.check(self._lib.addk_dmatvec(self._h, R, Vc.data_ptr(), max(self.N, 1), p(dl), p(ds), p(Y),
-                                          max(self.N, 1), _stream(stream)), "addk_dmatvec")
+                                          max(self.N_out, 1), _stream(stream)), "addk_dmatvec")
         t2 = lambda t: t.transpose(1, 2) if t is not None else None  # noqa: E731
         return (Y.t() if Y is not None else None), t2(dl), t2(ds)
 

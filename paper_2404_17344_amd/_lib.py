@@ -42,7 +42,8 @@ class AddkPlanInfo(ctypes.Structure):
                 ("n_os", ctypes.c_int32), ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("err_estimate", ctypes.c_double),
                 ("dense_points", ctypes.c_int64), ("tile_points", ctypes.c_int64),
-                ("knobs", ctypes.c_uint32), ("tuned", ctypes.c_int32)]
+                ("knobs", ctypes.c_uint32), ("tuned", ctypes.c_int32),
+                ("n_sources", ctypes.c_int64), ("n_targets", ctypes.c_int64)]
 
 
 _lib = None
@@ -64,6 +65,9 @@ _SIGS = {
     "addk_vjp": [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp],
     "addk_plan_update_params": [_vp, _pd, _pd, _vp],
     "addk_gsi": [_vp, _vp, _pd, _vp],
+    "addk_cg": [_vp, _d, _i32, _vp, _i64, _vp, _i64, _d, _i32, _pi32, _pd, _vp],
+    "addk_plan_create_targets": [ctypes.POINTER(_vp), _i64, _i64, _i32, _vp, _i64, _vp, _i64, _i32, _pi32, _pi32,
+                                 _i32, _pd, _pd, _i32, _i32, _d, _i32, _u32, _vp],
     "addk_plan_query": [_vp, ctypes.POINTER(AddkPlanInfo), _pd, _pd, _pi32],
     "addk_plan_destroy": [_vp],
     "addk_batch_create": [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _pi64,

@@ -71,6 +71,8 @@ struct WinDev {
 struct ProbDev {
     int64_t N;
     int32_t wbeg, wend;       // windows [wbeg, wend) of the engine belong to it
+    int64_t nsrc;             // points [0, nsrc) carry V (the rest are targets only)
+    int64_t yoff;             // outputs are points [yoff, N), row i - yoff of Y
     const double *V;
     int64_t ldv;
     const void *Vp;           // point-major copy of V in the engine's precision,
@@ -182,6 +184,8 @@ struct StageTimer {
 
 struct Plan {
     int64_t N = 0;
+    int64_t nsrc = 0;  // sources are points [0, nsrc); targets [nsrc, N) if nsrc < N (rectangular plan)
+    bool rect = false;
     int32_t D = 0, P = 0;
     int32_t kernel = ADDK_GAUSSIAN, n = 0, m = 0, nos = 0, precision = ADDK_FP64;
     uint32_t flags = 0;

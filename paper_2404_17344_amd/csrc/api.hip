@@ -50,6 +50,8 @@ static ProbDev single_prob(const Plan &pl)
     ProbDev p;
     std::memset(&p, 0, sizeof(p));
     p.N = pl.N;
+    p.nsrc = pl.nsrc;
+    p.yoff = pl.rect ? pl.nsrc : 0;
     p.wbeg = 0;
     p.wend = pl.P;
     return p;
@@ -168,7 +170,8 @@ addk_status addk_matvec(addk_plan plan, int32_t R, const double *V, int64_t ldv,
     if (pl.N == 0)
         return ADDK_OK;
     addk_status s;
-    if ((s = check_mat(V, ldv, pl.N, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, pl.N, "Y", true)) != ADDK_OK)
+    const int64_t nout_rows = pl.rect ? pl.N - pl.nsrc : pl.N;
+    if ((s = check_mat(V, ldv, pl.nsrc, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, nout_rows, "Y", true)) != ADDK_OK)
         return s;
     IoArgs io;
     std::memset(&io, 0, sizeof(io));
@@ -197,9 +200,10 @@ addk_status addk_dmatvec(addk_plan plan, int32_t R, const double *V, int64_t ldv
     if (pl.N == 0)
         return ADDK_OK;
     addk_status s;
-    if ((s = check_mat(V, ldv, pl.N, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, pl.N, "Y", false)) != ADDK_OK ||
-        (s = check_mat(dY_dell, ldy, pl.N, "dY_dell", false)) != ADDK_OK ||
-        (s = check_mat(dY_dsigma, ldy, pl.N, "dY_dsigma", false)) != ADDK_OK)
+    const int64_t nout_rows = pl.rect ? pl.N - pl.nsrc : pl.N;
+    if ((s = check_mat(V, ldv, pl.nsrc, "V", true)) != ADDK_OK || (s = check_mat(Y, ldy, nout_rows, "Y", false)) != ADDK_OK ||
+        (s = check_mat(dY_dell, ldy, nout_rows, "dY_dell", false)) != ADDK_OK ||
+        (s = check_mat(dY_dsigma, ldy, nout_rows, "dY_dsigma", false)) != ADDK_OK)
         return s;
     IoArgs io;
     std::memset(&io, 0, sizeof(io));
@@ -227,6 +231,8 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv, co
     Plan &pl = *(Plan *)plan;
     if (R < 1)
         return fail2(ADDK_ERR_INVALID_ARG, "R must be >= 1");
+    if (pl.rect)
+        return fail2(ADDK_ERR_UNSUPPORTED, "addk_vjp needs a square plan (targets = sources)");
     addk_status s;
     const bool scalars = grad_ell || grad_sigma;
     if ((grad_ell && !on_device(grad_ell)) || (grad_sigma && !on_device(grad_sigma)))
@@ -283,14 +289,14 @@ addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *strea
     if (pl.N == 0)
         return ADDK_OK;
     addk_status s;
-    if ((s = check_mat(v, pl.N, pl.N, "v", true)) != ADDK_OK)
+    if ((s = check_mat(v, pl.nsrc, pl.nsrc, "v", true)) != ADDK_OK)
         return s;
     hipStream_t st = (hipStream_t)stream;
     IoArgs io;
     std::memset(&io, 0, sizeof(io));
     io.single = single_prob(pl);
     io.single.V = v;
-    io.single.ldv = pl.N;
+    io.single.ldv = pl.nsrc;
     s = engine_run(pl.eng, 1, 0, true, false, io, st);  // spread and forward transform: modes into Vm
     if (s != ADDK_OK)
         return s;
@@ -352,6 +358,8 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
         const Plan &pl = *(Plan *)plans[p];
         if (pl.precision != prec)
             return fail2(ADDK_ERR_INVALID_ARG, "all plans of a batch must share one precision");
+        if (pl.rect)
+            return fail2(ADDK_ERR_UNSUPPORTED, "plans with separate targets cannot be batched");
         if (pl.N > 0) {
             addk_status s;
             if ((s = check_mat(V[p], ldv[p], pl.N, "V[p]", true)) != ADDK_OK ||
@@ -373,6 +381,8 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
         ProbDev &pd = E.probs[p];
         std::memset(&pd, 0, sizeof(pd));
         pd.N = pl->N;
+        pd.nsrc = pl->N;
+        pd.yoff = 0;
         pd.wbeg = (int)E.wdev.size();
         for (int w = 0; w < pl->P; ++w) {
             WinDev d = pl->eng.wdev[w];

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_v(IoArgs io, int R)
             for (int k = 0; k < 4; ++k) {
                 const int r = r0 + rq + 4 * k;
                 const int64_t i = i0 + il;
-                tile[rq + 4 * k][il] = (i < p.N && r < R) ? p.V[i + (int64_t)r * p.ldv] : 0.0;
+                tile[rq + 4 * k][il] = (i < p.nsrc && r < R) ? p.V[i + (int64_t)r * p.ldv] : 0.0;
             }
             __syncthreads();
 #pragma unroll
@@ -637,9 +637,10 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
     const int t = threadIdx.x, il = t & 63, rq = t >> 6;
     const int nout = (mode & 4) && p.dYl ? 2 : 1;
     const int nblk = (p.wend - p.wbeg) * nout;
-    for (int64_t i0 = blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
+    for (int64_t i0 = p.yoff + blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
         const int64_t i = i0 + il;
         const bool own = i < p.N;
+        const int64_t iy = i - p.yoff;  // output row
         for (int r0 = 0; r0 < R; r0 += 16) {
             const int nr = min(16, R - r0);
             auto load = [&](int k, double (&v)[4]) {
@@ -676,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                         if (rr >= nr)
                             continue;
                         const double v = tile[il][rr];
-                        const int64_t at = i + (int64_t)(r0 + rr) * p.ldy;
+                        const int64_t at = iy + (int64_t)(r0 + rr) * p.ldy;
                         if (o == 0) {
                             y[q] += w.sig2 * v;
                             if ((mode & 2) && p.dYs)
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     if (rq + 4 * q < nr)
-                        p.Y[i + (int64_t)(r0 + rq + 4 * q) * p.ldy] = y[q];
+                        p.Y[iy + (int64_t)(r0 + rq + 4 * q) * p.ldy] = y[q];
         }
     }
 }
@@ -1499,10 +1500,10 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
         return ADDK_OK;
     int64_t maxN = 0;
     for (const ProbDev &p : E.probs)
-        maxN = std::max(maxN, p.N);
+        maxN = std::max(maxN, p.N - p.yoff);
     if (!io.table)
-        maxN = io.single.N;
-    if (maxN == 0 || R == 0)
+        maxN = io.single.N - io.single.yoff;
+    if (maxN <= 0 || R == 0)
         return ADDK_OK;
     const int bx = (int)std::min<int64_t>((maxN + 63) / 64, 16384);
     const int ny = io.table ? E.nprob : 1;

@@ -868,6 +868,7 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
         return fail(ADDK_ERR_OOM, "host allocation failed");
     (void)hipGetDevice(&pl->device);
     pl->N = N;
+    pl->nsrc = N;
     pl->D = D;
     pl->P = P;
     pl->kernel = kernel;
@@ -947,6 +948,44 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
     return ADDK_OK;
 }
 
+addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int32_t D, const double *Xs,
+                                     int64_t ldxs, const double *Xt, int64_t ldxt, int32_t P,
+                                     const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
+                                     const double *ell, const double *sigma, int32_t n, int32_t m,
+                                     double oversampling, int32_t precision, uint32_t flags, void *stream)
+{
+    if (!out)
+        return fail(ADDK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (Ns < 0 || Nt < 0 || D <= 0 || Ns + Nt > INT32_MAX || (Ns > 0 && (!Xs || ldxs < D)) ||
+        (Nt > 0 && (!Xt || ldxt < D)))
+        return fail(ADDK_ERR_INVALID_ARG, "bad sizes or NULL pointers");
+    // one point set [sources; targets]: the torus and grid box cover both
+    const int64_t N = Ns + Nt;
+    double *dX = nullptr;
+    hipError_t e = hipSuccess;
+    if (N > 0 && (e = hipMalloc(&dX, N * D * sizeof(double))) != hipSuccess)
+        return fail(ADDK_ERR_OOM, "allocation of the point copy failed");
+    if (Ns > 0)
+        e = hipMemcpy2D(dX, D * sizeof(double), Xs, ldxs * sizeof(double), D * sizeof(double), Ns, hipMemcpyDefault);
+    if (e == hipSuccess && Nt > 0)
+        e = hipMemcpy2D(dX + Ns * D, D * sizeof(double), Xt, ldxt * sizeof(double), D * sizeof(double), Nt,
+                        hipMemcpyDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(dX);
+        return hip_fail(e, "copy of the points");
+    }
+    addk_status s = addk_plan_create(out, N, D, dX, D, P, win_offsets, win_features, kernel, ell, sigma, n, m,
+                                     oversampling, precision, flags, stream);
+    (void)hipFree(dX);
+    if (s != ADDK_OK)
+        return s;
+    Plan &pl = *(Plan *)*out;
+    pl.nsrc = Ns;
+    pl.rect = true;
+    return ADDK_OK;
+}
+
 addk_status addk_plan_destroy(addk_plan plan)
 {
     if (!plan)
@@ -1016,6 +1055,8 @@ addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_
         info->tile_points = pl.N * pl.P - info->dense_points;
         info->knobs = (pl.precision == ADDK_FP32 && !pl.eng.no_mfma) ? pl.eng.knobs : 0u;
         info->tuned = pl.eng.tuned ? 1 : 0;
+        info->n_sources = pl.nsrc;
+        info->n_targets = pl.rect ? pl.N - pl.nsrc : pl.N;
     }
     for (int w = 0; w < pl.P; ++w) {
         if (torus_period)
