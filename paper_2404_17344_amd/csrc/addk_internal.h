@@ -36,7 +36,9 @@ constexpr int kMaxW = 16;        // maximal taps per dimension (m <= 8)
 constexpr int kMaxNos = 128;     // maximal oversampled grid per dimension
 constexpr int kLdsBudget = 64 * 1024;
 constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
-constexpr int kDenseChunk = 256; // maximal points per dense work item
+constexpr int kDenseChunk = 256; // maximal points per dense interp item
+constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item (one window block each;
+                                   // bounds the FP32 accumulation length)
 constexpr int kMfmaMinR = 8;     // fewest RHS for which the matrix-core dense kernels are used
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
@@ -111,7 +113,9 @@ struct WinHost {
     void *Bk = nullptr, *Bd = nullptr;
     double *Bk64 = nullptr, *Bd64 = nullptr;
     std::vector<Chunk> chunks;  // sparse tile chunks; win field is filled by the engine
-    std::vector<Chunk> dense;   // dense cell runs; tile field holds the packed base cell
+    std::vector<Chunk> dense;   // dense cell runs for interp (<= kDenseChunk points); tile field holds
+                                // the packed base cell
+    std::vector<Chunk> dense_sp;  // the same runs for spreading, <= kSpreadChunk points each
     int64_t ndense_pts = 0;
 };
 
@@ -136,8 +140,10 @@ struct Engine {
     WinDev *d_wins = nullptr;
     Chunk *d_chunks[4] = {nullptr, nullptr, nullptr, nullptr};  // per d (1..3)
     int nchunks[4] = {0, 0, 0, 0};
-    Chunk *d_dense[4][2] = {};     // dense cell runs per d and window width (2m = 8, 12)
+    Chunk *d_dense[4][2] = {};     // dense cell runs (interp items) per d and window width (2m = 8, 12)
     int ndense[4][2] = {};
+    Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)
+    int ndense_sp[4][2] = {};
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
     bool no_mfma = false;          // use the vector-ALU dense kernels only

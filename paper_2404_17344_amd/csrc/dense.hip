@@ -49,17 +49,28 @@ __device__ __forceinline__ float kb_psi_d<float>(float z, float m, float b, floa
     return m * e1 * (1.f - e2) * inv_e2bm * __builtin_amdgcn_rcpf(s);
 }
 
-__device__ __forceinline__ void unpack_cell(int packed, int &bx, int &by, int &bz)
+// Dense item anchor: base cell (bx, by, bz) and the number of cells in z
+// (1, or 2 for two z-adjacent dense cells sharing one item, d = 3).
+__device__ __forceinline__ void unpack_cell(int packed, int &bx, int &by, int &bz, int &nzc)
 {
     bx = packed & 1023;
     by = (packed >> 10) & 1023;
-    bz = packed >> 20;
+    bz = (packed >> 20) & 1023;
+    nzc = ((packed >> 30) & 1) + 1;
 }
 
 __device__ __forceinline__ ProbDev get_prob_d(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
 
 __device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// Cells of a dense item's window block: (2m)^d, with one more z layer for the
+// two-cell items of d = 3.  Shared by the interp kernel and its launcher.
+template <int D, int W>
+constexpr int dense_block_cells()
+{
+    return D == 3 ? W * W * (W + 1) : (D == 2 ? W * W : W);
+}
 
 // ---------------------------------------------------------------------------
 // spread, dense cells.  blockDim.x = OUT * NRG threads; thread (q, rg) owns
@@ -70,9 +81,11 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
 {
     constexpr int OUT = D == 3 ? W * W : W;  // taps owned by thread groups
     constexpr int IN = D == 1 ? 1 : W;       // taps accumulated per thread (last dimension)
+    constexpr int IN2 = D == 3 ? W + 1 : IN; // z accumulators (items of two z cells, d = 3)
     constexpr int PB = 32;                   // points staged per round
     __shared__ real pw[PB][D][W];
     __shared__ real pv[PB][16];
+    __shared__ int pdz[PB];                  // z cell of the point inside the item (d = 3)
 
     const Chunk it = items[blockIdx.x];
     const WinDev &w = wins[it.win];
@@ -84,16 +97,16 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
     const int q = t % OUT, rg = t / OUT;
     const int ox = D == 3 ? q % W : q;
     const int oy = D == 3 ? q / W : 0;
-    int bx, by, bz;
-    unpack_cell(it.tile, bx, by, bz);
+    int bx, by, bz, nzc;
+    unpack_cell(it.tile, bx, by, bz, nzc);
     const int bb[3] = {bx, by, bz};
     const real *coords = (const real *)w.coords;
     const ProbDev pio = get_prob_d(io, w.prob);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
 
-    real acc[IN][RT];
+    real acc[IN2][RT];
 #pragma unroll
-    for (int k = 0; k < IN; ++k)
+    for (int k = 0; k < IN2; ++k)
 #pragma unroll
         for (int i = 0; i < RT; ++i)
             acc[k][i] = real(0);
@@ -104,7 +117,11 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
             const int p = e / (D * W), rem = e - p * (D * W);
             const int dd = rem / W, o = rem - dd * W;
             const real u = coords[dd * w.N + it.start + p0 + p];
-            pw[p][dd][o] = kb_psi_d(u - (real)(bb[dd] + o), mm, kb, ie);
+            // z weights relative to the point's own base cell (bz or bz + 1)
+            const int dz = (D == 3 && dd == 2) ? (int)floor(u) - w.m + 1 - bz : 0;
+            pw[p][dd][o] = kb_psi_d(u - (real)(bb[dd] + dz + o), mm, kb, ie);
+            if (D == 3 && dd == 2 && o == 0)
+                pdz[p] = dz;
         }
         for (int e = t; e < np * RBB; e += blockDim.x) {
             const int p = e / RBB, i = e - p * RBB;
@@ -123,6 +140,14 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
                     acc[0][i] += wo * vv[i];
+            } else if (D == 3 && pdz[p] != 0) {  // the item's second z cell
+#pragma unroll
+                for (int k = 0; k < IN; ++k) {
+                    const real wt = wo * pw[p][D - 1][k];
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+                        acc[k + (D == 3 ? 1 : 0)][i] += wt * vv[i];
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < IN; ++k) {
@@ -139,7 +164,9 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
     real *G = (real *)w.G;
     const int ex = w.ext[0], ey = w.ext[1];
 #pragma unroll
-    for (int k = 0; k < IN; ++k) {
+    for (int k = 0; k < IN2; ++k) {
+        if (k >= IN + nzc - 1)
+            break;
         int x, y, z;
         if (D == 3) {
             x = bx + ox;
@@ -171,7 +198,7 @@ template <typename real, int D, int W, int RB>
 __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
                                                          int R)
 {
-    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    constexpr int NC = dense_block_cells<D, W>();  // block cells (max)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *sub = (real *)smem_raw;
 
@@ -182,15 +209,16 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
         return;
     const int o = blockIdx.z;
     const int nr = min(RB, R - r0);
-    int bx, by, bz;
-    unpack_cell(it.tile, bx, by, bz);
+    int bx, by, bz, nzc;
+    unpack_cell(it.tile, bx, by, bz, nzc);
+    const int ncell = D == 3 ? W * W * (W + nzc - 1) : NC;  // the item's block (z cells bz .. bz + W + nzc - 2)
 
     const real *H = (const real *)w.H;
     const int ex = w.ext[0], ey = w.ext[1];
     const int np = (nr + 1) >> 1;
     const int p0 = r0 >> 1;
-    for (int idx = threadIdx.x; idx < np * NC; idx += kBlock) {
-        const int pi = idx / NC, c = idx - pi * NC;
+    for (int idx = threadIdx.x; idx < np * ncell; idx += kBlock) {
+        const int pi = idx / ncell, c = idx - pi * ncell;
         const int cx = c % W, cy = D > 1 ? (c / W) % W : 0, cz = D > 2 ? c / (W * W) : 0;
         const int64_t off =
             ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)(bz + cz) * ey + by + cy) * ex + bx + cx) * 2;
@@ -214,12 +242,15 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
         for (int k = 0; k < W; ++k)
             wy[k] = kb_psi_d(uy - (real)(by + k), mm, kb, ie);
     }
+    int dz = 0;  // z cell of the point inside the item
     if (D > 2) {
         const real uz = coords[2 * w.N + j];
+        dz = (int)floor(uz) - w.m + 1 - bz;
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            wz[k] = kb_psi_d(uz - (real)(bz + k), mm, kb, ie);
+            wz[k] = kb_psi_d(uz - (real)(bz + dz + k), mm, kb, ie);
     }
+    const real *subz = sub + (D > 2 ? dz * W * W * RB : 0);  // the point's own z window
     real acc[RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -245,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
             real cur[RB], nxt[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
-                cur[i] = sub[ox * RB + i];
+                cur[i] = subz[ox * RB + i];
 #pragma unroll
             for (int oy = 0; oy < W; ++oy) {
                 const real wxy = wxo * wy[oy];
@@ -253,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
                 for (int oz = 0; oz < W; ++oz) {
                     const int tn = oy * W + oz + 1;  // next tap in (oy, oz) order
                     if (tn < W * W) {
-                        const real *s = sub + (ox + W * ((tn / W) + W * (tn % W))) * RB;
+                        const real *s = subz + (ox + W * ((tn / W) + W * (tn % W))) * RB;
 #pragma unroll
                         for (int i = 0; i < RB; ++i)
                             nxt[i] = s[i];
@@ -286,22 +317,22 @@ template <typename real, int D, int W>
 static void spread_dense_w(Engine &E, int R, IoArgs io, hipStream_t st)
 {
     const int OUT = D == 3 ? W * W : W;
+    const Chunk *items = E.d_dense_sp[D][E.cur_dense];
+    const int nitems = E.ndense_sp[D][E.cur_dense];
     if (R == 1) {
-        dim3 grid(E.ndense[D][E.cur_dense], R);
-        hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, E.d_dense[D][E.cur_dense], io,
-                           R, 1);
+        dim3 grid(nitems, R);
+        hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, items, io, R, 1);
         return;
     }
     const int nrg = std::min(4, (R + 3) / 4);
-    dim3 grid(E.ndense[D][E.cur_dense], (R + 4 * nrg - 1) / (4 * nrg));
-    hipLaunchKernelGGL((k_spread_dense<real, D, W, 4>), grid, dim3(OUT * nrg), 0, st, E.d_wins, E.d_dense[D][E.cur_dense],
-                       io, R, nrg);
+    dim3 grid(nitems, (R + 4 * nrg - 1) / (4 * nrg));
+    hipLaunchKernelGGL((k_spread_dense<real, D, W, 4>), grid, dim3(OUT * nrg), 0, st, E.d_wins, items, io, R, nrg);
 }
 
 template <typename real, int D, int W, int RB>
 static void interp_dense_rb(Engine &E, int R, int nout, hipStream_t st)
 {
-    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    constexpr int NC = dense_block_cells<D, W>();
     dim3 grid(E.ndense[D][E.cur_dense], (R + RB - 1) / RB, nout);
     hipLaunchKernelGGL((k_interp_dense<real, D, W, RB>), grid, dim3(kBlock), (size_t)NC * RB * sizeof(real), st,
                        E.d_wins, E.d_dense[D][E.cur_dense], R);
@@ -310,7 +341,7 @@ static void interp_dense_rb(Engine &E, int R, int nout, hipStream_t st)
 template <typename real, int D, int W>
 static void interp_dense_w(Engine &E, int R, int nout, hipStream_t st)
 {
-    constexpr int NC = D == 3 ? W * W * W : (D == 2 ? W * W : W);
+    constexpr int NC = dense_block_cells<D, W>();
     int rbmax = 16;
     while (rbmax > 1 && (size_t)NC * rbmax * sizeof(real) > (size_t)kLdsBudget)
         rbmax >>= 1;

@@ -960,6 +960,8 @@ void engine_free(Engine &E)
         free_dev(E.d_chunks[d]);
         free_dev(E.d_dense[d][0]);
         free_dev(E.d_dense[d][1]);
+        free_dev(E.d_dense_sp[d][0]);
+        free_dev(E.d_dense_sp[d][1]);
     }
     for (int s = 0; s < ST_COUNT; ++s)
         free_dev(E.d_groups[s]);
@@ -1037,7 +1039,7 @@ addk_status engine_build_device(Engine &E, int precision)
     }
     const int L = lines_per_group(precision);
     std::vector<Chunk> ch[4];
-    std::vector<Chunk> dn[4][2];
+    std::vector<Chunk> dn[4][2], dsp[4][2];
     std::vector<LineGroup> gr[ST_COUNT];
     for (int d = 0; d < 4; ++d) {
         E.maxvol[d] = 0;
@@ -1056,6 +1058,11 @@ addk_status engine_build_device(Engine &E, int precision)
             Chunk cc = c;
             cc.win = (int)wi;
             dn[w.d][w.W == 8 ? 0 : 1].push_back(cc);
+        }
+        for (const Chunk &c : h.dense_sp) {
+            Chunk cc = c;
+            cc.win = (int)wi;
+            dsp[w.d][w.W == 8 ? 0 : 1].push_back(cc);
         }
         E.maxvol[w.d] = std::max(E.maxvol[w.d], w.S[0] * w.S[1] * w.S[2]);
         if (!h.chunks.empty()) {
@@ -1085,20 +1092,24 @@ addk_status engine_build_device(Engine &E, int precision)
                 return hip_fail(e, "hipMemcpy(chunks)");
         }
     }
+    auto upload_items = [](const std::vector<Chunk> &v, Chunk *&dptr, int &n) -> addk_status {
+        n = (int)v.size();
+        free_dev(dptr);
+        dptr = nullptr;
+        if (v.empty())
+            return ADDK_OK;
+        hipError_t e = hipMalloc(&dptr, v.size() * sizeof(Chunk));
+        if (e == hipSuccess)
+            e = hipMemcpy(dptr, v.data(), v.size() * sizeof(Chunk), hipMemcpyHostToDevice);
+        return e == hipSuccess ? ADDK_OK : hip_fail(e, "dense item lists");
+    };
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
-            E.ndense[d][wi] = (int)dn[d][wi].size();
-            free_dev(E.d_dense[d][wi]);
-            E.d_dense[d][wi] = nullptr;
-            if (!dn[d][wi].empty()) {
-                hipError_t e = hipMalloc(&E.d_dense[d][wi], dn[d][wi].size() * sizeof(Chunk));
-                if (e != hipSuccess)
-                    return hip_fail(e, "hipMalloc(dense items)");
-                e = hipMemcpy(E.d_dense[d][wi], dn[d][wi].data(), dn[d][wi].size() * sizeof(Chunk),
-                              hipMemcpyHostToDevice);
-                if (e != hipSuccess)
-                    return hip_fail(e, "hipMemcpy(dense items)");
-            }
+            addk_status s = upload_items(dn[d][wi], E.d_dense[d][wi], E.ndense[d][wi]);
+            if (s == ADDK_OK)
+                s = upload_items(dsp[d][wi], E.d_dense_sp[d][wi], E.ndense_sp[d][wi]);
+            if (s != ADDK_OK)
+                return s;
         }
     // base-cell maps and gather tiles for the matrix-core dense spread (d = 3)
     for (WinDev &d : E.wdev)
@@ -1109,7 +1120,7 @@ addk_status engine_build_device(Engine &E, int precision)
         E.d_dmap[wi] = nullptr;
         E.d_gtiles[wi] = nullptr;
         E.ngtiles[wi] = 0;
-        const std::vector<Chunk> &items = dn[3][wi];
+        const std::vector<Chunk> &items = dsp[3][wi];  // the spread items own the blocks
         if (items.empty())
             continue;
         std::vector<int64_t> moff(E.wdev.size(), -1);
@@ -1128,15 +1139,16 @@ addk_status engine_build_device(Engine &E, int precision)
         for (size_t i = 0; i < items.size(); ++i) {
             const Chunk &c = items[i];
             const WinDev &d = E.wdev[c.win];
-            const int bx = c.tile & 1023, by = (c.tile >> 10) & 1023, bz = c.tile >> 20;
+            const int bx = c.tile & 1023, by = (c.tile >> 10) & 1023, bz = (c.tile >> 20) & 1023;
+            const int nzc = ((c.tile >> 30) & 1) + 1;
             int2 &e = map[moff[c.win] + ((int64_t)bz * d.nbase[1] + by) * d.nbase[0] + bx];
             if (e.y == 0)
                 e.x = (int)i;
-            e.y += 1;
+            e.y = ((e.y & 0xffff) + 1) | ((nzc - 1) << 16);  // item count, z cells of the anchor's items
             const int nt0 = (d.ext[0] + 3) / 4, nt1 = (d.ext[1] + 3) / 4, nt2 = (d.ext[2] + 3) / 4;
             if (mark[c.win].empty())
                 mark[c.win].assign((size_t)nt0 * nt1 * nt2, 0);
-            for (int tz = bz / 4; tz <= (bz + d.W - 1) / 4 && tz < nt2; ++tz)
+            for (int tz = bz / 4; tz <= (bz + d.W + nzc - 2) / 4 && tz < nt2; ++tz)
                 for (int ty = by / 4; ty <= (by + d.W - 1) / 4 && ty < nt1; ++ty)
                     for (int tx = bx / 4; tx <= (bx + d.W - 1) / 4 && tx < nt0; ++tx)
                         mark[c.win][((size_t)tz * nt1 + ty) * nt0 + tx] = 1;
@@ -1248,7 +1260,7 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     // per-item blocks of the matrix-core dense spread: items x RHS blocks x (2m)^3 x 16
     for (int wi = 0; wi < 2; ++wi) {
         const int W = wi == 0 ? 8 : 12;
-        const int64_t need = (int64_t)E.ndense[3][wi] * ((rcap + 15) / 16) * W * W * W * 16;
+        const int64_t need = (int64_t)E.ndense_sp[3][wi] * ((rcap + 15) / 16) * (W + 1) * W * W * 16;
         free_dev(E.scratch[wi]);
         E.scratch[wi] = nullptr;
         E.scratch_cap[wi] = 0;
@@ -1396,7 +1408,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
     }
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
-            if (!E.ndense[d][wi])
+            if (!E.ndense_sp[d][wi])
                 continue;
             if (d == 3 && use_mfma(E, ADDK_KNOB_SPREAD_MFMA, R) && E.scratch[wi]) {
                 {

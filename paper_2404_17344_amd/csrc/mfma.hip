@@ -40,11 +40,14 @@ __device__ __forceinline__ float kb_psi_f(float z, float m, float b, float inv_e
     return m * e1 * (1.f - e2) * inv_e2bm * __builtin_amdgcn_rcpf(s);
 }
 
-__device__ __forceinline__ void unpack_cell_m(int packed, int &bx, int &by, int &bz)
+// Dense item anchor: base cell (bx, by, bz) and the number of cells in z
+// (1, or 2 for two z-adjacent dense cells sharing one item).
+__device__ __forceinline__ void unpack_cell_m(int packed, int &bx, int &by, int &bz, int &nzc)
 {
     bx = packed & 1023;
     by = (packed >> 10) & 1023;
-    bz = packed >> 20;
+    bz = (packed >> 20) & 1023;
+    nzc = ((packed >> 30) & 1) + 1;
 }
 
 __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
@@ -165,8 +168,8 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
                                                   float (*slab)[NO][W * W][16], float *wy_lds)
 {
     constexpr int NT = W / 4;  // K steps per x row
-    int bx, by, bz;
-    unpack_cell_m(it.tile, bx, by, bz);
+    int bx, by, bz, nzc;
+    unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
     const float *coords = (const float *)w.coords;
@@ -200,7 +203,10 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W, acc, wxq, wyl, uz, lbz, false);
+    // With two z cells, one of the 2m + 1 slabs lies just outside each point's
+    // window; the window there evaluates to ~2 m b e^{-bm} (< 1e-10), so no mask
+    // is applied in this FP32 kernel.
+    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -249,13 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                                                         IoArgs io, int R, float *__restrict__ scratch)
 {
     constexpr int WW = W * W;
-    constexpr int MT = WW / 16;  // M tiles per z-slab
-    constexpr int SPW = W / 4;   // z-slabs per wave (4 waves)
-    constexpr int PB = 32;       // points per round (8 K steps)
-    constexpr int FL = WW * 17;  // per-wave flush tile [tap][16 RHS + 1 pad]
+    constexpr int MT = WW / 16;        // M tiles (16 taps) per z-slab
+    constexpr int SPW = W / 4;         // z-slabs per wave: slabs wave + 4 s, s < SPW (the first 2m)
+    constexpr int XT = (MT + 3) / 4;   // M tiles per wave of slab 2m (two-cell items only)
+    constexpr int PB = 32;             // points per round (8 K steps)
+    constexpr int FL = WW * 17;        // per-wave flush tile [tap][16 RHS + 1 pad]
+    constexpr int PS = 3 * W + 1;     // window values per point: x [W], y [W], z [W + 1] (item slabs)
     struct Round {
         float pxy[PB][WW];
-        float pw[PB][3][W];
+        float pw[PB][PS];
         float pv[PB][16];
     };
     constexpr int RB_BYTES = 2 * (int)sizeof(Round);
@@ -268,9 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     const int r0 = blockIdx.y * 16;
     if (r0 >= R)
         return;
-    int bx, by, bz;
-    unpack_cell_m(it.tile, bx, by, bz);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int bx, by, bz, nzc;
+    unpack_cell_m(it.tile, bx, by, bz, nzc);
+    const int NS = W + nzc - 1;  // z-slabs of the item's block
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: slab branches are scalar
     const int q = lane >> 4, mrow = lane & 15;
     const float *coords = (const float *)w.coords;
     const ProbDev pio = get_prob_m(io, w.prob);
@@ -278,9 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     const int t = threadIdx.x;
 
     // prefetch registers: the coordinates behind this thread's window values
-    // (entry e = p * 3W + dd * W + o of the round's table, e = t + k * kBlock)
-    // and two RHS values; all threads then share the window evaluations
-    constexpr int NWE = PB * 3 * W;
+    // (entry e = p * PS + o of the round's table, o < W: x, o < 2W: y, else z;
+    // e = t + k * kBlock) and two RHS values; all threads then share the
+    // window evaluations
+    constexpr int NWE = PB * PS;
     constexpr int KW = (NWE + kBlock - 1) / kBlock;
     float pcs[KW];
     float pvv[2] = {0.f, 0.f};
@@ -289,7 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
-            const int p = e / (3 * W), dd = (e / W) % 3;
+            const int p = e / PS, o = e - p * PS;
+            const int dd = o < W ? 0 : (o < 2 * W ? 1 : 2);
             pcs[k] = (e < NWE && p < np) ? coords[dd * w.N + it.start + p0 + p] : 0.f;
         }
 #pragma unroll
@@ -302,14 +314,24 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     };
     auto store_raw = [&](Round &d, int p0) {
         const int np = min(PB, it.count - p0);
-        float *pw = &d.pw[0][0][0];
+        float *pw = &d.pw[0][0];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
             if (e < NWE) {
-                const int p = e / (3 * W), dd = (e / W) % 3, o = e % W;
-                const int b0 = dd == 0 ? bx : (dd == 1 ? by : bz);
-                pw[e] = p < np ? kb_psi_f(pcs[k] - (float)(b0 + o), mm, kb, ie) : 0.f;
+                const int p = e / PS, o = e - p * PS;
+                float v = 0.f;
+                if (o < 2 * W) {
+                    const int dd = o < W ? 0 : 1;
+                    v = kb_psi_f(pcs[k] - (float)((dd == 0 ? bx : by) + o - dd * W), mm, kb, ie);
+                } else {
+                    // z slab oz of the item: inside the point's own window only
+                    const int oz = o - 2 * W;
+                    const int dz = (int)floorf(pcs[k]) - w.m + 1 - bz;
+                    if ((unsigned)(oz - dz) < (unsigned)W)
+                        v = kb_psi_f(pcs[k] - (float)(bz + oz), mm, kb, ie);
+                }
+                pw[e] = p < np ? v : 0.f;
             }
         }
 #pragma unroll
@@ -321,16 +343,21 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     auto products = [&](Round &d) {
         for (int e = t; e < PB * WW; e += kBlock) {
             const int p = e / WW, c = e - p * WW;
-            d.pxy[p][c] = d.pw[p][0][c % W] * d.pw[p][1][c / W];
+            d.pxy[p][c] = d.pw[p][c % W] * d.pw[p][W + c / W];
         }
     };
 
-    f4 acc[SPW][MT];
+    // wave `wave` owns slabs wave + 4 s of the first 2m and, for two-cell
+    // items, the M tiles wave + 4 j of slab 2m
+    f4 acc[SPW][MT], accx[XT];
 #pragma unroll
     for (int s = 0; s < SPW; ++s)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
             acc[s][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < XT; ++j)
+        accx[j] = f4{0.f, 0.f, 0.f, 0.f};
 
     load(0);
     store_raw(rd[0], 0);
@@ -349,11 +376,21 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             const float b = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const float wz = cr.pw[pk][2][wave + 4 * s];
+                const float wz = cr.pw[pk][2 * W + wave + 4 * s];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const float a = cr.pxy[pk][mt * 16 + mrow] * wz;
                     acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[s][mt], 0, 0, 0);
+                }
+            }
+            {
+                // slab 2m: zero weights for single-cell items (outside every window)
+                const float wz = cr.pw[pk][3 * W];
+#pragma unroll
+                for (int j = 0; j < XT; ++j) {
+                    const int mt = min(wave + 4 * j, MT - 1);
+                    const float a = cr.pxy[pk][mt * 16 + mrow] * wz;
+                    accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, accx[j], 0, 0, 0);
                 }
             }
         }
@@ -367,9 +404,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     }
 
     // write the item's block [oz][oy][ox][16 RHS] to its scratch slot (plain
-    // stores; the blocks of all items are summed by k_gather_blocks)
+    // stores; the blocks of all items are summed by k_gather_blocks), each
+    // slab (or M tile of slab 2m) through a per-wave LDS transpose
     float *fl = (float *)lds + wave * FL;
-    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * (W * WW * 16);
+    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
+    auto wsync = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int oz = wave + 4 * s;
@@ -378,18 +421,30 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 fl[(mt * 16 + 4 * q + i) * 17 + mrow] = acc[s][mt][i];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wsync();
         float *ds = dst + (int64_t)oz * WW * 16;
         for (int idx = lane; idx < WW * 4; idx += 64) {
             const int tap = idx >> 2, r4 = (idx & 3) * 4;
             const float *src = fl + tap * 17 + r4;
             *(f4 *)(ds + tap * 16 + r4) = f4{src[0], src[1], src[2], src[3]};
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wsync();
+    }
+    if (NS > W) {
+#pragma unroll
+        for (int j = 0; j < XT; ++j) {
+            const int mt = wave + 4 * j;
+            if (mt >= MT)
+                break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                fl[(4 * q + i) * 17 + mrow] = accx[j][i];
+            wsync();
+            const int tap = lane >> 2, r4 = (lane & 3) * 4;
+            const float *src = fl + tap * 17 + r4;
+            *(f4 *)(dst + ((int64_t)W * WW + mt * 16 + tap) * 16 + r4) = f4{src[0], src[1], src[2], src[3]};
+            wsync();
+        }
     }
 }
 
@@ -406,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
 {
     constexpr int WW = W * W;
     __shared__ f4 red[3][64][4];
-    __shared__ int2 cand[(W + 3) * (W + 3) * (W + 3)];  // base-cell map of the candidate region
+    __shared__ int2 cand[(W + 3) * (W + 3) * (W + 4)];  // base-cell map of the candidate region
     const LineGroup tg = tiles[blockIdx.x];
     const WinDev &w = wins[tg.win];
     const int rb = blockIdx.y;
@@ -426,7 +481,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-    const int z0 = max(0, tz * 4 - (W - 1)), z1 = min(nb2 - 1, tz * 4 + 3);
+    // anchors: an item anchored at bz covers z cells bz .. bz + 2m - 2 + (nzc - 1)
+    const int z0 = max(0, tz * 4 - W), z1 = min(nb2 - 1, tz * 4 + 3);
     const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
     const int x0 = max(0, tx * 4 - (W - 1)), x1 = min(nb0 - 1, tx * 4 + 3);
     const bool any = x1 >= x0 && y1 >= y0 && z1 >= z0;
@@ -446,11 +502,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
                 const int2 it = crow[dx];
                 if (it.y == 0)
                     continue;
+                const int cnt = it.y & 0xffff, nzc = (it.y >> 16) + 1;
                 const int ox = gx - x0 - dx;
-                if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W && (unsigned)oz < (unsigned)W) {
+                if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
+                    (unsigned)oz < (unsigned)(W + nzc - 1)) {
                     const int tap = (oz * W + oy) * W + ox;
-                    for (int i = it.x; i < it.x + it.y; ++i) {
-                        const f4 *src = (const f4 *)(scratch + (((int64_t)i * nrb + rb) * (W * WW) + tap) * 16);
+                    for (int i = it.x; i < it.x + cnt; ++i) {
+                        const f4 *src = (const f4 *)(scratch + (((int64_t)i * nrb + rb) * ((W + 1) * WW) + tap) * 16);
                         acc[0] += src[0];
                         acc[1] += src[1];
                         acc[2] += src[2];
@@ -607,14 +665,14 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
 
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
-    if (E.precision != ADDK_FP32 || !E.ndense[3][wi] || !E.scratch[wi])
+    if (E.precision != ADDK_FP32 || !E.ndense_sp[3][wi] || !E.scratch[wi])
         return false;
-    dim3 grid(E.ndense[3][wi], (R + 15) / 16);
+    dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16);
     if (wi == 0)
-        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R,
+        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R,
                            E.scratch[wi]);
     else
-        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[3][wi], io, R,
+        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R,
                            E.scratch[wi]);
     return true;
 }

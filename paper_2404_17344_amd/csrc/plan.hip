@@ -625,6 +625,7 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         return fail(ADDK_ERR_OOM, "point arrays allocation failed");
     w.chunks.clear();
     w.dense.clear();
+    w.dense_sp.clear();
     if (N == 0)
         return ADDK_OK;
     void *ucoord = nullptr;
@@ -695,19 +696,36 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
             w.chunks.push_back({0, (int32_t)t, (int32_t)s, (int32_t)std::min<int64_t>(kChunk, pos - s)});
         const int tx = (int)(t % w.ntile[0]), ty = (int)((t / w.ntile[0]) % w.ntile[1]),
                   tz = (int)(t / ((int64_t)w.ntile[0] * w.ntile[1]));
-        for (int64_t c = 0; c < cpt; ++c) {
-            const int cnt = h[k0 + c];
-            if (!(dense_ok && cnt >= kDenseMin))
-                continue;
-            off[k0 + c] = (int32_t)pos;
-            const int cx = (int)(c % w.tb[0]), cy = (int)((c / w.tb[0]) % w.tb[1]),
-                      cz = (int)(c / ((int64_t)w.tb[0] * w.tb[1]));
-            const int bx = tx * w.tb[0] + cx, by = ty * w.tb[1] + cy, bz = tz * w.tb[2] + cz;
-            const int packed = bx | (by << 10) | (bz << 20);
-            for (int s = 0; s < cnt; s += kDenseChunk)
-                w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
-            pos += cnt;
-            w.ndense_pts += cnt;
+        // dense cells of the tile, z fastest; for d = 3 two dense cells adjacent
+        // in z form one item (their points consecutive), whose window block is
+        // (2m) x (2m) x (2m + 1): half the blocks of single cells
+        const bool isdense_any = dense_ok;
+        auto is_dense = [&](int64_t c) { return isdense_any && h[k0 + c] >= kDenseMin; };
+        for (int64_t cxy = 0; cxy < (int64_t)w.tb[0] * w.tb[1]; ++cxy) {
+            for (int cz = 0; cz < w.tb[2]; ++cz) {
+                const int64_t c = cxy + (int64_t)cz * w.tb[0] * w.tb[1];
+                if (!is_dense(c))
+                    continue;
+                const int64_t c2 = c + (int64_t)w.tb[0] * w.tb[1];
+                const int nzc = (w.d == 3 && cz + 1 < w.tb[2] && is_dense(c2)) ? 2 : 1;
+                const int cx = (int)(cxy % w.tb[0]), cy = (int)(cxy / w.tb[0]);
+                const int bx = tx * w.tb[0] + cx, by = ty * w.tb[1] + cy, bz = tz * w.tb[2] + cz;
+                const int packed = bx | (by << 10) | (bz << 20) | ((nzc - 1) << 30);
+                int cnt = 0;
+                for (int k = 0; k < nzc; ++k) {
+                    const int64_t ck = c + (int64_t)k * w.tb[0] * w.tb[1];
+                    off[k0 + ck] = (int32_t)(pos + cnt);
+                    cnt += h[k0 + ck];
+                }
+                for (int s = 0; s < cnt; s += kDenseChunk)
+                    w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
+                const int spc = w.d == 3 ? kSpreadChunk : kDenseChunk;
+                for (int s = 0; s < cnt; s += spc)
+                    w.dense_sp.push_back({0, packed, (int32_t)(pos + s), std::min(spc, cnt - s)});
+                pos += cnt;
+                w.ndense_pts += cnt;
+                cz += nzc - 1;
+            }
         }
     }
     e = hipMemcpy(hist, off.data(), nkeys * sizeof(int32_t), hipMemcpyHostToDevice);

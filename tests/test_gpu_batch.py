@@ -51,8 +51,10 @@ def test_uneven_batch_full_size_graph_autotuned(A):
     _say("uneven batch: autotune")
     knobs = B.autotune(reps=2)
     assert 0 <= knobs <= A.ADDK_KNOB_ALL_MFMA
-    # Replays and eager runs agree to FP32 rounding: the d = 1, 2 dense-cell
-    # spread sums with atomics, so the FP32 summation order varies run to run.
+    # Replays and eager runs agree to FP32 rounding (within the FP32 tolerance):
+    # the d = 1, 2 dense-cell and the sparse-tile spreads sum with atomics, so
+    # the FP32 summation order varies run to run.  A graph that reused stale
+    # buffers would be off by O(1).
     B.launch()
     torch.cuda.synchronize()
     first = [y.cpu().numpy().copy() for y in B.outputs()]
@@ -60,12 +62,12 @@ def test_uneven_batch_full_size_graph_autotuned(A):
         B.launch()
         torch.cuda.synchronize()
         for y0, y in zip(first, B.outputs()):
-            assert relerr(y.cpu().numpy(), y0) < 5e-6
+            assert relerr(y.cpu().numpy(), y0) < 1e-5
     B.run_eager()
     torch.cuda.synchronize()
     outs = [y.cpu().numpy() for y in B.outputs()]
     for y0, y in zip(first, outs):
-        assert relerr(y, y0) < 5e-6
+        assert relerr(y, y0) < 1e-5
     _say("uneven batch: oracle rows")
     rng = np.random.default_rng(44)
     for p, y in zip(probs, outs):
