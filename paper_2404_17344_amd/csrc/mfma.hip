@@ -373,24 +373,23 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 #pragma unroll
         for (int ks = 0; ks < PB / 4; ++ks) {
             const int pk = 4 * ks + q;
-            const float b = cr.pv[pk][mrow];
+            // the point's z weight of the slab scales the B operand (its RHS
+            // values), so the A operand is the plain x-y weight product
+            const float v = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const float wz = cr.pw[pk][2 * W + wave + 4 * s];
+                const float b = v * cr.pw[pk][2 * W + wave + 4 * s];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const float a = cr.pxy[pk][mt * 16 + mrow] * wz;
-                    acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[s][mt], 0, 0, 0);
-                }
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pxy[pk][mt * 16 + mrow], b, acc[s][mt], 0, 0, 0);
             }
             {
                 // slab 2m: zero weights for single-cell items (outside every window)
-                const float wz = cr.pw[pk][3 * W];
+                const float b = v * cr.pw[pk][3 * W];
 #pragma unroll
                 for (int j = 0; j < XT; ++j) {
                     const int mt = min(wave + 4 * j, MT - 1);
-                    const float a = cr.pxy[pk][mt * 16 + mrow] * wz;
-                    accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, accx[j], 0, 0, 0);
+                    accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pxy[pk][mt * 16 + mrow], b, accx[j], 0, 0, 0);
                 }
             }
         }
