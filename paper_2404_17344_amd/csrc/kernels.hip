@@ -374,13 +374,47 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
 // line FFTs in LDS (radix-2 Stockham), pruned to the box and to the kept modes
 
 // Each wave transforms its own L / 4 lines, so the passes only need the
-// wave to be in step (no block barrier between passes).
+// wave to be in step (no block barrier between passes).  Stockham passes of
+// radix 4 (a 4-point DFT in registers per butterfly), then one radix-2 pass
+// when log2(nos) is odd.  tw holds e^{2 pi i q / nos} for q < nos / 2; the
+// other half of the circle is its negative.
 template <typename real>
 __device__ cpx<real> *fft_lines(cpx<real> *a, cpx<real> *b, const cpx<real> *tw, int nos, int L, real sign)
 {
-    const int h = nos >> 1;
+    const int h = nos >> 1, qn = nos >> 2;
     const int lane = threadIdx.x & 63, lpw = L / (kBlock / 64), l0 = (threadIdx.x >> 6) * lpw;
-    for (int Ns = 1; Ns < nos; Ns <<= 1) {
+    auto twid = [&](int q) -> cpx<real> {  // e^{sign 2 pi i q / nos}, 0 <= q < nos
+        const cpx<real> c = q < h ? tw[q] : cpx<real>{-tw[q - h].x, -tw[q - h].y};
+        return {c.x, sign * c.y};
+    };
+    auto cmul = [](cpx<real> x, cpx<real> c) -> cpx<real> { return {x.x * c.x - x.y * c.y, x.x * c.y + x.y * c.x}; };
+    int Ns = 1;
+    for (; Ns * 4 <= nos; Ns <<= 2) {
+        for (int t = lane; t < lpw * qn; t += 64) {
+            const int l = l0 + t / qn, j = t - (t / qn) * qn;
+            const int k = j & (Ns - 1);
+            const int step = k * (qn / Ns);  // twiddle index unit of this butterfly
+            cpx<real> x0 = a[l * nos + j], x1 = a[l * nos + j + qn], x2 = a[l * nos + j + 2 * qn],
+                      x3 = a[l * nos + j + 3 * qn];
+            if (Ns > 1) {
+                x1 = cmul(x1, twid(step));
+                x2 = cmul(x2, twid(2 * step));
+                x3 = cmul(x3, twid(3 * step));
+            }
+            const cpx<real> a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = csub(x1, x3);
+            const cpx<real> ja3 = {-sign * a3.y, sign * a3.x};  // (sign i) a3
+            const int idx = ((j - k) << 2) + k;
+            b[l * nos + idx] = cadd(a0, a2);
+            b[l * nos + idx + Ns] = cadd(a1, ja3);
+            b[l * nos + idx + 2 * Ns] = csub(a0, a2);
+            b[l * nos + idx + 3 * Ns] = csub(a1, ja3);
+        }
+        wave_sync();
+        cpx<real> *s = a;
+        a = b;
+        b = s;
+    }
+    for (; Ns < nos; Ns <<= 1) {  // at most one radix-2 pass
         for (int t = lane; t < lpw * h; t += 64) {
             const int l = l0 + t / h, j = t - (t / h) * h;
             const cpx<real> x0 = a[l * nos + j], x1 = a[l * nos + j + h];
