@@ -14,5 +14,9 @@ Contents
                 sum of eq. (6) evaluated by brute force, the error bounds of
                 Theorems 1-2 / Remarks 1-2, and the global sensitivity
                 indices of Algorithm 1.
+``nearfield`` -- the near-field corrected product for the Matern-1/2 kernel:
+                image-free folded torus, Taylor-joint inner regularisation,
+                coefficients of the regularised kernel by a DFT of samples,
+                trigonometric sum plus a direct sum over close pairs.
 """
 from .direct import oracle_direct, oracle_vjp, oracle_threads, build_oracle, lib_path  # noqa: F401
