@@ -16,6 +16,14 @@ Printed as one JSON line, with
                  the timed region) against the FP32 vector peak,
   cpu_baseline : the FP64 CPU oracle timed on a bounded sample of output rows,
   accuracy     : FP32 result vs the FP64 GPU path and vs the oracle rows.
+
+``--workload matern-near-field`` measures the near-field corrected Matern-1/2
+product instead: the derivative workload's shape (N = 1e5 points, D = 9 N(0,1)
+features min-max scaled, 3 windows d = 3, l = (0.05, 0.1, 0.2), R = 1, n = 64,
+m = 6), one ``addk_dmatvec`` (K v, dK/dl_w v, dK/dsigma_w v) per step; its
+roofline is the close-pair kernel's, with the close pairs counted by brute
+force (FP64 distances on the device) and 47 + 4R flop per pair (distance, square root, exponential, two
+degree-8 polynomials in r^2, 2R multiply-adds).
 """
 from __future__ import annotations
 
@@ -33,7 +41,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "kernel matvecs/s and ∂K/∂ℓ matvecs/s at N=1e6, 5×d=3 windows, at rel err ≤1e-5"
+METRIC_MATERN = "Matérn-1/2 kernel matvecs/s and ∂K/∂ℓ, ∂K/∂σ matvecs/s at N=1e5, 3×d=3 windows, at rel err ≤1e-5"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def relerr_cols(a: np.ndarray, b: np.ndarray) -> float:
@@ -89,6 +99,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration) and exit")
+    ap.add_argument("--workload", choices=["large", "matern-near-field"], default="large")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="precision of the matern-near-field workload (the large one is FP32)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,6 +127,8 @@ def main():
     import workloads as WL
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "matern-near-field":
+        return matern_main(args, A, WL, torch)
     dev = torch.device("cuda:0")
     log("generating inputs")
     p = WL.large_c5(N=args.N)
@@ -230,6 +245,118 @@ def main():
                    "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "oversampling": p.oversampling,
                    "step": "addk_dmatvec: K V and dK/dl_w V, all windows",
                    "precision": "FP32 spread/FFT/interp, FP64 multipliers and window sums"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "stage_avg_ms": stage_ms,
+        "plan_ms": round(plan_ms, 2),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def matern_main(args, A, WL, torch):
+    """The near-field corrected Matern-1/2 product on the derivative workload's shape."""
+    dev = torch.device("cuda:0")
+    N = args.N if args.N != 1000000 else 100000
+    log("generating inputs (matern, N=%d)" % N)
+    p = WL.derivative_c3(N=N, kernel=WL.MATERN12)
+    R, P = p.R, p.P
+    V = torch.from_numpy(np.ascontiguousarray(p.V.T)).to(dev).t()
+    torch.cuda.synchronize()
+    log("plan (%s, near field)" % args.precision)
+    t0 = time.perf_counter()
+    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, kernel="matern12", n=p.n, m=p.m, oversampling=p.oversampling,
+                  precision=args.precision, near_field=True)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+
+    def step():
+        return plan.dmatvec(V, want_y=True, want_dell=True, want_dsigma=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        out = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    stages = plan.profile_read()
+    plan.profile(False)
+    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
+
+    # close pairs (ordered, the diagonal included) within each window's radius
+    # 5 T_w / n, counted with plain FP64 distances in row blocks
+    log("counting close pairs")
+    T = plan.query()["T"]
+    pairs = 0
+    for w, feats in enumerate(p.windows):
+        Xw = torch.from_numpy(np.ascontiguousarray(p.X[:, feats])).to(dev)
+        r2 = (5.0 * T[w] / p.n) ** 2
+        for s in range(0, N, 2048):
+            D2 = ((Xw[s:s + 2048, None, :] - Xw[None, :, :]) ** 2).sum(-1)
+            pairs += int((D2 < r2).sum().item())
+            del D2
+    flop_pair = 47 + 4 * R
+    tot_ms, launches = stages["near"]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = pairs * flop_pair / (avg_ms * 1e-3) / 1e12
+    peak = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    roofline = {"bound": "alu", "kernel": "near", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_flop_per_launch": pairs * flop_pair, "close_pairs": pairs}
+
+    Y = out[0].cpu().numpy()
+    dl = out[1].cpu().numpy()
+    ds = out[2].cpu().numpy()
+    cpu, accuracy = None, {}
+    if not args.no_cpu_baseline:
+        from oracle.direct import oracle_direct, oracle_threads
+        rng = np.random.default_rng(17343)
+        probe = rng.choice(N, 64, replace=False)
+        oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe[:8], want_derivs=True)
+        t0 = time.perf_counter()
+        oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe, want_derivs=True)
+        t_probe = time.perf_counter() - t0
+        nrows = int(min(max(64, 64 * args.cpu_seconds / max(t_probe, 1e-3)), N))
+        rows = rng.choice(N, nrows, replace=False)
+        t0 = time.perf_counter()
+        Yo, dlo, dso = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=rows, want_derivs=True)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(R * (nrows / N) / t_cpu, 6), "unit": "matvecs/s", "cores": oracle_threads(),
+               "kind": "oracle",
+               "sample": "%d of %d output rows, all 3 windows, 1 RHS, K v, dK/dl_w v and dK/dsigma_w v, FP64 "
+                         "direct sums; %.1f s; rate scaled by N/rows" % (nrows, N, t_cpu)}
+        if not args.no_accuracy:
+            accuracy["rel_err_Y_vs_oracle_rows"] = relerr_cols(Y[rows], Yo)
+            accuracy["rel_err_dY_dell_vs_oracle_rows"] = max(relerr_cols(dl[w][rows], dlo[w]) for w in range(P))
+            accuracy["rel_err_dY_dsigma_vs_oracle_rows"] = max(relerr_cols(ds[w][rows], dso[w]) for w in range(P))
+            accuracy["oracle_rows"] = nrows
+    result = {
+        "metric": METRIC_MATERN,
+        "value": round(R / (ms_per_step * 1e-3), 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "derivative Matern-1/2, near-field corrected: N=%d, D=9 N(0,1) features min-max "
+                               "scaled, 3 windows d=3, l=(0.05, 0.1, 0.2), sigma=1, R=1, n=64, m=6, oversampling 2"
+                               % N,
+                   "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "step": "addk_dmatvec: K v, dK/dl_w v, dK/dsigma_w v",
+                   "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,

@@ -74,6 +74,27 @@ typedef enum {
                                      kernels); same results up to rounding, for comparison     */
 #define ADDK_VECTOR_ALU_ONLY 16u  /* FP32 plans: run the dense-cell kernels on the vector ALUs
                                      instead of the matrix cores; for comparison              */
+#define ADDK_NEAR_FIELD 32u       /* ADDK_MATERN12 only: near-field corrected products (below) */
+
+/*
+ * ADDK_NEAR_FIELD.  The Matern-1/2 kernel has a cusp at r = 0, so its
+ * truncated Fourier series alone stays near 1e-2 (relative) at n = 64.  With
+ * this flag (regularisation for non-smooth kernels in NFFT-based fast
+ * summation, which the kernel extension of section 5 builds on):
+ *  - each window's torus period is T_w = 5 L_w / 2 and the periodic kernel has
+ *    no images: per coordinate, x^2 is replaced by a smooth even T-periodic
+ *    fold that equals x^2 on [-L_w, L_w];
+ *  - inside r < eps_w = 5 T_w / n the kernel (and the derivative kernel) is
+ *    replaced by the even polynomial of degree 16 that matches its value and
+ *    first 8 derivatives at eps_w; the Fourier multipliers are those of this
+ *    regularised kernel (DFT of (2n)^d samples);
+ *  - pairs closer than eps_w are summed directly with kernel minus polynomial.
+ * Every product (matvec, dmatvec, vjp, batches, targets, CG) then agrees with
+ * the direct sum to about 1e-5 relative or better.  The direct part costs
+ * O(N x neighbours within eps_w).  Errors: UNSUPPORTED with ADDK_GAUSSIAN,
+ * with ADDK_COEF_SAMPLED or ADDK_TORUS_PAPER, for n < 16, and in addk_gsi
+ * (whose variances are defined by the plain Fourier series).
+ */
 
 typedef struct addk_plan_s *addk_plan;
 typedef struct addk_batch_s *addk_batch;
@@ -97,7 +118,8 @@ typedef struct addk_batch_s *addk_batch;
  *  oversampling     sigma = n_os / n; n_os = round(sigma * n) must be a power
  *                   of two in [16, 128] and exceed n.
  *  precision        ADDK_FP64 or ADDK_FP32.
- *  flags            ADDK_COEF_* | ADDK_TORUS_* | ADDK_NO_ACCURACY_CHECK.
+ *  flags            ADDK_COEF_* | ADDK_TORUS_* | ADDK_NO_ACCURACY_CHECK |
+ *                   ADDK_TILE_KERNELS_ONLY | ADDK_VECTOR_ALU_ONLY | ADDK_NEAR_FIELD.
  *  stream           stream used for the set-up kernels.
  * Errors: INVALID_ARG (bad sizes/values/pointers), UNSUPPORTED (d_w > 3,
  * n_os outside [16,128] or not a power of two, data extent plus window wider
@@ -274,12 +296,12 @@ addk_status addk_batch_destroy(addk_batch batch);
  * read, and clears them.  Stage ids: see addk_stage_name (0 .. ADDK_NSTAGES-1).
  * Errors: INVALID_ARG (NULL plan), HIP.
  */
-#define ADDK_NSTAGES 13
+#define ADDK_NSTAGES 14
 addk_status addk_plan_profile(addk_plan plan, int32_t enable);
 addk_status addk_plan_profile_read(addk_plan plan, double *total_ms, int32_t *launches);
 /* "zero", "spread", "fft_x_fwd", "fft_y_fwd", "fft_fused", "fft_y_inv",
  * "fft_x_inv", "interp", "combine", "mode_dot", "spread_dense", "interp_dense",
- * "gather"; NULL for other ids.  Spreading and interpolation run in two kernels: tile
+ * "gather", "near"; NULL for other ids.  Spreading and interpolation run in two kernels: tile
  * kernels for sparsely populated cells and dense-cell kernels. */
 const char *addk_stage_name(int32_t stage);
 

@@ -11,7 +11,8 @@ near-field part, summed directly over close pairs (the regularisation of
 NFFT-based fast summation that the paper builds on; the paper gives no
 formulas for it, so every choice below is this implementation's reading):
 
-* Torus.  T = (5/2) L for a window whose points span at most L per coordinate.
+* Torus.  T = (5/2) L for a window whose points span at most L per coordinate
+  (L replaced by l when all points coincide, L = 0).
   The kernel is made T-periodic without images: each coordinate's square x^2
   is replaced by s(x) = x^2 (1 - h) + (T - x)^2 h on [0, T), with h a smooth
   step rising from 0 at x = L to 1 at x = T - L.  s is even and T-periodic,
@@ -46,9 +47,16 @@ FOLD_RATIO = 2.5      # T = FOLD_RATIO * L
 SAMPLE_FACTOR = 2     # M = SAMPLE_FACTOR * n samples per axis
 
 
+def fold_width(L: float, ell: float) -> float:
+    """Half-width L_f of the unfolded region: L, or l for a window of identical
+    points (L = 0), so that the near-field radius 5 T / n = 12.5 L_f / n stays
+    inside the unfolded region for n >= 16."""
+    return L if L > 0.0 else ell
+
+
 def near_period(L: float, ell: float) -> float:
-    """Torus period of a near-field window (L = 0: any period works; take 5 l / 2)."""
-    return FOLD_RATIO * (L if L > 0.0 else ell)
+    """Torus period of a near-field window: T = 5 L_f / 2."""
+    return FOLD_RATIO * fold_width(L, ell)
 
 
 def near_radius(T: float, n: int) -> float:
@@ -165,16 +173,17 @@ def nearfield_fast_sum_oracle(X: np.ndarray, windows: Sequence[Sequence[int]], e
         Xw = np.asarray(X, dtype=np.float64)[:, list(feats)]
         d = Xw.shape[1]
         c, L = window_geometry(Xw)
+        Lf = fold_width(L, ell[w])
         T = near_period(L, ell[w])
         eps = near_radius(T, n)
         xt = (Xw - c) / T
-        ck = coeffs_regularised(ell[w], T, L, n, d)
+        ck = coeffs_regularised(ell[w], T, Lf, n, d)
         kv = np.stack([trig_sum(ck, xt, V[:, r]) for r in range(R)], axis=1)
         kv += near_field_sum(Xw, V, ell[w], eps, False)
         Y += sigma[w] ** 2 * kv
         ds[w] = 2.0 * sigma[w] * kv
         if want_derivs:
-            cd = coeffs_regularised(ell[w], T, L, n, d, der=True)
+            cd = coeffs_regularised(ell[w], T, Lf, n, d, der=True)
             kd = np.stack([trig_sum(cd, xt, V[:, r]) for r in range(R)], axis=1)
             kd += near_field_sum(Xw, V, ell[w], eps, True)
             dl[w] = sigma[w] ** 2 * der_scale(MATERN12, ell[w]) * kd

@@ -30,7 +30,8 @@ ADDK_TORUS_PAPER = 2
 ADDK_NO_ACCURACY_CHECK = 4
 ADDK_TILE_KERNELS_ONLY = 8
 ADDK_VECTOR_ALU_ONLY = 16
-ADDK_NSTAGES = 13
+ADDK_NEAR_FIELD = 32
+ADDK_NSTAGES = 14
 ADDK_KNOB_SPREAD_MFMA = 1
 ADDK_KNOB_INTERP_DENSE_MFMA = 2
 ADDK_KNOB_INTERP_TILE_MFMA = 4

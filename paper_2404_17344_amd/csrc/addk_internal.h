@@ -43,6 +43,9 @@ constexpr int kMfmaMinR = 8;     // fewest RHS for which the matrix-core dense k
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).
+constexpr int kNearQ = 8;        // matched derivatives of the near-field polynomial
+constexpr int kNearChunk = 256;  // targets per near-field block
+
 struct WinDev {
     int d, n, n1, nos, m, W, prob, flags;
     int64_t N;
@@ -67,6 +70,13 @@ struct WinDev {
     const int2 *dmap;    // base cell -> {first, count} of its dense items in the engine's
                          // matrix-core item list (d = 3 only), or nullptr
     const void *tw;      // twiddles e^{2 pi i q / nos}, q < nos / 2 (complex real)
+    // near-field correction (Matern-1/2 with ADDK_NEAR_FIELD; nf = 0 otherwise)
+    int nf;
+    double nf_eps2;      // radius^2 in grid units^2
+    double nf_inv_eps2;
+    double nf_hl;        // (data units per grid unit) / l: r / l = sqrt(d2) * nf_hl
+    double nf_a[kNearQ + 1], nf_ad[kNearQ + 1];  // even polynomials in (r / eps) of kernel and derivative kernel
+    const int32_t *tile_off;  // tile t's points are [tile_off[t], tile_off[t + 1]) of the sorted order
 };
 
 // Problem-level input/output pointers (one per plan inside a batch).
@@ -117,12 +127,20 @@ struct WinHost {
                                 // the packed base cell
     std::vector<Chunk> dense_sp;  // the same runs for spreading, <= kSpreadChunk points each
     int64_t ndense_pts = 0;
+    // near-field correction
+    bool nf = false;
+    double nf_eps = 0.0;                          // radius in data units
+    double nf_Lf = 0.0;                           // half-width of the unfolded region (L, or l if L = 0)
+    double nf_a[kNearQ + 1], nf_ad[kNearQ + 1];
+    std::vector<int32_t> tile_off;                // host copy (ntiles + 1)
+    int32_t *d_tile_off = nullptr;
 };
 
 struct Plan;
 
 enum ProfStage { PS_ZERO = 0, PS_SPREAD, PS_FFT_X_FWD, PS_FFT_Y_FWD, PS_FFT_FUSED, PS_FFT_Y_INV, PS_FFT_X_INV,
-                 PS_INTERP, PS_COMBINE, PS_MODE_DOT, PS_SPREAD_DENSE, PS_INTERP_DENSE, PS_GATHER, PS_COUNT };
+                 PS_INTERP, PS_COMBINE, PS_MODE_DOT, PS_SPREAD_DENSE, PS_INTERP_DENSE, PS_GATHER, PS_NEAR,
+                 PS_COUNT };
 
 struct ProfRec {
     int stage;
@@ -144,6 +162,11 @@ struct Engine {
     int ndense[4][2] = {};
     Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)
     int ndense_sp[4][2] = {};
+    Chunk *d_near[4] = {};         // near-field target blocks per d (tile field = tile index)
+    int nnear[4] = {};
+    std::vector<int2> near_rng;    // per window: [first, end) of its blocks in the list of its d
+    double *d_near_part = nullptr; // near-field inner-product partials
+    int64_t near_part_cap = 0;
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)
     bool no_mfma = false;          // use the vector-ALU dense kernels only
@@ -232,6 +255,11 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
 void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st);
 bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st);
+
+// nearfield.hip (ADDK_NEAR_FIELD)
+void launch_near(Engine &E, int R, int nout, IoArgs io, hipStream_t st);
+addk_status engine_near_dot(Engine &E, int R, IoArgs io, const double *V, int64_t ldv, double *grad_ell,
+                            double *grad_sig, hipStream_t st);
 
 // plan.hip
 addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);

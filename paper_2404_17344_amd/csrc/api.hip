@@ -273,8 +273,12 @@ addk_status addk_vjp(addk_plan plan, int32_t R, const double *V, int64_t ldv, co
         return s;
     if (grad_V && (s = engine_combine(pl.eng, R, 1, io, st)) != ADDK_OK)
         return s;
-    if (scalars)
-        return engine_mode_dot(pl.eng, (R + 1) / 2, grad_ell, grad_sigma, st);
+    if (scalars) {
+        s = engine_mode_dot(pl.eng, (R + 1) / 2, grad_ell, grad_sigma, st);
+        if (s == ADDK_OK)
+            s = engine_near_dot(pl.eng, R, io, V, ldv, grad_ell, grad_sigma, st);  // close pairs of V and G
+        return s;
+    }
     return ADDK_OK;
 }
 
@@ -286,6 +290,9 @@ addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *strea
         return fail2(ADDK_ERR_INVALID_ARG, "theta is NULL");
     Plan &pl = *(Plan *)plan;
     std::memset(theta, 0, sizeof(double) * 8 * pl.P);
+    if (pl.flags & ADDK_NEAR_FIELD)
+        return fail2(ADDK_ERR_UNSUPPORTED, "addk_gsi: the variances are those of the plain Fourier series; create "
+                                           "the plan without ADDK_NEAR_FIELD");
     if (pl.N == 0)
         return ADDK_OK;
     addk_status s;
@@ -338,7 +345,7 @@ const char *addk_stage_name(int32_t stage)
 {
     static const char *names[PS_COUNT] = {"zero",      "spread",    "fft_x_fwd", "fft_y_fwd",    "fft_fused",
                                           "fft_y_inv", "fft_x_inv", "interp",    "combine",      "mode_dot",
-                                          "spread_dense", "interp_dense", "gather"};
+                                          "spread_dense", "interp_dense", "gather",       "near"};
     if (stage < 0 || stage >= PS_COUNT)
         return nullptr;
     return names[stage];

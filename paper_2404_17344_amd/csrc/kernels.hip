@@ -1010,6 +1010,14 @@ void engine_free(Engine &E)
     }
     free_dev(E.vpack);
     free_dev(E.d_tw);
+    for (int d = 1; d <= 3; ++d) {
+        free_dev(E.d_near[d]);
+        E.d_near[d] = nullptr;
+        E.nnear[d] = 0;
+    }
+    free_dev(E.d_near_part);
+    E.d_near_part = nullptr;
+    E.near_part_cap = 0;
     for (const ProfRec &r : E.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1137,6 +1145,27 @@ addk_status engine_build_device(Engine &E, int precision)
             e = hipMemcpy(dptr, v.data(), v.size() * sizeof(Chunk), hipMemcpyHostToDevice);
         return e == hipSuccess ? ADDK_OK : hip_fail(e, "dense item lists");
     };
+    // near-field target blocks: runs of <= kNearChunk sorted points of one tile
+    {
+        std::vector<Chunk> nl[4];
+        E.near_rng.assign(E.wdev.size(), make_int2(0, 0));
+        for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
+            const WinHost &h = E.plans[E.wplan[wi]]->wins[E.wlocal[wi]];
+            if (!h.nf || h.tile_off.empty())
+                continue;
+            std::vector<Chunk> &l = nl[h.d];
+            E.near_rng[wi].x = (int)l.size();
+            for (int64_t t = 0; t < h.ntiles; ++t)
+                for (int32_t s = h.tile_off[t]; s < h.tile_off[t + 1]; s += kNearChunk)
+                    l.push_back({(int32_t)wi, (int32_t)t, s, std::min<int32_t>(kNearChunk, h.tile_off[t + 1] - s)});
+            E.near_rng[wi].y = (int)l.size();
+        }
+        for (int d = 1; d <= 3; ++d) {
+            addk_status s = upload_items(nl[d], E.d_near[d], E.nnear[d]);
+            if (s != ADDK_OK)
+                return s;
+        }
+    }
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
             addk_status s = upload_items(dn[d][wi], E.d_dense[d][wi], E.ndense[d][wi]);
@@ -1506,6 +1535,10 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
                         continue;
                     launch_interp_dense(E, d, wi, R, nout, st);
                 }
+            if (E.nnear[1] || E.nnear[2] || E.nnear[3]) {
+                StageTimer t(E, PS_NEAR, st);
+                launch_near(E, R, nout, io, st);
+            }
         }
     }
     hipError_t e = hipGetLastError();

@@ -1,0 +1,370 @@
+// Near-field part of the corrected Matern-1/2 products (ADDK_NEAR_FIELD).
+//
+// The Fourier part of such a plan uses the multipliers of the regularised
+// kernel, which differs from the true kernel only for pairs closer than eps:
+// there, the kernel's cusp at r = 0 is replaced by an even polynomial p.  This
+// file adds the difference back by summing K_NE(r) = kappa(r) - p(r) over the
+// pairs with r < eps, for kappa = e^{-r/l} and for the derivative kernel
+// (r/l) e^{-r/l} with its own polynomial (eq. (4) restricted to close pairs).
+//
+// Layout.  The plan sorted every window's points by tile (a box of base cells
+// of the spreading grid); the points of tile t are the range
+// [tile_off[t], tile_off[t+1]) of the sorted order, coordinates in grid units.
+// A block takes up to 256 consecutive sorted points (targets, one per thread,
+// all in one tile), bounds them by a box, and walks the rows of tiles (along
+// x, contiguous in the sorted order) whose boxes come within eps of it.  The
+// sources of a row are staged in LDS 256 at a time (coordinates and the
+// point-major right-hand sides) and read by all threads as broadcasts.  Each
+// target is owned by one thread, which adds its sums to the window's product
+// buffer after the interpolation has written it, in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "addk_internal.h"
+
+namespace addk {
+
+namespace {
+
+__device__ __forceinline__ ProbDev nf_prob(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
+
+__device__ __forceinline__ float nf_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double nf_exp(double x) { return exp(x); }
+
+template <typename real>
+__device__ __forceinline__ real horner(const real *a, real t2)
+{
+    real p = a[kNearQ];
+#pragma unroll
+    for (int k = kNearQ - 1; k >= 0; --k)
+        p = p * t2 + a[k];
+    return p;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// DOT = false: Yw[o][i][r0 + r] += sum_j K_NE,o(ij) Vp[j][r0 + r], o < NO
+//               (o = 0 kernel, o = 1 derivative kernel).
+// DOT = true:  partial[(blockIdx.x * gridDim.y + blockIdx.y) * 2 + o] =
+//               sum over the block's targets i of sum_j K_NE,o(ij) <Vt_i, Vp_j>
+//               (RHS r0 .. r0 + RT - 1), Vt_i read from the caller's V.
+template <typename real, int D, int RT, int NO, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
+                                                 IoArgs io, int R, const double *__restrict__ Vt, int64_t ldvt,
+                                                 double *__restrict__ partial)
+{
+    __shared__ real sc[kBlock][4];          // source coordinates (grid units)
+    __shared__ real sv[kBlock][RT];         // source right-hand sides
+    __shared__ float red[4][6];
+    __shared__ double dred[4][2];
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int r0 = blockIdx.y * RT;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const ProbDev pio = nf_prob(io, w.prob);
+    const real *coords = (const real *)w.coords;
+    const bool own = t < ch.count;
+    const int64_t i = ch.start + (own ? t : 0);
+    real u[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        u[a] = coords[(int64_t)a * w.N + i];
+    // box of the block's targets
+    float bmin[3] = {0.f, 0.f, 0.f}, bmax[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        float lo = wave_min(own ? (float)u[a] : 3.0e38f);
+        float hi = wave_max(own ? (float)u[a] : -3.0e38f);
+        if (lane == 0) {
+            red[wave][a] = lo;
+            red[wave][3 + a] = hi;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        bmin[a] = fminf(fminf(red[0][a], red[1][a]), fminf(red[2][a], red[3][a]));
+        bmax[a] = fmaxf(fmaxf(red[0][3 + a], red[1][3 + a]), fmaxf(red[2][3 + a], red[3][3 + a]));
+    }
+    const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
+    const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;  // slightly generous for the box tests
+    real pa[kNearQ + 1], pd[kNearQ + 1];
+#pragma unroll
+    for (int k = 0; k <= kNearQ; ++k) {
+        pa[k] = (real)w.nf_a[k];
+        pd[k] = (real)w.nf_ad[k];
+    }
+    // tile range per axis: the coordinates are relative to the grid box, and the
+    // base cell of a point u is floor(u) - m + 1
+    int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
+    bool none = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int nb = w.ext[a] - w.W + 1;
+        const int b0 = max(0, (int)floorf(bmin[a] - eg) - w.m + 1);
+        const int b1 = min(nb - 1, (int)floorf(bmax[a] + eg) - w.m + 1);
+        none = none || b1 < b0;
+        t0[a] = b0 / w.tb[a];
+        t1[a] = min(w.ntile[a] - 1, b1 / w.tb[a]);
+    }
+    // targets' values (DOT) and accumulators
+    real vt[RT];
+    real acc[NO][RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        vt[r] = real(0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+            acc[o][r] = real(0);
+    }
+    real sk = real(0), sd = real(0);
+    if (DOT && own) {
+        const int orig = w.perm[i];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+            vt[r] = r0 + r < R ? (real)Vt[orig + (int64_t)(r0 + r) * ldvt] : real(0);
+    }
+    const real *vp = (const real *)pio.Vp;
+    const int32_t *toff = w.tile_off;
+    if (!none) {
+        for (int tz = t0[2]; tz <= t1[2]; ++tz) {
+            for (int ty = t0[1]; ty <= t1[1]; ++ty) {
+                // distance of the target box to the row's box in y and z
+                float g2 = 0.f;
+                if (D > 1) {
+                    const float rlo = (float)(ty * w.tb[1] + w.m - 1);
+                    const float rhi = rlo + (float)w.tb[1];
+                    const float g = fmaxf(0.f, fmaxf(rlo - bmax[1], bmin[1] - rhi));
+                    g2 += g * g;
+                }
+                if (D > 2) {
+                    const float rlo = (float)(tz * w.tb[2] + w.m - 1);
+                    const float rhi = rlo + (float)w.tb[2];
+                    const float g = fmaxf(0.f, fmaxf(rlo - bmax[2], bmin[2] - rhi));
+                    g2 += g * g;
+                }
+                if (g2 >= eg * eg)
+                    continue;
+                const int64_t trow = ((int64_t)tz * w.ntile[1] + ty) * w.ntile[0];
+                const int s = toff[trow + t0[0]], e = toff[trow + t1[0] + 1];
+                for (int b = s; b < e; b += kBlock) {
+                    __syncthreads();
+                    const int j = b + t;
+                    if (j < e) {
+#pragma unroll
+                        for (int a = 0; a < D; ++a)
+                            sc[t][a] = coords[(int64_t)a * w.N + j];
+                        const int64_t orig = w.perm[j];
+#pragma unroll
+                        for (int r = 0; r < RT; ++r)
+                            sv[t][r] = vp[orig * pio.ldvp + r0 + r];
+                    }
+                    __syncthreads();
+                    const int nsrc = min(kBlock, e - b);
+                    for (int jj = 0; jj < nsrc; ++jj) {
+                        real d2 = real(0);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            const real dx = u[a] - sc[jj][a];
+                            d2 += dx * dx;
+                        }
+                        if (d2 < eps2) {
+                            const real rl = sqrt(d2) * hl;
+                            const real ex = nf_exp(-rl);
+                            const real t2 = d2 * ie2;
+                            const real kn = ex - horner(pa, t2);
+                            const real kd = (NO > 1 || DOT) ? rl * ex - horner(pd, t2) : real(0);
+                            if (DOT) {
+                                real dot = real(0);
+#pragma unroll
+                                for (int r = 0; r < RT; ++r)
+                                    dot += vt[r] * sv[jj][r];
+                                sk += kn * dot;
+                                sd += kd * dot;
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < RT; ++r) {
+                                    const real v = sv[jj][r];
+                                    acc[0][r] += kn * v;
+                                    if (NO > 1)
+                                        acc[NO > 1 ? 1 : 0][r] += kd * v;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (DOT) {
+        double a0 = own ? (double)sk : 0.0, a1 = own ? (double)sd : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+        }
+        if (lane == 0) {
+            dred[wave][0] = a0;
+            dred[wave][1] = a1;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double *pp = partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * 2;
+            pp[0] = (dred[0][0] + dred[1][0]) + (dred[2][0] + dred[3][0]);
+            pp[1] = (dred[0][1] + dred[1][1]) + (dred[2][1] + dred[3][1]);
+        }
+        return;
+    }
+    if (!own)
+        return;
+    const int64_t orig = w.perm[i];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        double *dst = w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+            if (r0 + r < R)
+                dst[r] += (double)acc[o][r];
+    }
+}
+
+// Per window: grad_ell += der_scale * sum of the derivative partials,
+// grad_sig += dsig * sum of the kernel partials (fixed order).
+__global__ void k_near_dot_finish(const WinDev *__restrict__ wins, int win, const double *partial, int nblk,
+                                  double *grad_ell, double *grad_sig)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double sk = 0.0, sd = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        sk += partial[2 * b];
+        sd += partial[2 * b + 1];
+    }
+    const WinDev &w = wins[win];
+    if (grad_ell)
+        grad_ell[0] += w.der_scale * sd;
+    if (grad_sig)
+        grad_sig[0] += w.dsig * sk;
+}
+
+int near_rt(int R) { return R == 1 ? 1 : (R <= 4 ? 4 : 16); }
+
+template <typename real, int D, int RT, bool DOT>
+void launch_near_rt(Engine &E, int R, int nout, IoArgs io, const double *Vt, int64_t ldvt, double *partial,
+                    hipStream_t st)
+{
+    dim3 grid(E.nnear[D], (R + RT - 1) / RT);
+    if (DOT)
+        hipLaunchKernelGGL((k_near<real, D, RT, 2, true>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
+                           Vt, ldvt, partial);
+    else if (nout > 1)
+        hipLaunchKernelGGL((k_near<real, D, RT, 2, false>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
+                           Vt, ldvt, partial);
+    else
+        hipLaunchKernelGGL((k_near<real, D, RT, 1, false>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
+                           Vt, ldvt, partial);
+}
+
+template <typename real, int D, bool DOT>
+void launch_near_d(Engine &E, int R, int nout, IoArgs io, const double *Vt, int64_t ldvt, double *partial,
+                   hipStream_t st)
+{
+    switch (near_rt(R)) {
+    case 1: launch_near_rt<real, D, 1, DOT>(E, R, nout, io, Vt, ldvt, partial, st); break;
+    case 4: launch_near_rt<real, D, 4, DOT>(E, R, nout, io, Vt, ldvt, partial, st); break;
+    default: launch_near_rt<real, D, 16, DOT>(E, R, nout, io, Vt, ldvt, partial, st); break;
+    }
+}
+
+template <bool DOT>
+void launch_near_all(Engine &E, int R, int nout, IoArgs io, const double *Vt, int64_t ldvt, double *const *part,
+                     hipStream_t st)
+{
+    for (int d = 1; d <= 3; ++d) {
+        if (!E.nnear[d])
+            continue;
+        double *p = part ? part[d] : nullptr;
+        if (E.precision == ADDK_FP32) {
+            if (d == 1) launch_near_d<float, 1, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+            if (d == 2) launch_near_d<float, 2, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+            if (d == 3) launch_near_d<float, 3, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+        } else {
+            if (d == 1) launch_near_d<double, 1, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+            if (d == 2) launch_near_d<double, 2, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+            if (d == 3) launch_near_d<double, 3, DOT>(E, R, nout, io, Vt, ldvt, p, st);
+        }
+    }
+}
+
+}  // namespace
+
+void launch_near(Engine &E, int R, int nout, IoArgs io, hipStream_t st)
+{
+    if (nout < 1)
+        return;
+    launch_near_all<false>(E, R, std::min(nout, 2), io, nullptr, 0, nullptr, st);
+}
+
+addk_status engine_near_dot(Engine &E, int R, IoArgs io, const double *V, int64_t ldv, double *grad_ell,
+                            double *grad_sig, hipStream_t st)
+{
+    const int ny = (R + near_rt(R) - 1) / near_rt(R);
+    int64_t need = 0;
+    for (int d = 1; d <= 3; ++d)
+        need += (int64_t)E.nnear[d] * ny * 2;
+    if (need == 0)
+        return ADDK_OK;
+    if (E.near_part_cap < need) {
+        if (E.d_near_part)
+            (void)hipFree(E.d_near_part);
+        E.d_near_part = nullptr;
+        E.near_part_cap = 0;
+        hipError_t e = hipMalloc(&E.d_near_part, need * sizeof(double));
+        if (e != hipSuccess)
+            return hip_fail(e, "near-field partials");
+        E.near_part_cap = need;
+    }
+    double *part[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t off = 0;
+    for (int d = 1; d <= 3; ++d) {
+        part[d] = E.d_near_part + off;
+        off += (int64_t)E.nnear[d] * ny * 2;
+    }
+    if (!io.table) {
+        io.single.Vp = E.vpack;
+        io.single.ldvp = E.vpack_ld;
+    }
+    launch_near_all<true>(E, R, 2, io, V, ldv, part, st);
+    for (int wi = 0; wi < (int)E.wdev.size(); ++wi) {
+        const WinDev &w = E.wdev[wi];
+        const int2 rg = E.near_rng[wi];
+        if (!w.nf || rg.y <= rg.x)
+            continue;
+        const double *p = part[w.d] + (int64_t)rg.x * ny * 2;
+        hipLaunchKernelGGL(k_near_dot_finish, dim3(1), dim3(64), 0, st, E.d_wins, wi, p, (rg.y - rg.x) * ny,
+                           grad_ell ? grad_ell + E.wlocal[wi] : nullptr, grad_sig ? grad_sig + E.wlocal[wi] : nullptr);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return hip_fail(e, "near-field launch");
+    return ADDK_OK;
+}
+
+}  // namespace addk

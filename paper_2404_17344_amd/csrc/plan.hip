@@ -142,6 +142,80 @@ static double torus_period(int kernel, double L, double ell, int n, uint32_t rul
     return L + ell * std::log((double)n);
 }
 
+// ---------------------------------------------------------------------------
+// Near-field correction of the Matern-1/2 kernel (ADDK_NEAR_FIELD).  The cusp
+// of exp(-r/l) at r = 0 is moved into a compactly supported near-field kernel
+// summed directly over close pairs; the rest is smooth and periodic and goes
+// through the Fourier method:
+//   period      T = 5 L / 2 (L by l if all points coincide), with each coordinate's square x^2 replaced by a
+//               fold s(x) = x^2 (1 - h) + (T - x)^2 h on [0, T) (h: degree-7
+//               smoothstep from x = L to x = T - L), so that the periodic
+//               kernel equals the true one for every difference of two points;
+//   radius      eps = 5 T / n;
+//   polynomial  p(r) = sum_j a_j (r / eps)^(2j), j <= 8, with the value and the
+//               first 8 derivatives of the kernel at eps;
+//   near field  K_NE(r) = kappa(r) - p(r) for r < eps, 0 beyond;
+//   multipliers DFT of (2n)^d samples of kappa(sqrt(sum_i s(x_i))) - K_NE(|x|).
+// The derivative kernel (r/l) e^{-r/l} gets its own polynomial.
+constexpr double kNearFold = 2.5;
+constexpr double kNearRadius = 5.0;  // in units of T / n
+
+// Half-width of the unfolded region: L, or l when all points coincide (L = 0),
+// so that the radius 5 T / n = 12.5 L_f / n stays inside it for n >= 16.
+static double near_fold_width(double L, double ell) { return L > 0.0 ? L : ell; }
+
+// Solve sum_j a_j C(2j, s) = eps^s kappa^(s)(eps) / s!, s = 0..q (the Taylor
+// conditions at t = r / eps = 1, rows divided by s!), by Gaussian elimination
+// with partial pivoting.  kappa^(s)(r) = (-1/l)^s e^{-r/l} for exp(-r/l) and
+// (-1/l)^s e^{-r/l} (r - s l) / l for (r/l) e^{-r/l}.
+static void near_poly(double ell, double eps, bool der, double *a)
+{
+    constexpr int Q = kNearQ + 1;
+    double A[Q][Q + 1];
+    double fact = 1.0;
+    for (int s = 0; s < Q; ++s) {
+        if (s > 0)
+            fact *= s;
+        for (int j = 0; j < Q; ++j) {
+            double c = 0.0;  // binomial C(2j, s)
+            if (s <= 2 * j) {
+                c = 1.0;
+                for (int i = 0; i < s; ++i)
+                    c = c * (2 * j - i) / (i + 1);
+            }
+            A[s][j] = c;
+        }
+        const double e = std::exp(-eps / ell) * std::pow(-eps / ell, (double)s);
+        A[s][Q] = (der ? e * (eps - s * ell) / ell : e) / fact;
+    }
+    for (int c = 0; c < Q; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < Q; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c]))
+                piv = r;
+        for (int k = 0; k <= Q; ++k)
+            std::swap(A[c][k], A[piv][k]);
+        for (int r = c + 1; r < Q; ++r) {
+            const double f = A[r][c] / A[c][c];
+            for (int k = c; k <= Q; ++k)
+                A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int c = Q - 1; c >= 0; --c) {
+        double v = A[c][Q];
+        for (int k = c + 1; k < Q; ++k)
+            v -= A[c][k] * a[k];
+        a[c] = v / A[c][c];
+    }
+}
+
+static void near_setup(WinHost &w, int n)
+{
+    w.nf_eps = kNearRadius * w.T / n;
+    near_poly(w.ell, w.nf_eps, false, w.nf_a);
+    near_poly(w.ell, w.nf_eps, true, w.nf_ad);
+}
+
 // A-priori relative error estimate of one window: image + truncation + window terms.
 static double error_estimate(int kernel, double L, double T, double ell, int n, int m, double sig)
 {
@@ -328,6 +402,50 @@ __global__ void k_samples(double2 *s, int d, int n, double T, double ell, int ke
     }
 }
 
+struct NearPoly {
+    double a[kNearQ + 1];
+};
+
+// Samples of the regularised near-field kernel at T j / M, j in I_M^d (array
+// index j + M/2, axis 0 fastest): kappa(sqrt(sum_i s(x_i))) - K_NE(|x|) with
+// the folded squares s and K_NE(r) = kappa(r) - p(r) for r < eps.
+__global__ void k_samples_near(double2 *s, int d, int M, double T, double L, double ell, double eps, NearPoly p,
+                               int der)
+{
+    int64_t tot = M;
+    for (int i = 1; i < d; ++i)
+        tot *= M;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = idx;
+        double sf = 0.0, r2 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            const int j = (int)(r % M) - M / 2;
+            r /= M;
+            const double ax = fabs(T * j / M);
+            r2 += ax * ax;
+            if (ax <= L) {
+                sf += ax * ax;
+            } else {
+                const double t = (ax - L) / (T - 2.0 * L);
+                const double h = t * t * t * t * (35.0 - 84.0 * t + 70.0 * t * t - 20.0 * t * t * t);
+                sf += ax * ax * (1.0 - h) + (T - ax) * (T - ax) * h;
+            }
+        }
+        const double rf = sqrt(sf);
+        double v = der ? rf / ell * exp(-rf / ell) : exp(-rf / ell);
+        const double r0 = sqrt(r2);
+        if (r0 < eps) {
+            const double t2 = r2 / (eps * eps);
+            double q = p.a[kNearQ];
+            for (int k = kNearQ - 1; k >= 0; --k)
+                q = q * t2 + p.a[k];
+            const double k0 = der ? r0 / ell * exp(-r0 / ell) : exp(-r0 / ell);
+            v -= k0 - q;
+        }
+        s[idx] = make_double2(v, 0.0);
+    }
+}
+
 // out_k = sum_j in_j exp(-2 pi i j k / n) along one axis; j, k in I_n (index + n/2)
 __global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, int n, int axis)
 {
@@ -354,7 +472,9 @@ __global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, 
     }
 }
 
-__global__ void k_coef_from_hat(const double2 *__restrict__ chat, double *B, int d, int n,
+// B_k for k in {-n/2..n/2}^d from the DFT c^ of M^d samples (M >= n; k is
+// read at index k + M/2 of each axis, c^ being M-periodic in k)
+__global__ void k_coef_from_hat(const double2 *__restrict__ chat, double *B, int d, int n, int M,
                                 const double *__restrict__ psi)
 {
     const int n1 = n + 1, half = n / 2;
@@ -363,7 +483,7 @@ __global__ void k_coef_from_hat(const double2 *__restrict__ chat, double *B, int
         tot *= n1;
     double scale = 1.0;
     for (int i = 0; i < d; ++i)
-        scale /= n;
+        scale /= M;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * blockDim.x) {
         int k[3] = {0, 0, 0};
         int64_t r = idx, hidx = 0, hs = 1;
@@ -372,9 +492,9 @@ __global__ void k_coef_from_hat(const double2 *__restrict__ chat, double *B, int
             const int c = (int)(r % n1);
             r /= n1;
             k[i] = c - half;
-            const int kk = k[i] == half ? -half : k[i];  // c^ is n-periodic in k
-            hidx += (int64_t)(kk + half) * hs;
-            hs *= n;
+            const int kk = k[i] == M / 2 ? -M / 2 : k[i];  // c^ is M-periodic in k
+            hidx += (int64_t)(kk + M / 2) * hs;
+            hs *= M;
             dec /= psi[c] * psi[c];
         }
         B[idx] = herm_weight(k, d, half) * dec * scale * chat[hidx].x;
@@ -411,6 +531,8 @@ static hipError_t free_win_arrays(WinHost &w)
         f(w.Bd);
     f(w.Bk64);
     f(w.Bd64);
+    f(w.d_tile_off);
+    w.d_tile_off = nullptr;
     w.coords = nullptr;
     w.perm = nullptr;
     w.Bk = w.Bd = nullptr;
@@ -450,7 +572,36 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
             }
         }
         const int nb = (int)std::min<int64_t>((tot + 255) / 256, 1024);
-        if (pl.flags & ADDK_COEF_SAMPLED) {
+        if (w.nf) {
+            const int M = 2 * pl.n;
+            const int64_t ns = ipow(M, w.d);
+            double2 *s0 = nullptr, *s1 = nullptr;
+            if ((e = hipMalloc(&s0, ns * sizeof(double2))) != hipSuccess ||
+                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess) {
+                (void)hipFree(s0);
+                return fail(ADDK_ERR_OOM, "sample buffer allocation failed");
+            }
+            const int nbs = (int)std::min<int64_t>((ns + 255) / 256, 4096);
+            for (int der = 0; der < 2; ++der) {
+                NearPoly p;
+                for (int j = 0; j <= kNearQ; ++j)
+                    p.a[j] = der ? w.nf_ad[j] : w.nf_a[j];
+                hipLaunchKernelGGL(k_samples_near, dim3(nbs), dim3(256), 0, st, s0, w.d, M, w.T, w.nf_Lf, w.ell,
+                                   w.nf_eps, p, der);
+                double2 *a = s0, *bb = s1;
+                for (int ax = 0; ax < w.d; ++ax) {
+                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, M, ax);
+                    std::swap(a, bb);
+                }
+                hipLaunchKernelGGL(k_coef_from_hat, dim3(nb), dim3(256), 0, st, a, der ? w.Bd64 : w.Bk64, w.d,
+                                   pl.n, M, pl.d_psi);
+            }
+            e = hipStreamSynchronize(st);
+            (void)hipFree(s0);
+            (void)hipFree(s1);
+            if (e != hipSuccess)
+                return hip_fail(e, "near-field multipliers");
+        } else if (pl.flags & ADDK_COEF_SAMPLED) {
             const int64_t ns = ipow(pl.n, w.d);
             double2 *s0 = nullptr, *s1 = nullptr;
             if ((e = hipMalloc(&s0, ns * sizeof(double2))) != hipSuccess ||
@@ -465,7 +616,7 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
                     std::swap(a, bb);
                 }
                 hipLaunchKernelGGL(k_coef_from_hat, dim3(nb), dim3(256), 0, st, a, der ? w.Bd64 : w.Bk64, w.d,
-                                   pl.n, pl.d_psi);
+                                   pl.n, pl.n, pl.d_psi);
             }
             e = hipStreamSynchronize(st);
             (void)hipFree(s0);
@@ -503,6 +654,22 @@ static bool is_device_ptr(const void *p)
     return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
 }
 
+static void fill_near(const Plan &pl, const WinHost &w, WinDev &d)
+{
+    d.nf = w.nf ? 1 : 0;
+    d.tile_off = w.d_tile_off;
+    if (!w.nf)
+        return;
+    const double eg = w.nf_eps * pl.nos / w.T;  // radius in grid units
+    d.nf_eps2 = eg * eg;
+    d.nf_inv_eps2 = 1.0 / (eg * eg);
+    d.nf_hl = w.T / pl.nos / w.ell;
+    for (int j = 0; j <= kNearQ; ++j) {
+        d.nf_a[j] = w.nf_a[j];
+        d.nf_ad[j] = w.nf_ad[j];
+    }
+}
+
 static void fill_windesc(const Plan &pl, const WinHost &w, int prob, WinDev &d)
 {
     std::memset(&d, 0, sizeof(d));
@@ -530,6 +697,7 @@ static void fill_windesc(const Plan &pl, const WinHost &w, int prob, WinDev &d)
     d.perm = w.perm;
     d.Bk = w.Bk;
     d.Bd = w.Bd;
+    fill_near(pl, w, d);
 }
 
 static addk_status build_plan_engine(Plan &pl)
@@ -587,7 +755,12 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         L = std::max(L, mx[dd] - mn[dd]);
     }
     w.L = L;
-    w.T = torus_period(pl.kernel, L, w.ell, pl.n, pl.flags & ADDK_TORUS_PAPER, dmax);
+    w.nf = (pl.flags & ADDK_NEAR_FIELD) != 0;
+    if (w.nf)
+        w.nf_Lf = near_fold_width(L, w.ell);
+    w.T = w.nf ? kNearFold * w.nf_Lf : torus_period(pl.kernel, L, w.ell, pl.n, pl.flags & ADDK_TORUS_PAPER, dmax);
+    if (w.nf)
+        near_setup(w, pl.n);
     w.eta = M_PI * pl.n * w.ell / (std::sqrt(2.0) * w.T);
     if (w.eta < 1.0 && !(pl.flags & ADDK_NO_ACCURACY_CHECK))
         return fail(ADDK_ERR_ACCURACY, "window length scale too small for the grid: eta = pi n l / (sqrt2 T) = " +
@@ -624,6 +797,9 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         (e = hipMalloc(&w.perm, std::max<int64_t>(1, N) * sizeof(int32_t))) != hipSuccess)
         return fail(ADDK_ERR_OOM, "point arrays allocation failed");
     w.chunks.clear();
+    w.tile_off.clear();
+    if (w.nf)
+        w.tile_off.assign(w.ntiles + 1, 0);
     w.dense.clear();
     w.dense_sp.clear();
     if (N == 0)
@@ -687,6 +863,8 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     for (int64_t t = 0; t < w.ntiles; ++t) {
         const int64_t k0 = t * cpt;
         const int64_t s0 = pos;
+        if (w.nf)
+            w.tile_off[t] = (int32_t)s0;
         for (int64_t c = 0; c < cpt; ++c)
             if (!(dense_ok && h[k0 + c] >= kDenseMin)) {
                 off[k0 + c] = (int32_t)pos;
@@ -727,6 +905,14 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
                 cz += nzc - 1;
             }
         }
+    }
+    if (w.nf) {
+        w.tile_off[w.ntiles] = (int32_t)pos;
+        e = hipMalloc(&w.d_tile_off, (w.ntiles + 1) * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(w.d_tile_off, w.tile_off.data(), (w.ntiles + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_fail(e, "near-field tile ranges");
     }
     e = hipMemcpy(hist, off.data(), nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess)
@@ -848,8 +1034,17 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
     if (precision != ADDK_FP64 && precision != ADDK_FP32)
         return fail(ADDK_ERR_INVALID_ARG, "precision must be ADDK_FP64 or ADDK_FP32");
     if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK | ADDK_TILE_KERNELS_ONLY |
-                  ADDK_VECTOR_ALU_ONLY))
+                  ADDK_VECTOR_ALU_ONLY | ADDK_NEAR_FIELD))
         return fail(ADDK_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ADDK_NEAR_FIELD) {
+        if (kernel != ADDK_MATERN12)
+            return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD applies to the Matern-1/2 kernel only");
+        if (flags & (ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER))
+            return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD sets its own period and multipliers (no "
+                                              "ADDK_COEF_SAMPLED / ADDK_TORUS_PAPER)");
+        if (n < 16)
+            return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD needs n >= 16");
+    }
     if (n < 4 || (n & 1))
         return fail(ADDK_ERR_INVALID_ARG, "n must be even and >= 4");
     if (m < 2 || m > kMaxW / 2)
@@ -1034,6 +1229,8 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
         pl.wins[w].ell = ell[w];
         pl.wins[w].sigma = sigma[w];
         pl.wins[w].eta = M_PI * pl.n * ell[w] / (std::sqrt(2.0) * pl.wins[w].T);
+        if (pl.wins[w].nf)
+            near_setup(pl.wins[w], pl.n);  // T and the radius stay, the polynomials follow l
     }
     addk_status s = plan_compute_multipliers(pl, (hipStream_t)stream);
     if (s != ADDK_OK)
@@ -1043,6 +1240,7 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
         d.sig2 = sigma[w] * sigma[w];
         d.der_scale = d.sig2 * (pl.kernel == ADDK_GAUSSIAN ? 2.0 / ell[w] : 1.0 / ell[w]);
         d.dsig = 2.0 * sigma[w];
+        fill_near(pl, pl.wins[w], d);
     }
     pl.eng.dirty = true;
     return engine_upload(pl.eng);

@@ -126,3 +126,29 @@ def test_choose_n_refuses_unreachable_tolerance():
         A.choose_n(F.GAUSSIAN, 0.5, 0.01, m=6, oversampling=2.0, tol=1e-5)
     with pytest.raises(A.AddkError):
         A.choose_n(F.GAUSSIAN, 0.5, 0.1, m=2, oversampling=2.0, tol=1e-12)
+
+
+def test_near_field_flag_is_validated_before_any_device_work():
+    """ADDK_NEAR_FIELD: refused for the Gaussian, with sampled coefficients or
+    the paper's torus rule, and for n < 16; these checks run on the host."""
+    import ctypes
+    L = _lib()
+    lib = L.load()
+    X = np.zeros((2, 2))
+    off = (ctypes.c_int32 * 2)(0, 2)
+    feat = (ctypes.c_int32 * 2)(0, 1)
+    ell = np.array([0.1])
+    sig = np.array([1.0])
+
+    def create(kernel, n, flags):
+        h = ctypes.c_void_p()
+        return lib.addk_plan_create(ctypes.byref(h), 2, 2, X.ctypes.data, 2, 1, off, feat, kernel,
+                                    ell.ctypes.data_as(L._pd), sig.ctypes.data_as(L._pd), n, 2, 2.0, L.ADDK_FP64,
+                                    flags, None)
+    nf = L.ADDK_NEAR_FIELD
+    assert create(L.ADDK_GAUSSIAN, 32, nf) == L.ADDK_ERR_UNSUPPORTED
+    assert create(L.ADDK_MATERN12, 32, nf | L.ADDK_COEF_SAMPLED) == L.ADDK_ERR_UNSUPPORTED
+    assert create(L.ADDK_MATERN12, 32, nf | L.ADDK_TORUS_PAPER) == L.ADDK_ERR_UNSUPPORTED
+    assert create(L.ADDK_MATERN12, 8, nf) == L.ADDK_ERR_UNSUPPORTED
+    assert create(L.ADDK_MATERN12, 32, 1 << 20) == L.ADDK_ERR_INVALID_ARG
+    assert lib.addk_stage_name(L.ADDK_NSTAGES - 1).decode() == "near"

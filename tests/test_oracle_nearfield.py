@@ -95,3 +95,16 @@ def test_nearfield_fast_sum_matches_direct(wins, ell):
     # and the plain scheme is far off on the same problem
     Yp = F.fast_sum_oracle(X, wins, F.MATERN12, [ell] * P, sig, V, 64)
     assert rel(Yp, Yd) > 1e-3
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_coincident_points(d):
+    """All points equal (L = 0): every kernel value is kappa(0) = 1, so
+    K v = (sum_j v_j) for every row and the derivative kernel (r/l) e^{-r/l}
+    vanishes, up to the method's error at n = 64 (measured 3e-7 and 8e-7 of
+    sum |v| for d = 1, 3; 5e-6 for the derivative kernel)."""
+    X = np.tile(np.array([[0.1, -0.05, 0.2]])[:, :d], (4, 1))
+    V = np.array([[1.0], [-0.5], [2.0], [0.25]])
+    Y, dl, _ = NF.nearfield_fast_sum_oracle(X, [list(range(d))], [0.1], [1.0], V, 64, want_derivs=True)
+    np.testing.assert_allclose(Y, np.full((4, 1), V.sum()), rtol=0, atol=2e-6 * abs(V).sum())
+    assert np.abs(dl).max() < 1e-5 * abs(V).sum()
