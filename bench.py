@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--workload", choices=["large", "matern-near-field"], default="large")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="precision of the matern-near-field workload (the large one is FP32)")
+    ap.add_argument("--n", type=int, default=64, help="bandwidth of the matern-near-field workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -265,7 +266,8 @@ def matern_main(args, A, WL, torch):
     torch.cuda.synchronize()
     log("plan (%s, near field)" % args.precision)
     t0 = time.perf_counter()
-    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, kernel="matern12", n=p.n, m=p.m, oversampling=p.oversampling,
+    n = args.n
+    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, kernel="matern12", n=n, m=p.m, oversampling=p.oversampling,
                   precision=args.precision, near_field=True)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -299,7 +301,7 @@ def matern_main(args, A, WL, torch):
     pairs = 0
     for w, feats in enumerate(p.windows):
         Xw = torch.from_numpy(np.ascontiguousarray(p.X[:, feats])).to(dev)
-        r2 = (5.0 * T[w] / p.n) ** 2
+        r2 = (5.0 * T[w] / n) ** 2
         for s in range(0, N, 2048):
             D2 = ((Xw[s:s + 2048, None, :] - Xw[None, :, :]) ** 2).sum(-1)
             pairs += int((D2 < r2).sum().item())
@@ -353,9 +355,9 @@ def matern_main(args, A, WL, torch):
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "derivative Matern-1/2, near-field corrected: N=%d, D=9 N(0,1) features min-max "
-                               "scaled, 3 windows d=3, l=(0.05, 0.1, 0.2), sigma=1, R=1, n=64, m=6, oversampling 2"
-                               % N,
-                   "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "step": "addk_dmatvec: K v, dK/dl_w v, dK/dsigma_w v",
+                               "scaled, 3 windows d=3, l=(0.05, 0.1, 0.2), sigma=1, R=1, n=%d, m=6, oversampling 2"
+                               % (N, n),
+                   "N": N, "R": R, "P": P, "n": n, "m": p.m, "step": "addk_dmatvec: K v, dK/dl_w v, dK/dsigma_w v",
                    "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -116,13 +116,13 @@ typedef struct addk_batch_s *addk_batch;
  *  m                window half-width in oversampled grid cells (2..8);
  *                   every point touches (2m)^d grid cells.
  *  oversampling     sigma = n_os / n; n_os = round(sigma * n) must be a power
- *                   of two in [16, 128] and exceed n.
+ *                   of two in [16, 256] and exceed n.
  *  precision        ADDK_FP64 or ADDK_FP32.
  *  flags            ADDK_COEF_* | ADDK_TORUS_* | ADDK_NO_ACCURACY_CHECK |
  *                   ADDK_TILE_KERNELS_ONLY | ADDK_VECTOR_ALU_ONLY | ADDK_NEAR_FIELD.
  *  stream           stream used for the set-up kernels.
  * Errors: INVALID_ARG (bad sizes/values/pointers), UNSUPPORTED (d_w > 3,
- * n_os outside [16,128] or not a power of two, data extent plus window wider
+ * n_os outside [16,256] or not a power of two, data extent plus window wider
  * than the torus), ACCURACY (eta_w = pi n l_w / (sqrt2 T_w) < 1), OOM, HIP.
  */
 addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double *X, int64_t ldx,
@@ -317,7 +317,7 @@ addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, u
  * range of its points, data units) and length scale l whose a-priori error
  * estimate (image, truncation and window terms, automatic torus period) is at
  * most tol, among the n the library supports for this m and oversampling
- * (round(oversampling n) a power of two in [16, 128], eta >= 1, data box
+ * (round(oversampling n) a power of two in [16, 256], eta >= 1, data box
  * inside the torus).  For a plan, take the largest n over its windows.
  * err_estimate (optional) receives the estimate at the chosen n.
  * Errors: INVALID_ARG; ACCURACY when no supported n reaches tol. */

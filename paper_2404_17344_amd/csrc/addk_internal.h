@@ -33,7 +33,7 @@ constexpr int kBlock = 256;      // threads per block of every stage kernel
 constexpr int kGroup = 16;       // lanes cooperating on one point in spread/interp
 constexpr int kChunk = 1024;     // maximal points per spread/interp work item
 constexpr int kMaxW = 16;        // maximal taps per dimension (m <= 8)
-constexpr int kMaxNos = 128;     // maximal oversampled grid per dimension
+constexpr int kMaxNos = 256;     // maximal oversampled grid per dimension
 constexpr int kLdsBudget = 64 * 1024;
 constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
 constexpr int kDenseChunk = 256; // maximal points per dense interp item
@@ -44,7 +44,7 @@ constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).
 constexpr int kNearQ = 8;        // matched derivatives of the near-field polynomial
-constexpr int kNearChunk = 256;  // targets per near-field block
+constexpr int kNearChunk = 64;   // targets per near-field block (one wave)
 
 struct WinDev {
     int d, n, n1, nos, m, W, prob, flags;
@@ -162,6 +162,8 @@ struct Engine {
     int ndense[4][2] = {};
     Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)
     int ndense_sp[4][2] = {};
+    int fft_L = 16;                // lines per FFT block (halved when some window's grid exceeds 128)
+    int nos_max = 16;              // largest oversampled grid edge of the engine's windows
     Chunk *d_near[4] = {};         // near-field target blocks per d (tile field = tile index)
     int nnear[4] = {};
     std::vector<int2> near_rng;    // per window: [first, end) of its blocks in the list of its d

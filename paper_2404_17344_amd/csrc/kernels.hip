@@ -435,6 +435,7 @@ __device__ cpx<real> *fft_lines(cpx<real> *a, cpx<real> *b, const cpx<real> *tw,
 }
 
 struct FftCall {
+    int nos_lds;    // line length the LDS buffers are laid out for (the engine's largest grid)
     int npair;
     int nout;       // fused: number of multipliers / inverse outputs (0, 1, 2)
     int modes_sel;  // fused: 0 none, 1 store forward modes into Vm, 2 into Gm
@@ -497,11 +498,10 @@ __device__ __forceinline__ int64_t line_addr(const int *dims, int axis, int i0, 
     return ((int64_t)i2 * dims[1] + i1) * dims[0] + i0;
 }
 
-template <typename real, int AXIS, int MODE>
+template <typename real, int AXIS, int MODE, int L>
 __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins, const LineGroup *__restrict__ groups,
                                                 FftCall call)
 {
-    constexpr int L = sizeof(real) == 4 ? 16 : 8;
     using C = cpx<real>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const LineGroup lg = groups[blockIdx.x];
@@ -519,9 +519,9 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     select_arrays<real, AXIS, MODE>(w, pair, o, sa);
 
     C *tw = (C *)smem_raw;
-    C *buf0 = tw + kMaxNos / 2;
-    C *buf1 = buf0 + L * kMaxNos;
-    C *buf2 = buf1 + L * kMaxNos;
+    C *buf0 = tw + call.nos_lds / 2;
+    C *buf1 = buf0 + L * call.nos_lds;
+    C *buf2 = buf1 + L * call.nos_lds;
     for (int q = threadIdx.x; q < nos / 2; q += kBlock)
         tw[q] = ((const C *)w.tw)[q];
 
@@ -883,7 +883,14 @@ addk_status engine_gsi(Engine &E, const std::vector<const double *> &B64, const 
 // ---------------------------------------------------------------------------
 // host side
 
-static int lines_per_group(int precision) { return precision == ADDK_FP32 ? 16 : 8; }
+// Lines per FFT block: 16 (FP32) or 8 (FP64) lines of up to 128 points; half
+// as many when a grid has 256 points per edge, so that the three line buffers
+// stay within 64 KiB of LDS.
+static int lines_per_group(int precision, int nos_max)
+{
+    const int L = precision == ADDK_FP32 ? 16 : 8;
+    return nos_max > 128 ? L / 2 : L;
+}
 
 static size_t real_size(int precision) { return precision == ADDK_FP32 ? sizeof(float) : sizeof(double); }
 
@@ -1079,7 +1086,11 @@ addk_status engine_build_device(Engine &E, int precision)
         if (s != ADDK_OK)
             return s;
     }
-    const int L = lines_per_group(precision);
+    E.nos_max = 16;
+    for (const WinDev &w : E.wdev)
+        E.nos_max = std::max(E.nos_max, w.nos);
+    const int L = lines_per_group(precision, E.nos_max);
+    E.fft_L = L;
     std::vector<Chunk> ch[4];
     std::vector<Chunk> dn[4][2], dsp[4][2];
     std::vector<LineGroup> gr[ST_COUNT];
@@ -1437,10 +1448,15 @@ static void launch_fft(Engine &E, int st_id, int ny, FftCall call, hipStream_t s
 {
     if (!E.ngroups[st_id] || ny <= 0)
         return;
-    constexpr int L = sizeof(real) == 4 ? 16 : 8;
-    const size_t sh = (kMaxNos / 2 + 3 * L * kMaxNos) * sizeof(cpx<real>);
-    hipLaunchKernelGGL((k_fft<real, AXIS, MODE>), dim3(E.ngroups[st_id], ny), dim3(kBlock), sh, st, E.d_wins,
-                       E.d_groups[st_id], call);
+    constexpr int LF = sizeof(real) == 4 ? 16 : 8;  // lines per block for grids up to 128 points
+    call.nos_lds = E.nos_max;
+    const size_t sh = ((size_t)E.nos_max / 2 + 3 * (size_t)E.fft_L * E.nos_max) * sizeof(cpx<real>);
+    if (E.fft_L == LF)
+        hipLaunchKernelGGL((k_fft<real, AXIS, MODE, LF>), dim3(E.ngroups[st_id], ny), dim3(kBlock), sh, st, E.d_wins,
+                           E.d_groups[st_id], call);
+    else
+        hipLaunchKernelGGL((k_fft<real, AXIS, MODE, LF / 2>), dim3(E.ngroups[st_id], ny), dim3(kBlock), sh, st,
+                           E.d_wins, E.d_groups[st_id], call);
 }
 
 template <typename real>
@@ -1485,7 +1501,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
             StageTimer t(E, PS_SPREAD_DENSE, st);
             launch_spread_dense(E, d, wi, R, io, st);
         }
-    FftCall fc{npair, nout, modes_sel};
+    FftCall fc{E.nos_max, npair, nout, modes_sel};
     if (E.ngroups[ST_FWD0]) {
         StageTimer t(E, PS_FFT_X_FWD, st);
         launch_fft<real, 0, 0>(E, ST_FWD0, npair, fc, st);

@@ -10,13 +10,14 @@
 // Layout.  The plan sorted every window's points by tile (a box of base cells
 // of the spreading grid); the points of tile t are the range
 // [tile_off[t], tile_off[t+1]) of the sorted order, coordinates in grid units.
-// A block takes up to 256 consecutive sorted points (targets, one per thread,
-// all in one tile), bounds them by a box, and walks the rows of tiles (along
-// x, contiguous in the sorted order) whose boxes come within eps of it.  The
-// sources of a row are staged in LDS 256 at a time (coordinates and the
-// point-major right-hand sides) and read by all threads as broadcasts.  Each
-// target is owned by one thread, which adds its sums to the window's product
-// buffer after the interpolation has written it, in a fixed order.
+// A block is one wave: it takes up to 64 consecutive sorted points (targets,
+// one per lane, all in one tile), bounds them by a box, and walks the rows of
+// tiles (along x, contiguous in the sorted order) that come within eps of the
+// box, each row cut to the ball's chord.  The sources of a row are staged in
+// LDS 64 at a time (coordinates and the point-major right-hand sides) and read
+// by all lanes as broadcasts.  Each target is owned by one lane, which adds its
+// sums to the window's product buffer after the interpolation has written it,
+// in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +35,9 @@ __device__ __forceinline__ ProbDev nf_prob(const IoArgs &io, int p) { return io.
 
 __device__ __forceinline__ float nf_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double nf_exp(double x) { return exp(x); }
+// FP32: the hardware square root (about 1 ulp), without the rounding fix-up
+__device__ __forceinline__ float nf_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double nf_sqrt(double x) { return sqrt(x); }
 
 template <typename real>
 __device__ __forceinline__ real horner(const real *a, real t2)
@@ -65,19 +69,19 @@ __device__ __forceinline__ float wave_max(float v)
 // DOT = true:  partial[(blockIdx.x * gridDim.y + blockIdx.y) * 2 + o] =
 //               sum over the block's targets i of sum_j K_NE,o(ij) <Vt_i, Vp_j>
 //               (RHS r0 .. r0 + RT - 1), Vt_i read from the caller's V.
+constexpr int kNearBlock = 64;  // one wave per block
+
 template <typename real, int D, int RT, int NO, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
+__global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ wins, const Chunk *__restrict__ chunks,
                                                  IoArgs io, int R, const double *__restrict__ Vt, int64_t ldvt,
                                                  double *__restrict__ partial)
 {
-    __shared__ real sc[kBlock][4];          // source coordinates (grid units)
-    __shared__ real sv[kBlock][RT];         // source right-hand sides
-    __shared__ float red[4][6];
-    __shared__ double dred[4][2];
+    __shared__ real sc[kNearBlock][4];                // source coordinates (grid units); [3] = value if RT = 1
+    __shared__ real sv[RT > 1 ? kNearBlock : 1][RT];  // source right-hand sides (RT > 1)
     const Chunk ch = chunks[blockIdx.x];
     const WinDev &w = wins[ch.win];
     const int r0 = blockIdx.y * RT;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x;
     const ProbDev pio = nf_prob(io, w.prob);
     const real *coords = (const real *)w.coords;
     const bool own = t < ch.count;
@@ -86,22 +90,12 @@ __global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins
 #pragma unroll
     for (int a = 0; a < D; ++a)
         u[a] = coords[(int64_t)a * w.N + i];
-    // box of the block's targets
+    // box of the wave's targets
     float bmin[3] = {0.f, 0.f, 0.f}, bmax[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        float lo = wave_min(own ? (float)u[a] : 3.0e38f);
-        float hi = wave_max(own ? (float)u[a] : -3.0e38f);
-        if (lane == 0) {
-            red[wave][a] = lo;
-            red[wave][3 + a] = hi;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        bmin[a] = fminf(fminf(red[0][a], red[1][a]), fminf(red[2][a], red[3][a]));
-        bmax[a] = fmaxf(fmaxf(red[0][3 + a], red[1][3 + a]), fmaxf(red[2][3 + a], red[3][3 + a]));
+        bmin[a] = wave_min(own ? (float)u[a] : 3.0e38f);
+        bmax[a] = wave_max(own ? (float)u[a] : -3.0e38f);
     }
     const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
     const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;  // slightly generous for the box tests
@@ -162,9 +156,17 @@ __global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins
                 }
                 if (g2 >= eg * eg)
                     continue;
+                // x tiles within the ball's chord at this row's y/z distance
+                const float rx = sqrtf(eg * eg - g2);
+                const int nbx = w.ext[0] - w.W + 1;
+                const int bx0 = max(0, (int)floorf(bmin[0] - rx) - w.m + 1);
+                const int bx1 = min(nbx - 1, (int)floorf(bmax[0] + rx) - w.m + 1);
+                if (bx1 < bx0)
+                    continue;
+                const int tx0 = bx0 / w.tb[0], tx1 = min(w.ntile[0] - 1, bx1 / w.tb[0]);
                 const int64_t trow = ((int64_t)tz * w.ntile[1] + ty) * w.ntile[0];
-                const int s = toff[trow + t0[0]], e = toff[trow + t1[0] + 1];
-                for (int b = s; b < e; b += kBlock) {
+                const int s = toff[trow + tx0], e = toff[trow + tx1 + 1];
+                for (int b = s; b < e; b += kNearBlock) {
                     __syncthreads();
                     const int j = b + t;
                     if (j < e) {
@@ -172,39 +174,64 @@ __global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins
                         for (int a = 0; a < D; ++a)
                             sc[t][a] = coords[(int64_t)a * w.N + j];
                         const int64_t orig = w.perm[j];
+                        if (RT == 1)
+                            sc[t][3] = vp[orig * pio.ldvp + r0];
+                        else
 #pragma unroll
-                        for (int r = 0; r < RT; ++r)
-                            sv[t][r] = vp[orig * pio.ldvp + r0 + r];
+                            for (int r = 0; r < RT; ++r)
+                                sv[RT > 1 ? t : 0][r] = vp[orig * pio.ldvp + r0 + r];
+                    } else {  // padding up to a multiple of 4: far away, never within eps
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+                            sc[t][a] = real(a < D ? 1.0e6 : 0.0);
                     }
                     __syncthreads();
-                    const int nsrc = min(kBlock, e - b);
-                    for (int jj = 0; jj < nsrc; ++jj) {
-                        real d2 = real(0);
+                    const int nsrc4 = __builtin_amdgcn_readfirstlane((min(kNearBlock, e - b) + 3) & ~3);
+                    for (int j4 = 0; j4 < nsrc4; j4 += 4) {
+                        // four sources per step: their loads issue together
+                        real s4[4][4];
 #pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            const real dx = u[a] - sc[jj][a];
-                            d2 += dx * dx;
+                        for (int k = 0; k < 4; ++k)
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                s4[k][a] = sc[j4 + k][a];
+                        real d2v[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            real d2 = real(0);
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                const real dx = u[a] - s4[k][a];
+                                d2 += dx * dx;
+                            }
+                            d2v[k] = d2;
                         }
-                        if (d2 < eps2) {
-                            const real rl = sqrt(d2) * hl;
-                            const real ex = nf_exp(-rl);
-                            const real t2 = d2 * ie2;
-                            const real kn = ex - horner(pa, t2);
-                            const real kd = (NO > 1 || DOT) ? rl * ex - horner(pd, t2) : real(0);
-                            if (DOT) {
-                                real dot = real(0);
 #pragma unroll
-                                for (int r = 0; r < RT; ++r)
-                                    dot += vt[r] * sv[jj][r];
-                                sk += kn * dot;
-                                sd += kd * dot;
-                            } else {
+                        for (int k = 0; k < 4; ++k) {
+                            const int jj = j4 + k;
+                            const real d2 = d2v[k];
+                            const real *s4k = s4[k];
+                            if (d2 < eps2) {
+                                const real rl = nf_sqrt(d2) * hl;
+                                const real ex = nf_exp(-rl);
+                                const real t2 = d2 * ie2;
+                                const real kn = ex - horner(pa, t2);
+                                const real kd = (NO > 1 || DOT) ? rl * ex - horner(pd, t2) : real(0);
+                                if (DOT) {
+                                    real dot = real(0);
 #pragma unroll
-                                for (int r = 0; r < RT; ++r) {
-                                    const real v = sv[jj][r];
-                                    acc[0][r] += kn * v;
-                                    if (NO > 1)
-                                        acc[NO > 1 ? 1 : 0][r] += kd * v;
+                                    for (int r = 0; r < RT; ++r)
+                                        dot += vt[r] * (RT == 1 ? s4k[3] : sv[RT > 1 ? jj : 0][r]);
+                                    sk += kn * dot;
+                                    sd += kd * dot;
+                                } else {
+#pragma unroll
+                                    for (int r = 0; r < RT; ++r) {
+                                        const real v = RT == 1 ? s4k[3] : sv[RT > 1 ? jj : 0][r];
+                                        acc[0][r] += kn * v;
+                                        if (NO > 1)
+                                            acc[NO > 1 ? 1 : 0][r] += kd * v;
+                                    }
                                 }
                             }
                         }
@@ -220,15 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_near(const WinDev *__restrict__ wins
             a0 += __shfl_xor(a0, o, 64);
             a1 += __shfl_xor(a1, o, 64);
         }
-        if (lane == 0) {
-            dred[wave][0] = a0;
-            dred[wave][1] = a1;
-        }
-        __syncthreads();
         if (t == 0) {
             double *pp = partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * 2;
-            pp[0] = (dred[0][0] + dred[1][0]) + (dred[2][0] + dred[3][0]);
-            pp[1] = (dred[0][1] + dred[1][1]) + (dred[2][1] + dred[3][1]);
+            pp[0] = a0;
+            pp[1] = a1;
         }
         return;
     }
@@ -272,14 +294,14 @@ void launch_near_rt(Engine &E, int R, int nout, IoArgs io, const double *Vt, int
 {
     dim3 grid(E.nnear[D], (R + RT - 1) / RT);
     if (DOT)
-        hipLaunchKernelGGL((k_near<real, D, RT, 2, true>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
-                           Vt, ldvt, partial);
+        hipLaunchKernelGGL((k_near<real, D, RT, 2, true>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io,
+                           R, Vt, ldvt, partial);
     else if (nout > 1)
-        hipLaunchKernelGGL((k_near<real, D, RT, 2, false>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
-                           Vt, ldvt, partial);
+        hipLaunchKernelGGL((k_near<real, D, RT, 2, false>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io,
+                           R, Vt, ldvt, partial);
     else
-        hipLaunchKernelGGL((k_near<real, D, RT, 1, false>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_near[D], io, R,
-                           Vt, ldvt, partial);
+        hipLaunchKernelGGL((k_near<real, D, RT, 1, false>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io,
+                           R, Vt, ldvt, partial);
 }
 
 template <typename real, int D, bool DOT>

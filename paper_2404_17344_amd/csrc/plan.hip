@@ -402,6 +402,18 @@ __global__ void k_samples(double2 *s, int d, int n, double T, double ell, int ke
     }
 }
 
+// exp(-2 pi i q / M), q < M, on the device (caller frees)
+static hipError_t dft_twiddles(int M, double2 **out)
+{
+    std::vector<double2> t(M);
+    for (int q = 0; q < M; ++q)
+        t[q] = make_double2(std::cos(2.0 * M_PI * q / M), -std::sin(2.0 * M_PI * q / M));
+    hipError_t e = hipMalloc(out, M * sizeof(double2));
+    if (e == hipSuccess)
+        e = hipMemcpy(*out, t.data(), M * sizeof(double2), hipMemcpyHostToDevice);
+    return e;
+}
+
 struct NearPoly {
     double a[kNearQ + 1];
 };
@@ -446,8 +458,10 @@ __global__ void k_samples_near(double2 *s, int d, int M, double T, double L, dou
     }
 }
 
-// out_k = sum_j in_j exp(-2 pi i j k / n) along one axis; j, k in I_n (index + n/2)
-__global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, int n, int axis)
+// out_k = sum_j in_j exp(-2 pi i j k / n) along one axis; j, k in I_n (index + n/2);
+// tw[q] = exp(-2 pi i q / n), q < n
+__global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, int n, int axis,
+                           const double2 *__restrict__ tw)
 {
     int64_t tot = n, stride = 1;
     for (int i = 1; i < d; ++i)
@@ -462,8 +476,7 @@ __global__ void k_dft_axis(const double2 *__restrict__ in, double2 *out, int d, 
         for (int jc = 0; jc < n; ++jc) {
             const int j = jc - n / 2;
             const int jk = (int)((((int64_t)j * k) % n + n) % n);
-            double sn, cs;
-            sincospi(-2.0 * jk / n, &sn, &cs);
+            const double cs = tw[jk].x, sn = tw[jk].y;
             const double2 v = in[basei + (int64_t)jc * stride];
             re += v.x * cs - v.y * sn;
             im += v.x * sn + v.y * cs;
@@ -575,10 +588,11 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
         if (w.nf) {
             const int M = 2 * pl.n;
             const int64_t ns = ipow(M, w.d);
-            double2 *s0 = nullptr, *s1 = nullptr;
+            double2 *s0 = nullptr, *s1 = nullptr, *dtw = nullptr;
             if ((e = hipMalloc(&s0, ns * sizeof(double2))) != hipSuccess ||
-                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess) {
+                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess || (e = dft_twiddles(M, &dtw)) != hipSuccess) {
                 (void)hipFree(s0);
+                (void)hipFree(s1);
                 return fail(ADDK_ERR_OOM, "sample buffer allocation failed");
             }
             const int nbs = (int)std::min<int64_t>((ns + 255) / 256, 4096);
@@ -590,7 +604,7 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
                                    w.nf_eps, p, der);
                 double2 *a = s0, *bb = s1;
                 for (int ax = 0; ax < w.d; ++ax) {
-                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, M, ax);
+                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, M, ax, dtw);
                     std::swap(a, bb);
                 }
                 hipLaunchKernelGGL(k_coef_from_hat, dim3(nb), dim3(256), 0, st, a, der ? w.Bd64 : w.Bk64, w.d,
@@ -599,20 +613,25 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
             e = hipStreamSynchronize(st);
             (void)hipFree(s0);
             (void)hipFree(s1);
+            (void)hipFree(dtw);
             if (e != hipSuccess)
                 return hip_fail(e, "near-field multipliers");
         } else if (pl.flags & ADDK_COEF_SAMPLED) {
             const int64_t ns = ipow(pl.n, w.d);
-            double2 *s0 = nullptr, *s1 = nullptr;
+            double2 *s0 = nullptr, *s1 = nullptr, *dtw = nullptr;
             if ((e = hipMalloc(&s0, ns * sizeof(double2))) != hipSuccess ||
-                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess)
+                (e = hipMalloc(&s1, ns * sizeof(double2))) != hipSuccess ||
+                (e = dft_twiddles(pl.n, &dtw)) != hipSuccess) {
+                (void)hipFree(s0);
+                (void)hipFree(s1);
                 return fail(ADDK_ERR_OOM, "sample buffer allocation failed");
+            }
             const int nbs = (int)std::min<int64_t>((ns + 255) / 256, 1024);
             for (int der = 0; der < 2; ++der) {
                 hipLaunchKernelGGL(k_samples, dim3(nbs), dim3(256), 0, st, s0, w.d, pl.n, w.T, w.ell, pl.kernel, der);
                 double2 *a = s0, *bb = s1;
                 for (int ax = 0; ax < w.d; ++ax) {
-                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, pl.n, ax);
+                    hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, pl.n, ax, dtw);
                     std::swap(a, bb);
                 }
                 hipLaunchKernelGGL(k_coef_from_hat, dim3(nb), dim3(256), 0, st, a, der ? w.Bd64 : w.Bk64, w.d,
@@ -621,6 +640,7 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
             e = hipStreamSynchronize(st);
             (void)hipFree(s0);
             (void)hipFree(s1);
+            (void)hipFree(dtw);
             if (e != hipSuccess)
                 return hip_fail(e, "sampled coefficients");
         } else {
@@ -984,7 +1004,7 @@ addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, doubl
         (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12))
         return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n: bad argument");
     // Candidates: even n whose oversampled grid round(sigma n) is a power of two
-    // in [16, 128] with room for the window; the first (smallest, cheapest) one
+    // in [16, 256] with room for the window; the first (smallest, cheapest) one
     // whose a-priori estimate meets tol and whose data box fits the torus wins.
     double best_err = INFINITY;
     for (int c = 4; c < kMaxNos; c += 2) {
@@ -1053,7 +1073,7 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
         return fail(ADDK_ERR_INVALID_ARG, "oversampling must be > 1");
     const long nos = std::lround(oversampling * n);
     if (nos < 16 || nos > kMaxNos || (nos & (nos - 1)) || nos <= n)
-        return fail(ADDK_ERR_UNSUPPORTED, "oversampled grid n_os = round(sigma n) must be a power of two in [16, 128] "
+        return fail(ADDK_ERR_UNSUPPORTED, "oversampled grid n_os = round(sigma n) must be a power of two in [16, 256] "
                                           "and exceed n");
     if (4 * m > nos)
         return fail(ADDK_ERR_UNSUPPORTED, "window support 2m must not exceed half the oversampled grid");

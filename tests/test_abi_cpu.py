@@ -120,10 +120,14 @@ def test_choose_n_meets_tolerance_on_the_trigonometric_sum(ell, tol, d):
 
 
 def test_choose_n_refuses_unreachable_tolerance():
+    """l = 0.003 on an extent of 0.5 needs more than 256 grid points per edge;
+    l = 0.01 is reachable only with the 256-point grid (n > 64)."""
     import paper_2404_17344_amd as A
     _lib()
     with pytest.raises(A.AddkError):
-        A.choose_n(F.GAUSSIAN, 0.5, 0.01, m=6, oversampling=2.0, tol=1e-5)
+        A.choose_n(F.GAUSSIAN, 0.5, 0.003, m=6, oversampling=2.0, tol=1e-5)
+    n, _ = A.choose_n(F.GAUSSIAN, 0.5, 0.01, m=6, oversampling=2.0, tol=1e-5)
+    assert 64 < n <= 128
     with pytest.raises(A.AddkError):
         A.choose_n(F.GAUSSIAN, 0.5, 0.1, m=2, oversampling=2.0, tol=1e-12)
 
