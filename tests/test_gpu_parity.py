@@ -247,7 +247,7 @@ def test_argument_errors(A):
     with pytest.raises(A.AddkError, match="accuracy"):
         A.Plan(X, [[0]], [0.005], [1.0], n=16, m=4)
     with pytest.raises(A.AddkError, match="unsupported"):
-        A.Plan(X, [[0]], [0.1], [1.0], n=64, m=6, oversampling=4.0)  # n_os = 256
+        A.Plan(X, [[0]], [0.1], [1.0], n=128, m=6, oversampling=4.0)  # n_os = 512
     plan = A.Plan(X, [[0, 1]], [0.1], [1.0], n=32, m=6)
     import ctypes
     from paper_2404_17344_amd import _lib as L
