@@ -535,11 +535,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
         return;
     float *G = (float *)w.G;
     const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
+    // all loads of the cell's 8 complex grid values first, then the stores
+    float2 g[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int r = r0 + i;
+    for (int p = 0; p < 8; ++p)
+        g[p] = r0 + 2 * p < R ? *(const float2 *)(G + ((int64_t)((r0 >> 1) + p) * w.szG + c) * 2) : float2{0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int r = r0 + 2 * p;
         if (r < R)
-            G[((int64_t)(r >> 1) * w.szG + c) * 2 + (r & 1)] += acc[i >> 2][i & 3];
+            G[((int64_t)(r >> 1) * w.szG + c) * 2] = g[p].x + acc[(2 * p) >> 2][(2 * p) & 3];
+        if (r + 1 < R)
+            G[((int64_t)(r >> 1) * w.szG + c) * 2 + 1] = g[p].y + acc[(2 * p + 1) >> 2][(2 * p + 1) & 3];
     }
 }
 
