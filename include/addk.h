@@ -141,8 +141,9 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
  * addk_matvec / addk_dmatvec with V of Ns rows and Y (and the derivative
  * outputs) of Nt rows, addk_gsi with v of Ns rows; addk_vjp and batches need
  * square plans (ADDK_ERR_UNSUPPORTED).  Other arguments and errors as in
- * addk_plan_create.  The current implementation spreads and interpolates at
- * all Ns + Nt points (the targets carry zero weight).
+ * addk_plan_create.  Sources and targets are sorted separately: the sources
+ * are spread and the targets interpolated (and, with ADDK_NEAR_FIELD, each
+ * target meets only the sources within the near-field radius).
  */
 addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int32_t D, const double *Xs,
                                      int64_t ldxs, const double *Xt, int64_t ldxt, int32_t P,
@@ -242,8 +243,8 @@ typedef struct {
     int32_t n, m, n_os, precision, kernel;
     int64_t workspace_bytes;    /* device bytes currently held by the plan           */
     double err_estimate;        /* a-priori relative error estimate (max over windows) */
-    int64_t dense_points;       /* point-window pairs handled by the dense-cell kernels */
-    int64_t tile_points;        /* point-window pairs handled by the tile kernels       */
+    int64_t dense_points;       /* source point-window pairs spread by the dense-cell kernels */
+    int64_t tile_points;        /* source point-window pairs spread by the tile kernels       */
     uint32_t knobs;             /* ADDK_KNOB_* in effect                                 */
     int32_t tuned;              /* 1 once addk_plan_autotune chose the knobs             */
     int64_t n_sources;          /* rows of V (= N unless the plan has separate targets) */

@@ -134,6 +134,12 @@ struct WinHost {
     double nf_a[kNearQ + 1], nf_ad[kNearQ + 1];
     std::vector<int32_t> tile_off;                // host copy (ntiles + 1)
     int32_t *d_tile_off = nullptr;
+    // plans with separate target points sort the sources and the targets as two
+    // segments of the same arrays: the lists above (chunks, dense_sp, tile_off)
+    // then cover the sources, dense covers the targets, and these the targets
+    bool split = false;
+    std::vector<Chunk> chunks_i;                  // sparse tile chunks of the targets (interp)
+    std::vector<int32_t> tile_off_t;              // targets' tile ranges (near-field blocks)
 };
 
 struct Plan;
@@ -156,8 +162,10 @@ struct Engine {
     std::vector<int> wplan;        // plan index of each window
     std::vector<int> wlocal;       // window index inside its plan
     WinDev *d_wins = nullptr;
-    Chunk *d_chunks[4] = {nullptr, nullptr, nullptr, nullptr};  // per d (1..3)
+    Chunk *d_chunks[4] = {nullptr, nullptr, nullptr, nullptr};  // sparse tile chunks for spreading, per d (1..3)
     int nchunks[4] = {0, 0, 0, 0};
+    Chunk *d_chunks_i[4] = {nullptr, nullptr, nullptr, nullptr};  // ... for interpolation (the same list for
+    int nchunks_i[4] = {0, 0, 0, 0};                                // square plans, the targets' otherwise)
     Chunk *d_dense[4][2] = {};     // dense cell runs (interp items) per d and window width (2m = 8, 12)
     int ndense[4][2] = {};
     Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)

@@ -141,7 +141,7 @@ static std::vector<uint32_t> knob_candidates(const Engine &E)
     bool dense = false, tile = false;
     for (int wi = 0; wi < 2; ++wi)
         dense = dense || E.ndense[3][wi] > 0;
-    tile = E.nchunks[3] > 0 && (E.tile_w[3] == 8 || E.tile_w[3] == 12);
+    tile = E.nchunks_i[3] > 0 && (E.tile_w[3] == 8 || E.tile_w[3] == 12);
     std::vector<uint32_t> out;
     for (uint32_t k = 0; k <= ADDK_KNOB_ALL_MFMA; ++k) {
         if (!dense && (k & (ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA)) !=

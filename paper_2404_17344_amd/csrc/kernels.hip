@@ -999,6 +999,7 @@ void engine_free(Engine &E)
     free_dev(E.d_wins);
     for (int d = 0; d < 4; ++d) {
         free_dev(E.d_chunks[d]);
+        free_dev(E.d_chunks_i[d]);
         free_dev(E.d_dense[d][0]);
         free_dev(E.d_dense[d][1]);
         free_dev(E.d_dense_sp[d][0]);
@@ -1091,7 +1092,7 @@ addk_status engine_build_device(Engine &E, int precision)
         E.nos_max = std::max(E.nos_max, w.nos);
     const int L = lines_per_group(precision, E.nos_max);
     E.fft_L = L;
-    std::vector<Chunk> ch[4];
+    std::vector<Chunk> ch[4], chi[4];
     std::vector<Chunk> dn[4][2], dsp[4][2];
     std::vector<LineGroup> gr[ST_COUNT];
     for (int d = 0; d < 4; ++d) {
@@ -1107,6 +1108,11 @@ addk_status engine_build_device(Engine &E, int precision)
             cc.win = (int)wi;
             ch[w.d].push_back(cc);
         }
+        for (const Chunk &c : h.split ? h.chunks_i : h.chunks) {
+            Chunk cc = c;
+            cc.win = (int)wi;
+            chi[w.d].push_back(cc);
+        }
         for (const Chunk &c : h.dense) {
             Chunk cc = c;
             cc.win = (int)wi;
@@ -1118,7 +1124,7 @@ addk_status engine_build_device(Engine &E, int precision)
             dsp[w.d][w.W == 8 ? 0 : 1].push_back(cc);
         }
         E.maxvol[w.d] = std::max(E.maxvol[w.d], w.S[0] * w.S[1] * w.S[2]);
-        if (!h.chunks.empty()) {
+        if (!h.chunks.empty() || !h.chunks_i.empty()) {
             if (E.tile_w[w.d] == 0)
                 E.tile_w[w.d] = w.W;
             else if (E.tile_w[w.d] != w.W)
@@ -1133,16 +1139,20 @@ addk_status engine_build_device(Engine &E, int precision)
     for (int d = 1; d <= 3; ++d) {
         if (E.maxvol[d])
             E.rb[d] = pick_rb(E.maxvol[d], precision, d);
-        E.nchunks[d] = (int)ch[d].size();
-        free_dev(E.d_chunks[d]);
-        E.d_chunks[d] = nullptr;
-        if (!ch[d].empty()) {
-            hipError_t e = hipMalloc(&E.d_chunks[d], ch[d].size() * sizeof(Chunk));
-            if (e != hipSuccess)
-                return hip_fail(e, "hipMalloc(chunks)");
-            e = hipMemcpy(E.d_chunks[d], ch[d].data(), ch[d].size() * sizeof(Chunk), hipMemcpyHostToDevice);
-            if (e != hipSuccess)
-                return hip_fail(e, "hipMemcpy(chunks)");
+        for (int side = 0; side < 2; ++side) {  // spreading, interpolation
+            const std::vector<Chunk> &v = side == 0 ? ch[d] : chi[d];
+            Chunk *&dp = side == 0 ? E.d_chunks[d] : E.d_chunks_i[d];
+            (side == 0 ? E.nchunks[d] : E.nchunks_i[d]) = (int)v.size();
+            free_dev(dp);
+            dp = nullptr;
+            if (!v.empty()) {
+                hipError_t e = hipMalloc(&dp, v.size() * sizeof(Chunk));
+                if (e != hipSuccess)
+                    return hip_fail(e, "hipMalloc(chunks)");
+                e = hipMemcpy(dp, v.data(), v.size() * sizeof(Chunk), hipMemcpyHostToDevice);
+                if (e != hipSuccess)
+                    return hip_fail(e, "hipMemcpy(chunks)");
+            }
         }
     }
     auto upload_items = [](const std::vector<Chunk> &v, Chunk *&dptr, int &n) -> addk_status {
@@ -1162,13 +1172,14 @@ addk_status engine_build_device(Engine &E, int precision)
         E.near_rng.assign(E.wdev.size(), make_int2(0, 0));
         for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
             const WinHost &h = E.plans[E.wplan[wi]]->wins[E.wlocal[wi]];
-            if (!h.nf || h.tile_off.empty())
+            const std::vector<int32_t> &to = h.split ? h.tile_off_t : h.tile_off;  // the targets' tiles
+            if (!h.nf || to.empty())
                 continue;
             std::vector<Chunk> &l = nl[h.d];
             E.near_rng[wi].x = (int)l.size();
             for (int64_t t = 0; t < h.ntiles; ++t)
-                for (int32_t s = h.tile_off[t]; s < h.tile_off[t + 1]; s += kNearChunk)
-                    l.push_back({(int32_t)wi, (int32_t)t, s, std::min<int32_t>(kNearChunk, h.tile_off[t + 1] - s)});
+                for (int32_t s = to[t]; s < to[t + 1]; s += kNearChunk)
+                    l.push_back({(int32_t)wi, (int32_t)t, s, std::min<int32_t>(kNearChunk, to[t + 1] - s)});
             E.near_rng[wi].y = (int)l.size();
         }
         for (int d = 1; d <= 3; ++d) {
@@ -1407,8 +1418,8 @@ template <typename real, int D, int RB>
 static void launch_interp_rb(Engine &E, int R, int nout, hipStream_t st)
 {
     const size_t sh = ((size_t)RB * E.maxvol[D] + 16 * D * kMaxW) * sizeof(real);
-    dim3 grid(E.nchunks[D], (R + RB - 1) / RB, nout);
-    hipLaunchKernelGGL((k_interp<real, D, RB>), grid, dim3(kBlock), sh, st, E.d_wins, E.d_chunks[D], R);
+    dim3 grid(E.nchunks_i[D], (R + RB - 1) / RB, nout);
+    hipLaunchKernelGGL((k_interp<real, D, RB>), grid, dim3(kBlock), sh, st, E.d_wins, E.d_chunks_i[D], R);
 }
 
 static int rb_for(const Engine &E, int D, int R)
@@ -1533,7 +1544,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         }
         if (interp) {
             for (int d = 1; d <= 3; ++d) {
-                if (!E.nchunks[d])
+                if (!E.nchunks_i[d])
                     continue;
                 StageTimer t(E, PS_INTERP, st);
                 if (d == 3 && use_mfma(E, ADDK_KNOB_INTERP_TILE_MFMA, R) && launch_interp_tile_mfma(E, R, nout, st))

@@ -702,10 +702,10 @@ namespace addk {
 bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st)
 {
     const int W = E.tile_w[3];
-    if (E.precision != ADDK_FP32 || !E.nchunks[3] || (W != 8 && W != 12))
+    if (E.precision != ADDK_FP32 || !E.nchunks_i[3] || (W != 8 && W != 12))
         return false;
-    dim3 grid(E.nchunks[3], (R + 15) / 16);
-    const Chunk *ch = E.d_chunks[3];
+    dim3 grid(E.nchunks_i[3], (R + 15) / 16);
+    const Chunk *ch = E.d_chunks_i[3];
     if (W == 8 && nout == 1)
         hipLaunchKernelGGL((k_interp_tile_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
     else if (W == 8)

@@ -265,6 +265,9 @@ __global__ void k_minmax(const double *__restrict__ X, int64_t ldx, int64_t N, i
 
 struct KeyArgs {
     int d, nos, m, W, cpt;
+    int64_t nsrc;   // points at or after nsrc form the second (target) segment, if split
+    int32_t nkeys;  // keys per segment
+    int split;
     int f[3];
     double c[3];
     double invT;
@@ -306,7 +309,7 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
         // cell key: tile-major, then the base cell inside the tile
         const int tl = t[0] + a.ntile[0] * (t[1] + a.ntile[1] * t[2]);
         const int c = (b3[0] - t[0] * a.tb[0]) + a.tb[0] * ((b3[1] - t[1] * a.tb[1]) + a.tb[1] * (b3[2] - t[2] * a.tb[2]));
-        const int k = tl * a.cpt + c;
+        const int k = tl * a.cpt + c + (a.split && j >= a.nsrc ? a.nkeys : 0);
         key[j] = k;
         atomicAdd(&hist[k], 1);
     }
@@ -817,9 +820,10 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         (e = hipMalloc(&w.perm, std::max<int64_t>(1, N) * sizeof(int32_t))) != hipSuccess)
         return fail(ADDK_ERR_OOM, "point arrays allocation failed");
     w.chunks.clear();
+    w.chunks_i.clear();
     w.tile_off.clear();
-    if (w.nf)
-        w.tile_off.assign(w.ntiles + 1, 0);
+    w.tile_off_t.clear();
+    w.split = pl.rect;
     w.dense.clear();
     w.dense_sp.clear();
     if (N == 0)
@@ -827,7 +831,8 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     void *ucoord = nullptr;
     int32_t *key = nullptr, *hist = nullptr, *bad = nullptr;
     if ((e = hipMalloc(&ucoord, N * w.d * rs)) != hipSuccess || (e = hipMalloc(&key, N * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&hist, (w.ntiles * w.tb[0] * w.tb[1] * w.tb[2] + 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&hist, (w.ntiles * w.tb[0] * w.tb[1] * w.tb[2] * (w.split ? 2 : 1) + 1) * sizeof(int32_t))) !=
+            hipSuccess ||
         (e = hipMalloc(&bad, sizeof(int32_t))) != hipSuccess)
         return fail(ADDK_ERR_OOM, "sort buffers allocation failed");
     KeyArgs ka;
@@ -848,11 +853,15 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     }
     const int64_t cpt = (int64_t)w.tb[0] * w.tb[1] * w.tb[2];
     const int64_t nkeys = w.ntiles * cpt;
+    const int nseg = w.split ? 2 : 1;
+    ka.nsrc = pl.nsrc;
+    ka.nkeys = (int32_t)nkeys;
+    ka.split = w.split ? 1 : 0;
     {
         std::vector<int32_t> zeros(1, 0);
         e = hipMemcpy(bad, zeros.data(), sizeof(int32_t), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemsetAsync(hist, 0, nkeys * sizeof(int32_t), st);  // plan set-up is never captured
+            e = hipMemsetAsync(hist, 0, nseg * nkeys * sizeof(int32_t), st);  // plan set-up is never captured
         if (e != hipSuccess)
             return hip_fail(e, "clear histogram");
     }
@@ -862,9 +871,9 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     else
         hipLaunchKernelGGL(k_keys<double>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (double *)ucoord, key, hist,
                            bad);
-    std::vector<int32_t> h(nkeys);
+    std::vector<int32_t> hall(nseg * nkeys);
     int32_t hbad = 0;
-    e = hipMemcpyAsync(h.data(), hist, nkeys * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(hall.data(), hist, nseg * nkeys * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
@@ -876,22 +885,32 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
     // Order inside a tile: points of sparsely populated cells first (one
     // contiguous range, processed by the tile kernels), then each densely
     // populated cell (processed by the dense-cell kernels).
+    // With separate targets the sources' segment comes first: its tile chunks
+    // and dense runs feed the spreading, the targets' the interpolation.
     const bool dense_ok = dense_width_ok(W) && !(pl.flags & kFlagNoDense);
-    std::vector<int32_t> off(nkeys, 0);
+    std::vector<int32_t> offall(nseg * nkeys, 0);
     int64_t pos = 0;
     w.ndense_pts = 0;
+    for (int seg = 0; seg < nseg; ++seg) {
+    const int32_t *h = hall.data() + seg * nkeys;
+    int32_t *off = offall.data() + seg * nkeys;
+    const bool spread_side = seg == 0, interp_side = seg == nseg - 1;
+    std::vector<Chunk> &tchunks = seg == 0 ? w.chunks : w.chunks_i;
+    std::vector<int32_t> &toff = seg == 0 ? w.tile_off : w.tile_off_t;
+    if (w.nf)
+        toff.assign(w.ntiles + 1, 0);
     for (int64_t t = 0; t < w.ntiles; ++t) {
         const int64_t k0 = t * cpt;
         const int64_t s0 = pos;
         if (w.nf)
-            w.tile_off[t] = (int32_t)s0;
+            toff[t] = (int32_t)s0;
         for (int64_t c = 0; c < cpt; ++c)
             if (!(dense_ok && h[k0 + c] >= kDenseMin)) {
                 off[k0 + c] = (int32_t)pos;
                 pos += h[k0 + c];
             }
         for (int64_t s = s0; s < pos; s += kChunk)
-            w.chunks.push_back({0, (int32_t)t, (int32_t)s, (int32_t)std::min<int64_t>(kChunk, pos - s)});
+            tchunks.push_back({0, (int32_t)t, (int32_t)s, (int32_t)std::min<int64_t>(kChunk, pos - s)});
         const int tx = (int)(t % w.ntile[0]), ty = (int)((t / w.ntile[0]) % w.ntile[1]),
                   tz = (int)(t / ((int64_t)w.ntile[0] * w.ntile[1]));
         // dense cells of the tile, z fastest; for d = 3 two dense cells adjacent
@@ -915,26 +934,31 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
                     off[k0 + ck] = (int32_t)(pos + cnt);
                     cnt += h[k0 + ck];
                 }
-                for (int s = 0; s < cnt; s += kDenseChunk)
-                    w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
+                if (interp_side)
+                    for (int s = 0; s < cnt; s += kDenseChunk)
+                        w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
                 const int spc = w.d == 3 ? kSpreadChunk : kDenseChunk;
-                for (int s = 0; s < cnt; s += spc)
-                    w.dense_sp.push_back({0, packed, (int32_t)(pos + s), std::min(spc, cnt - s)});
+                if (spread_side)
+                    for (int s = 0; s < cnt; s += spc)
+                        w.dense_sp.push_back({0, packed, (int32_t)(pos + s), std::min(spc, cnt - s)});
                 pos += cnt;
-                w.ndense_pts += cnt;
+                if (spread_side)
+                    w.ndense_pts += cnt;
                 cz += nzc - 1;
             }
         }
     }
+    if (w.nf)
+        toff[w.ntiles] = (int32_t)pos;
+    }
     if (w.nf) {
-        w.tile_off[w.ntiles] = (int32_t)pos;
         e = hipMalloc(&w.d_tile_off, (w.ntiles + 1) * sizeof(int32_t));
         if (e == hipSuccess)
             e = hipMemcpy(w.d_tile_off, w.tile_off.data(), (w.ntiles + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e != hipSuccess)
             return hip_fail(e, "near-field tile ranges");
     }
-    e = hipMemcpy(hist, off.data(), nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(hist, offall.data(), nseg * nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess)
         return hip_fail(e, "hipMemcpy(offsets)");
     if (pl.precision == ADDK_FP32)
@@ -1038,10 +1062,11 @@ addk_status addk_window_ft(int32_t m, int32_t n_os, double oversampling, double 
     return ADDK_OK;
 }
 
-addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double *X, int64_t ldx, int32_t P,
-                             const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
-                             const double *ell, const double *sigma, int32_t n, int32_t m, double oversampling,
-                             int32_t precision, uint32_t flags, void *stream)
+// Plan over N points; with rect, points [nsrc, N) are separate targets.
+static addk_status plan_create_impl(addk_plan *out, int64_t N, int64_t nsrc, bool rect, int32_t D, const double *X,
+                                    int64_t ldx, int32_t P, const int32_t *win_offsets, const int32_t *win_features,
+                                    int32_t kernel, const double *ell, const double *sigma, int32_t n, int32_t m,
+                                    double oversampling, int32_t precision, uint32_t flags, void *stream)
 {
     if (!out)
         return fail(ADDK_ERR_INVALID_ARG, "out is NULL");
@@ -1101,7 +1126,8 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
         return fail(ADDK_ERR_OOM, "host allocation failed");
     (void)hipGetDevice(&pl->device);
     pl->N = N;
-    pl->nsrc = N;
+    pl->nsrc = nsrc;
+    pl->rect = rect;
     pl->D = D;
     pl->P = P;
     pl->kernel = kernel;
@@ -1181,6 +1207,15 @@ addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double 
     return ADDK_OK;
 }
 
+addk_status addk_plan_create(addk_plan *out, int64_t N, int32_t D, const double *X, int64_t ldx, int32_t P,
+                             const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
+                             const double *ell, const double *sigma, int32_t n, int32_t m, double oversampling,
+                             int32_t precision, uint32_t flags, void *stream)
+{
+    return plan_create_impl(out, N, N, false, D, X, ldx, P, win_offsets, win_features, kernel, ell, sigma, n, m,
+                            oversampling, precision, flags, stream);
+}
+
 addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int32_t D, const double *Xs,
                                      int64_t ldxs, const double *Xt, int64_t ldxt, int32_t P,
                                      const int32_t *win_offsets, const int32_t *win_features, int32_t kernel,
@@ -1193,7 +1228,8 @@ addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int
     if (Ns < 0 || Nt < 0 || D <= 0 || Ns + Nt > INT32_MAX || (Ns > 0 && (!Xs || ldxs < D)) ||
         (Nt > 0 && (!Xt || ldxt < D)))
         return fail(ADDK_ERR_INVALID_ARG, "bad sizes or NULL pointers");
-    // one point set [sources; targets]: the torus and grid box cover both
+    // one point set [sources; targets], sorted as two segments: the torus and
+    // grid box cover both, the sources are spread and the targets interpolated
     const int64_t N = Ns + Nt;
     double *dX = nullptr;
     hipError_t e = hipSuccess;
@@ -1208,15 +1244,10 @@ addk_status addk_plan_create_targets(addk_plan *out, int64_t Ns, int64_t Nt, int
         (void)hipFree(dX);
         return hip_fail(e, "copy of the points");
     }
-    addk_status s = addk_plan_create(out, N, D, dX, D, P, win_offsets, win_features, kernel, ell, sigma, n, m,
-                                     oversampling, precision, flags, stream);
+    addk_status s = plan_create_impl(out, N, Ns, true, D, dX, D, P, win_offsets, win_features, kernel, ell, sigma,
+                                     n, m, oversampling, precision, flags, stream);
     (void)hipFree(dX);
-    if (s != ADDK_OK)
-        return s;
-    Plan &pl = *(Plan *)*out;
-    pl.nsrc = Ns;
-    pl.rect = true;
-    return ADDK_OK;
+    return s;
 }
 
 addk_status addk_plan_destroy(addk_plan plan)
@@ -1288,7 +1319,7 @@ addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_
         info->dense_points = 0;
         for (const WinHost &w : pl.wins)
             info->dense_points += w.ndense_pts;
-        info->tile_points = pl.N * pl.P - info->dense_points;
+        info->tile_points = pl.nsrc * pl.P - info->dense_points;
         info->knobs = (pl.precision == ADDK_FP32 && !pl.eng.no_mfma) ? pl.eng.knobs : 0u;
         info->tuned = pl.eng.tuned ? 1 : 0;
         info->n_sources = pl.nsrc;

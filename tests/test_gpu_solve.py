@@ -132,3 +132,20 @@ def test_cg_krr_additive_workload(A):
     p64 = A.Plan(p.X, p.windows, p.ell, p.sigma, n=64, m=6, precision="fp64")
     r = p64.matvec(x).cpu().numpy() + beta * x.cpu().numpy() - y
     assert np.linalg.norm(r) / np.linalg.norm(y) < 1.2e-3
+
+
+@pytest.mark.parametrize("case", ["outside", "one_target", "one_source"])
+def test_target_edge_cases(A, case):
+    """Targets partly outside the sources' box (the torus covers both sets), a
+    single target and a single source: FP64 against the direct sum."""
+    rng = np.random.default_rng(95)
+    Ns, Nt = {"outside": (2000, 800), "one_target": (2500, 1), "one_source": (1, 600)}[case]
+    Xs = rng.uniform(-0.25, 0.25, size=(Ns, 6))
+    Xt = rng.uniform(0.1, 0.4, size=(Nt, 6)) if case == "outside" else rng.uniform(-0.25, 0.25, size=(Nt, 6))
+    V = rng.standard_normal((Ns, 2))
+    ell, sig = np.array([0.12, 0.2, 0.1]), np.array([1.0, 0.7, 1.3])
+    _say("targets edge case %s" % case)
+    plan = A.Plan(Xs, WINS, ell, sig, n=32, m=6, targets=Xt)
+    Y = plan.matvec(cuda(V)).cpu().numpy()
+    Yo = _oracle_targets(Xs, Xt, V, ell, sig)
+    assert relerr(Y, Yo) < 1e-10
