@@ -58,7 +58,8 @@ __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return 
 // the NG * NO accumulator chains are independent.
 template <int SW, int NT, int SX, int NG, int NO>
 __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&wxq)[NG][NT], const float *wyl,
-                                              const float (&wz)[NG], const float (*sl)[16], int ny, int q, int mrow)
+                                              const float (&wz)[NG], const bool (&live)[NG], const float (*sl)[16],
+                                              int ny, int q, int mrow)
 {
     constexpr int C = SW * SX;  // cells of one output's slab
 #pragma unroll
@@ -77,6 +78,8 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
                 b[o] = sl[o * C + oy * SX + 4 * t + q][mrow];
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
+                if (!live[g])  // wave-uniform: no point of the group reaches this slab
+                    continue;
                 const float a = wyz[g] * wxq[g][t];
 #pragma unroll
                 for (int o = 0; o < NO; ++o)
@@ -149,12 +152,15 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
         if (oz + 1 < nz)
             load(oz + 1);  // in flight during this slab's products
         float wz[NG];
+        bool live[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            const bool in = !zmask || (unsigned)(oz - lbz[g]) < (unsigned)w.W;
-            wz[g] = in ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
+            // lbz: the point's first z slab in the box (far away for inactive lanes)
+            const bool in = (unsigned)(oz - lbz[g]) < (unsigned)w.W;
+            live[g] = __builtin_amdgcn_readfirstlane(__any(in)) != 0;
+            wz[g] = (!zmask || in) ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
         }
-        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, &slab[oz & 1][0][0], sy, q, mrow);
+        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, live, &slab[oz & 1][0][0], sy, q, mrow);
         if (oz + 1 < nz)
             store((oz + 1) & 1);
         __syncthreads();
@@ -187,7 +193,7 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
         const int j = it.start + (act ? p : 0);
         const float ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
-        lbz[g] = 0;
+        lbz[g] = act ? (int)floorf(uz[g]) - w.m + 1 - bz : (1 << 20);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             wxq[g][t] = act ? kb_psi_f(ux - (float)(bx + 4 * t + q), mm, kb, ie) : 0.f;
@@ -205,7 +211,8 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
     // With two z cells, one of the 2m + 1 slabs lies just outside each point's
     // window; the window there evaluates to ~2 m b e^{-bm} (< 1e-10), so no mask
-    // is applied in this FP32 kernel.
+    // is applied in this FP32 kernel; a group whose points all lie in one of
+    // the cells skips its outside slab altogether.
     stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
     if (mrow >= nr)
         return;
@@ -575,7 +582,7 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
         const float ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
         const int lx = (int)floorf(ux) - w.m + 1 - x0, ly = (int)floorf(uy) - w.m + 1 - y0;
-        lbz[g] = (int)floorf(uz[g]) - w.m + 1 - z0;
+        lbz[g] = act ? (int)floorf(uz[g]) - w.m + 1 - z0 : (1 << 20);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int ox = 4 * t + q;
