@@ -377,28 +377,47 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         if (more)
             load(p0 + PB);  // in flight during this round's products
         Round &cr = rd[buf];
+        // Operands of one K step (four points): A = x-y weight products of the
+        // M tiles, and the B factors (RHS value, z weights of the wave's slabs).
+        // The next step's operands are read from LDS before this step's
+        // matrix ops issue, so the reads overlap them.
+        struct Ops {
+            float a[MT], ax[XT], v, wz[SPW + 1];
+        };
+        auto fetch = [&](int ks, Ops &o) {
+            const int pk = 4 * ks + q;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                o.a[mt] = cr.pxy[pk][mt * 16 + mrow];
+#pragma unroll
+            for (int j = 0; j < XT; ++j)
+                o.ax[j] = cr.pxy[pk][min(wave + 4 * j, MT - 1) * 16 + mrow];
+            o.v = cr.pv[pk][mrow];
+#pragma unroll
+            for (int s = 0; s < SPW; ++s)
+                o.wz[s] = cr.pw[pk][2 * W + wave + 4 * s];
+            o.wz[SPW] = cr.pw[pk][3 * W];  // slab 2m: zero for single-cell items
+        };
+        Ops ops[2];
+        fetch(0, ops[0]);
 #pragma unroll
         for (int ks = 0; ks < PB / 4; ++ks) {
-            const int pk = 4 * ks + q;
+            const Ops &o = ops[ks & 1];
+            if (ks + 1 < PB / 4)
+                fetch(ks + 1, ops[(ks + 1) & 1]);
             // the point's z weight of the slab scales the B operand (its RHS
             // values), so the A operand is the plain x-y weight product
-            const float v = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const float b = v * cr.pw[pk][2 * W + wave + 4 * s];
+                const float b = o.v * o.wz[s];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
-                    acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pxy[pk][mt * 16 + mrow], b, acc[s][mt], 0, 0, 0);
+                    acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[mt], b, acc[s][mt], 0, 0, 0);
             }
-            {
-                // slab 2m: zero weights for single-cell items (outside every window)
-                const float b = v * cr.pw[pk][3 * W];
+            const float bx = o.v * o.wz[SPW];
 #pragma unroll
-                for (int j = 0; j < XT; ++j) {
-                    const int mt = min(wave + 4 * j, MT - 1);
-                    accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pxy[pk][mt * 16 + mrow], b, accx[j], 0, 0, 0);
-                }
-            }
+            for (int j = 0; j < XT; ++j)
+                accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.ax[j], bx, accx[j], 0, 0, 0);
         }
         if (more) {
             store_raw(rd[buf ^ 1], p0 + PB);
