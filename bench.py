@@ -22,8 +22,9 @@ product instead: the derivative workload's shape (N = 1e5 points, D = 9 N(0,1)
 features min-max scaled, 3 windows d = 3, l = (0.05, 0.1, 0.2), R = 1, n = 64,
 m = 6), one ``addk_dmatvec`` (K v, dK/dl_w v, dK/dsigma_w v) per step; its
 roofline is the close-pair kernel's, with the close pairs counted by brute
-force (FP64 distances on the device) and 47 + 4R flop per pair (distance, square root, exponential, two
-degree-8 polynomials in r^2, 2R multiply-adds).
+force (FP64 distances on the device): 47 flop per unordered pair for the two
+kernel values (distance, square root, exponential, two degree-8 polynomials in
+r^2; the kernels are symmetric) and 4R per ordered pair (2R multiply-adds).
 """
 from __future__ import annotations
 
@@ -306,14 +307,17 @@ def matern_main(args, A, WL, torch):
             D2 = ((Xw[s:s + 2048, None, :] - Xw[None, :, :]) ** 2).sum(-1)
             pairs += int((D2 < r2).sum().item())
             del D2
-    flop_pair = 47 + 4 * R
+    # kernel values once per unordered pair (the diagonal's N per window once),
+    # multiply-adds per ordered pair
+    unordered = (pairs + N * len(p.windows)) // 2
+    flop = 47 * unordered + 4 * R * pairs
     tot_ms, launches = stages["near"]
     avg_ms = tot_ms / max(launches, 1)
-    achieved = pairs * flop_pair / (avg_ms * 1e-3) / 1e12
+    achieved = flop / (avg_ms * 1e-3) / 1e12
     peak = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
     roofline = {"bound": "alu", "kernel": "near", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_flop_per_launch": pairs * flop_pair, "close_pairs": pairs}
+                "algorithmic_flop_per_launch": flop, "close_pairs": pairs, "unordered_pairs": unordered}
 
     Y = out[0].cpu().numpy()
     dl = out[1].cpu().numpy()

@@ -89,6 +89,10 @@ typedef enum {
  *    first 8 derivatives at eps_w; the Fourier multipliers are those of this
  *    regularised kernel (DFT of (2n)^d samples);
  *  - pairs closer than eps_w are summed directly with kernel minus polynomial.
+ *    With one right-hand side and no separate targets, each such pair is
+ *    evaluated once for both of its points (the kernels are symmetric) and the
+ *    sums are added atomically: repeated calls then agree to rounding, not to
+ *    the bit.
  * Every product (matvec, dmatvec, vjp, batches, targets, CG) then agrees with
  * the direct sum to about 1e-5 relative or better.  The direct part costs
  * O(N x neighbours within eps_w).  Errors: UNSUPPORTED with ADDK_GAUSSIAN,

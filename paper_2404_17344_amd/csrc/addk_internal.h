@@ -77,6 +77,7 @@ struct WinDev {
     double nf_hl;        // (data units per grid unit) / l: r / l = sqrt(d2) * nf_hl
     double nf_a[kNearQ + 1], nf_ad[kNearQ + 1];  // even polynomials in (r / eps) of kernel and derivative kernel
     const int32_t *tile_off;  // tile t's points are [tile_off[t], tile_off[t + 1]) of the sorted order
+    double *nf_ys;            // [2][N] close-pair sums by sorted position (zero between calls)
 };
 
 // Problem-level input/output pointers (one per plan inside a batch).
@@ -176,6 +177,7 @@ struct Engine {
     int nnear[4] = {};
     std::vector<int2> near_rng;    // per window: [first, end) of its blocks in the list of its d
     double *d_near_part = nullptr; // near-field inner-product partials
+    double *d_near_ys = nullptr;   // near-field sums by sorted position (WinDev::nf_ys)
     int64_t near_part_cap = 0;
     int cur_dense = 0;
     int tile_w[4] = {0, 0, 0, 0};  // common window width of the tile work lists per d (0: mixed)

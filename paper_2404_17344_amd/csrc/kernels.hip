@@ -1025,6 +1025,8 @@ void engine_free(Engine &E)
     }
     free_dev(E.d_near_part);
     E.d_near_part = nullptr;
+    free_dev(E.d_near_ys);
+    E.d_near_ys = nullptr;
     E.near_part_cap = 0;
     for (const ProfRec &r : E.recs) {
         (void)hipEventDestroy(r.a);
@@ -1318,6 +1320,28 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     }
     E.ws_bytes = bytes;
     E.yw_bytes = ybytes;
+    // close-pair sums of the near-field windows by sorted position, cleared here
+    // once and by every pass that reads them
+    {
+        int64_t ys = 0;
+        for (const WinDev &w : E.wdev)
+            ys += w.nf ? 2 * w.N : 0;
+        free_dev(E.d_near_ys);
+        E.d_near_ys = nullptr;
+        if (ys > 0) {
+            e = hipMalloc(&E.d_near_ys, ys * sizeof(double));
+            if (e == hipSuccess)
+                e = hipMemset(E.d_near_ys, 0, ys * sizeof(double));
+            if (e != hipSuccess)
+                return hip_fail(e, "near-field sum buffer");
+            E.ws_bytes += ys * (int64_t)sizeof(double);
+        }
+        double *q = E.d_near_ys;
+        for (WinDev &w : E.wdev) {
+            w.nf_ys = w.nf ? q : nullptr;
+            q += w.nf ? 2 * w.N : 0;
+        }
+    }
     // point-major copy of the right-hand sides of every problem
     {
         int64_t packN = 0;

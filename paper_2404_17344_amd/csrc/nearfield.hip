@@ -18,6 +18,11 @@
 // by all lanes as broadcasts.  Each target is owned by one lane, which adds its
 // sums to the window's product buffer after the interpolation has written it,
 // in a fixed order.
+//
+// With one right-hand side and targets = sources (the plain K v and dK/dl v
+// products), k_near_sym evaluates each close pair once instead of twice: the
+// kernels are symmetric, so K_ij serves both i's sum and j's.  Its sums are
+// added atomically, so their rounding order varies from call to call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -267,6 +272,206 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
     }
 }
 
+// One right-hand side, targets = sources: each close pair once.  A block's
+// targets are the sorted points [cs, ce).  Sources inside that range are taken
+// as ordered pairs (the lane of target i adds K_ij v_j), sources at positions
+// >= ce symmetrically (the lane also adds K_ij v_i to source j's sum), and
+// sources before cs are left to the blocks that own them, which meet this
+// block's points as their symmetric partners: every ordered pair is counted
+// once.  A staged batch of n sources is walked diagonally, lane t pairing with
+// source (t + k) mod n at step k, so that the lanes of one step add to distinct
+// source sums in LDS (FP64 LDS adds; lanes t and t + n share a sum when n < 64).  Both sides' sums go by atomic adds to the window's
+// buffer of sums by sorted position, where one wave's adds fall on consecutive
+// words (their rounding order is not fixed); k_near_scatter then adds that
+// buffer to the product buffer (after the interpolation) and clears it.
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+template <typename real, int D, int NO>
+__global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restrict__ wins,
+                                                         const Chunk *__restrict__ chunks, IoArgs io)
+{
+    __shared__ __align__(16) real sc[kNearBlock][4];  // x, y, z (grid units), value
+    __shared__ double sa[kNearBlock][NO];             // the staged sources' symmetric sums
+    const Chunk ch = chunks[blockIdx.x];
+    const WinDev &w = wins[ch.win];
+    const int t = threadIdx.x;
+    const ProbDev pio = nf_prob(io, w.prob);
+    const real *coords = (const real *)w.coords;
+    const real *vp = (const real *)pio.Vp;
+    const bool own = t < ch.count;
+    const int64_t i = ch.start + (own ? t : 0);
+    const int cs = ch.start, ce = ch.start + ch.count;
+    real u[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        u[a] = coords[(int64_t)a * w.N + i];
+    const int64_t oi = w.perm[i];
+    const real vi = own ? vp[oi * pio.ldvp] : real(0);
+    float bmin[3] = {0.f, 0.f, 0.f}, bmax[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        bmin[a] = uniform(wave_min(own ? (float)u[a] : 3.0e38f));
+        bmax[a] = uniform(wave_max(own ? (float)u[a] : -3.0e38f));
+    }
+    const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
+    const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;
+    real pa[kNearQ + 1], pd[kNearQ + 1];
+#pragma unroll
+    for (int k = 0; k <= kNearQ; ++k) {
+        pa[k] = (real)w.nf_a[k];
+        pd[k] = (real)w.nf_ad[k];
+    }
+    int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
+    bool none = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int nb = w.ext[a] - w.W + 1;
+        const int b0 = max(0, (int)floorf(bmin[a] - eg) - w.m + 1);
+        const int b1 = min(nb - 1, (int)floorf(bmax[a] + eg) - w.m + 1);
+        none = none || b1 < b0;
+        t0[a] = b0 / w.tb[a];
+        t1[a] = min(w.ntile[a] - 1, b1 / w.tb[a]);
+    }
+    real acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+        acc[o] = real(0);
+    double *ys = w.nf_ys;
+    // the sources [b, e), at most 64 of them
+    auto batch = [&](int b, int e, bool sym) {
+        const int n = __builtin_amdgcn_readfirstlane(e - b);
+        __syncthreads();
+        if (t < n) {
+            const int64_t j = b + t;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                sc[t][a] = coords[(int64_t)a * w.N + j];
+            sc[t][3] = vp[(int64_t)w.perm[j] * pio.ldvp];
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+                sa[t][o] = 0.0;
+        }
+        __syncthreads();
+        int idx = t % n;
+        for (int k = 0; k < n; k += 4) {
+            real s4[4][4];
+            int id4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                id4[q] = idx;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    s4[q][a] = sc[idx][a];
+                idx = idx + 1 == n ? 0 : idx + 1;
+            }
+            real d2v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                real d2 = real(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const real dx = u[a] - s4[q][a];
+                    d2 += dx * dx;
+                }
+                d2v[q] = d2;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool hit = own && k + q < n && d2v[q] < eps2;
+                real kn = real(0), kd = real(0);
+                if (hit) {
+                    const real rl = nf_sqrt(d2v[q]) * hl;
+                    const real ex = nf_exp(-rl);
+                    const real t2 = d2v[q] * ie2;
+                    kn = ex - horner(pa, t2);
+                    acc[0] += kn * s4[q][3];
+                    if (NO > 1) {
+                        kd = rl * ex - horner(pd, t2);
+                        acc[NO > 1 ? 1 : 0] += kd * s4[q][3];
+                    }
+                }
+                if (sym && hit) {
+                    atomicAdd(&sa[id4[q]][0], (double)(kn * vi));
+                    if (NO > 1)
+                        atomicAdd(&sa[id4[q]][NO > 1 ? 1 : 0], (double)(kd * vi));
+                }
+            }
+        }
+        if (sym) {
+            __syncthreads();
+            if (t < n) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    const double c = sa[t][o];
+                    if (c != 0.0)
+                        unsafeAtomicAdd(ys + o * w.N + b + t, c);
+                }
+            }
+        }
+    };
+    const int32_t *toff = w.tile_off;
+    if (!none) {
+        for (int tz = t0[2]; tz <= t1[2]; ++tz) {
+            for (int ty = t0[1]; ty <= t1[1]; ++ty) {
+                float g2 = 0.f;
+                if (D > 1) {
+                    const float rlo = (float)(ty * w.tb[1] + w.m - 1);
+                    const float g = fmaxf(0.f, fmaxf(rlo - bmax[1], bmin[1] - (rlo + (float)w.tb[1])));
+                    g2 += g * g;
+                }
+                if (D > 2) {
+                    const float rlo = (float)(tz * w.tb[2] + w.m - 1);
+                    const float g = fmaxf(0.f, fmaxf(rlo - bmax[2], bmin[2] - (rlo + (float)w.tb[2])));
+                    g2 += g * g;
+                }
+                if (g2 >= eg * eg)
+                    continue;
+                const float rx = sqrtf(eg * eg - g2);
+                const int nbx = w.ext[0] - w.W + 1;
+                const int bx0 = max(0, (int)floorf(bmin[0] - rx) - w.m + 1);
+                const int bx1 = min(nbx - 1, (int)floorf(bmax[0] + rx) - w.m + 1);
+                if (bx1 < bx0)
+                    continue;
+                const int tx0 = bx0 / w.tb[0], tx1 = min(w.ntile[0] - 1, bx1 / w.tb[0]);
+                const int64_t trow = ((int64_t)tz * w.ntile[1] + ty) * w.ntile[0];
+                const int s = toff[trow + tx0], e = toff[trow + tx1 + 1];
+                if (e <= cs)  // all before the block's points
+                    continue;
+                for (int b = max(s, cs); b < min(e, ce); b += kNearBlock)  // the block's own points
+                    batch(b, min(b + kNearBlock, min(e, ce)), false);
+                for (int b = max(s, ce); b < e; b += kNearBlock)  // the points after them
+                    batch(b, min(b + kNearBlock, e), true);
+            }
+        }
+    }
+    if (own) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+            unsafeAtomicAdd(ys + o * w.N + i, (double)acc[o]);
+    }
+}
+
+// Yw[o][perm[j]][0] += ys[o][j], then ys[o][j] = 0, for the near-field windows
+// (blockIdx.y = window).
+__global__ void k_near_scatter(const WinDev *__restrict__ wins, int nout)
+{
+    const WinDev &w = wins[blockIdx.y];
+    if (!w.nf)
+        return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= w.N)
+        return;
+    const int64_t oj = w.perm[j];
+    for (int o = 0; o < nout; ++o) {
+        double *src = w.nf_ys + o * w.N + j;
+        w.Yw[(o * w.N + oj) * w.Rcap] += *src;
+        *src = 0.0;
+    }
+}
+
 // Per window: grad_ell += der_scale * sum of the derivative partials,
 // grad_sig += dsig * sum of the kernel partials (fixed order).
 __global__ void k_near_dot_finish(const WinDev *__restrict__ wins, int win, const double *partial, int nblk,
@@ -335,12 +540,49 @@ void launch_near_all(Engine &E, int R, int nout, IoArgs io, const double *Vt, in
     }
 }
 
+template <typename real, int D>
+void launch_near_sym_d(Engine &E, int nout, IoArgs io, hipStream_t st)
+{
+    const dim3 grid(E.nnear[D]);
+    if (nout > 1)
+        hipLaunchKernelGGL((k_near_sym<real, D, 2>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
+    else
+        hipLaunchKernelGGL((k_near_sym<real, D, 1>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
+}
+
+template <typename real>
+void launch_near_sym(Engine &E, int nout, IoArgs io, hipStream_t st)
+{
+    int64_t nmax = 0;
+    for (const WinDev &w : E.wdev)
+        nmax = std::max<int64_t>(nmax, w.nf ? w.N : 0);
+    if (E.nnear[1])
+        launch_near_sym_d<real, 1>(E, nout, io, st);
+    if (E.nnear[2])
+        launch_near_sym_d<real, 2>(E, nout, io, st);
+    if (E.nnear[3])
+        launch_near_sym_d<real, 3>(E, nout, io, st);
+    if (nmax > 0)
+        hipLaunchKernelGGL(k_near_scatter, dim3((unsigned)((nmax + 255) / 256), (unsigned)E.wdev.size()), dim3(256), 0,
+                           st, E.d_wins, nout);
+}
+
 }  // namespace
 
 void launch_near(Engine &E, int R, int nout, IoArgs io, hipStream_t st)
 {
     if (nout < 1)
         return;
+    bool square = true;  // every near-field window's targets are its sources
+    for (const Plan *pl : E.plans)
+        square = square && !pl->rect;
+    if (R == 1 && square) {
+        if (E.precision == ADDK_FP32)
+            launch_near_sym<float>(E, std::min(nout, 2), io, st);
+        else
+            launch_near_sym<double>(E, std::min(nout, 2), io, st);
+        return;
+    }
     launch_near_all<false>(E, R, std::min(nout, 2), io, nullptr, 0, nullptr, st);
 }
 

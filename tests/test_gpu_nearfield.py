@@ -44,15 +44,17 @@ def _plan(A, p, prec, **kw):
                   near_field=True, **kw)
 
 
+@pytest.mark.parametrize("R", [3, 1])
 @pytest.mark.parametrize("N", [1500, 37])
-def test_matches_the_corrected_method_oracle(A, N):
+def test_matches_the_corrected_method_oracle(A, N, R):
     """Same method, independent implementations: spread / FFT / interp plus the
     close-pair kernel against exact NDFTs plus a dense pair sum.  d = 1, 2, 3
     windows with their own l; n = 32 (more than one tile per axis, ragged
-    tiles); FP64 agreement to 1e-8 (the window's own error is far below)."""
-    p = WL.small_problem(N, 6, [[0], [1, 2], [3, 4, 5]], seed=301, R=3, ell=[0.05, 0.1, 0.2],
+    tiles); FP64 agreement to 1e-8 (the window's own error is far below).
+    R = 1 takes the symmetric close-pair kernel (each pair evaluated once)."""
+    p = WL.small_problem(N, 6, [[0], [1, 2], [3, 4, 5]], seed=301, R=R, ell=[0.05, 0.1, 0.2],
                          sigma=[1.0, 0.8, 0.6], kernel=WL.MATERN12, n=32, m=6)
-    _say("near field vs corrected oracle N=%d" % N)
+    _say("near field vs corrected oracle N=%d R=%d" % (N, R))
     plan = _plan(A, p, "fp64")
     Y, dl, ds = plan.dmatvec(cuda(p.V))
     Yo, dlo, dso = NF.nearfield_fast_sum_oracle(p.X, p.windows, p.ell, p.sigma, p.V, p.n, want_derivs=True)
@@ -135,6 +137,41 @@ def test_targets_and_batch(A):
         torch.cuda.synchronize()
         for y, y0 in zip(B.outputs(), own):
             assert relerr(y.cpu().numpy(), y0) < 1e-12
+    B.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_symmetric_pairs_equal_one_sided(A, prec, tol):
+    """One right-hand side (each close pair evaluated once, for both points)
+    against the same vector as both columns of an R = 2 product (each pair
+    from both ends): equal up to rounding, also on a second call (the sums
+    by sorted position are cleared after each use).  Gaussian points, so
+    that tiles hold full and partial 64-point batches."""
+    p = WL.small_problem(20000, 6, [[0, 1, 2], [3, 4], [5]], seed=308, R=1, ell=[0.1, 0.05, 0.2],
+                         sigma=[1.0, 0.7, 0.9], kernel=WL.MATERN12, n=64, m=6, dist="gauss")
+    _say("near field symmetric vs one-sided %s" % prec)
+    plan = _plan(A, p, prec)
+    v = cuda(p.V[:, :1])
+    two = cuda(np.concatenate([p.V[:, :1], p.V[:, :1]], axis=1))
+    Y2, dl2, ds2 = plan.dmatvec(two)
+    for _ in range(2):
+        Y1, dl1, ds1 = plan.dmatvec(v)
+        assert relerr(Y1.cpu().numpy(), Y2.cpu().numpy()[:, :1]) < tol
+        for w in range(3):
+            assert relerr(dl1[w].cpu().numpy(), dl2[w].cpu().numpy()[:, :1]) < tol
+            assert relerr(ds1[w].cpu().numpy(), ds2[w].cpu().numpy()[:, :1]) < tol
+    _say("near field symmetric batch replays")
+    q = WL.small_problem(3000, 3, [[0, 1], [2]], seed=309, R=1, ell=[0.1, 0.2], sigma=[1.0, 1.0],
+                         kernel=WL.MATERN12, n=64, m=6)
+    plans = [plan, _plan(A, q, prec)]
+    own = [pl.matvec(cuda(x)).cpu().numpy() for pl, x in zip(plans, (p.V[:, :1], q.V))]
+    B = A.Batch(plans, R=1)
+    B.set_inputs([v, cuda(q.V)])
+    for _ in range(3):
+        B.launch()
+        torch.cuda.synchronize()
+        for y, y0 in zip(B.outputs(), own):
+            assert relerr(y.cpu().numpy(), y0) < tol
     B.close()
 
 
