@@ -518,26 +518,54 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
         cand[idx] = map[((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx];
     }
     __syncthreads();
+    // Per row of candidate cells, the cells holding items (a ballot over the
+    // row) are taken four at a time: the loads of all four are issued before
+    // any is added, so that a wave keeps four cells' reads in flight.  The sum
+    // order is the row order, as in a plain loop over the cells.
+    const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
     for (int dz = wave; dz < nz; dz += 4) {
         const int bz = z0 + dz, oz = gz - bz;
         for (int dy = 0; dy < ny; ++dy) {
             const int by = y0 + dy, oy = gy - by;
             const int2 *crow = cand + (dz * ny + dy) * nx;
-            for (int dx = 0; dx < nx; ++dx) {
-                const int2 it = crow[dx];
-                if (it.y == 0)
-                    continue;
-                const int cnt = it.y & 0xffff, nzc = (it.y >> 16) + 1;
-                const int ox = gx - x0 - dx;
-                if ((unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
-                    (unsigned)oz < (unsigned)(W + nzc - 1)) {
-                    const int tap = (oz * W + oy) * W + ox;
-                    for (int i = it.x; i < it.x + cnt; ++i) {
-                        const f4 *src = (const f4 *)(scratch + (((int64_t)i * nrb + rb) * ((W + 1) * WW) + tap) * 16);
-                        acc[0] += src[0];
-                        acc[1] += src[1];
-                        acc[2] += src[2];
-                        acc[3] += src[3];
+            uint64_t live = __ballot(lane < nx && crow[lane < nx ? lane : 0].y != 0);
+            while (live) {
+                int2 its[4];
+                bool in[4];
+                const f4 *src[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int dx = live ? __builtin_ctzll(live) : 0;
+                    const bool valid = live != 0;
+                    live &= live - 1;
+                    its[k] = valid ? crow[dx] : int2{0, 0};
+                    const int nzc = (its[k].y >> 16) + 1;
+                    const int ox = gx - x0 - dx;
+                    in[k] = valid && (unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
+                            (unsigned)oz < (unsigned)(W + nzc - 1);
+                    const int tap = in[k] ? (oz * W + oy) * W + ox : 0;
+                    src[k] = (const f4 *)(scratch + (((int64_t)its[k].x * nrb + rb) * ((W + 1) * WW) + tap) * 16);
+                }
+                f4 v[4][4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        v[k][j] = in[k] ? src[k][j] : zero4;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[j] += v[k][j];
+                    // further items of a cell with more than one (rare)
+                    const int cnt = its[k].y & 0xffff;
+                    for (int i = 1; i < cnt; ++i) {
+                        if (!in[k])
+                            break;
+                        const f4 *s2 = src[k] + (int64_t)i * nrb * ((W + 1) * WW) * 4;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[j] += s2[j];
                     }
                 }
             }
