@@ -90,11 +90,13 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
 }
 
 // Stream the z-slabs of an (SX x SW x nz) box of NO output grids, starting at
-// grid cell (x0, y0, z0), through LDS (double buffered, register prefetch) and
-// accumulate the products of the wave's NG point groups.  Cells outside the
-// window's grid box read as zero.  Every thread of the block calls this with
-// the same nz, so the barriers inside match.
-template <int SW, int SX, int NT, int NG, int NO>
+// grid cell (x0, y0, z0), through LDS (NB = 2: double buffered; NB = 1: one
+// buffer and a second barrier per slab, for more blocks per CU; the next
+// slab is prefetched into registers either way) and accumulate the products
+// of the wave's NG point groups.  Cells outside the window's grid box read as
+// zero.  Every thread of the block calls this with the same nz, so the
+// barriers inside match.
+template <int SW, int SX, int NT, int NG, int NO, int NB = 2>
 __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
                                              int y0, int z0, int sx, int sy, int nz, f4 (&acc)[NO][NG],
                                              const float (&wxq)[NG][NT], const float *wyl,
@@ -160,9 +162,12 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
             live[g] = __builtin_amdgcn_readfirstlane(__any(in)) != 0;
             wz[g] = (!zmask || in) ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
         }
-        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, live, &slab[oz & 1][0][0], sy, q, mrow);
-        if (oz + 1 < nz)
-            store((oz + 1) & 1);
+        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, live, &slab[NB == 2 ? oz & 1 : 0][0][0], sy, q, mrow);
+        if (oz + 1 < nz) {
+            if (NB == 1)
+                __syncthreads();  // every wave is done with the buffer
+            store(NB == 2 ? (oz + 1) & 1 : 0);
+        }
         __syncthreads();
     }
 }
@@ -213,7 +218,7 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
     // window; the window there evaluates to ~2 m b e^{-bm} (< 1e-10), so no mask
     // is applied in this FP32 kernel; a group whose points all lie in one of
     // the cells skips its outside slab altogether.
-    stream_slabs<W, W, NT, NG, NO>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
+    stream_slabs<W, W, NT, NG, NO, 1>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -236,10 +241,13 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
 // the dispatch below is a uniform branch and every wave runs the same slab
 // loop (and barriers).
 template <int W, int NO>
-__global__ __launch_bounds__(kBlock) void k_interp_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                        int R)
+__global__ __launch_bounds__(kBlock, NO == 2 ? 5 : 1) void k_interp_mfma(const WinDev *__restrict__ wins,
+                                                                         const Chunk *__restrict__ items, int R)
 {
-    __shared__ __align__(16) float slab[2][NO][W * W][16];
+    // one slab buffer (31 KB of LDS with the y weights at 2m = 12, two outputs)
+    // and, with two outputs, at most 96 registers (a few spills at the slab
+    // barriers): five blocks per CU
+    __shared__ __align__(16) float slab[1][NO][W * W][16];
     __shared__ __align__(16) float wy_lds[4 * 4 * W * 16];
     const Chunk it = items[blockIdx.x];
     const WinDev &w = wins[it.win];
@@ -652,7 +660,8 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<SY, SX, 4, NG, NO>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz, lbz, true);
+    stream_slabs<SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz, lbz,
+                                       true);
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -673,10 +682,12 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
 // cells of the tile) against the tile's (4 + 2m - 1)^3 sub-grid, taken as one
 // super-cell with x padded to 16; weights outside a point's support are zero.
 template <int W, int NO>
-__global__ __launch_bounds__(kBlock) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
-                                                             const Chunk *__restrict__ chunks, int R)
+__global__ __launch_bounds__(kBlock, NO == 2 ? 3 : 1) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
+                                                                              const Chunk *__restrict__ chunks, int R)
 {
-    __shared__ __align__(16) float slab[2][NO][(3 + W) * 16][16];
+    // one slab buffer (46 KB of LDS with the y weights at 2m = 12, two outputs)
+    // and, with two outputs, at most 168 registers: three blocks per CU
+    __shared__ __align__(16) float slab[1][NO][(3 + W) * 16][16];
     __shared__ __align__(16) float wy_lds[4 * 4 * (3 + W) * 16];
     const Chunk ch = chunks[blockIdx.x];
     const WinDev &w = wins[ch.win];
