@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     C *tw = (C *)smem_raw;
     C *buf0 = tw + call.nos_lds / 2;
     C *buf1 = buf0 + L * call.nos_lds;
-    C *buf2 = buf1 + L * call.nos_lds;
+    C *buf2 = buf1 + L * call.nos_lds;  // allocated for MODE 2 only
     for (int q = threadIdx.x; q < nos / 2; q += kBlock)
         tw[q] = ((const C *)w.tw)[q];
 
@@ -1485,7 +1485,10 @@ static void launch_fft(Engine &E, int st_id, int ny, FftCall call, hipStream_t s
         return;
     constexpr int LF = sizeof(real) == 4 ? 16 : 8;  // lines per block for grids up to 128 points
     call.nos_lds = E.nos_max;
-    const size_t sh = ((size_t)E.nos_max / 2 + 3 * (size_t)E.fft_L * E.nos_max) * sizeof(cpx<real>);
+    // twiddles and the line buffers: two for a plain pass, a third for the
+    // inverse transforms of the fused pass (more blocks per CU without it)
+    const size_t nbuf = MODE == 2 ? 3 : 2;
+    const size_t sh = ((size_t)E.nos_max / 2 + nbuf * (size_t)E.fft_L * E.nos_max) * sizeof(cpx<real>);
     if (E.fft_L == LF)
         hipLaunchKernelGGL((k_fft<real, AXIS, MODE, LF>), dim3(E.ngroups[st_id], ny), dim3(kBlock), sh, st, E.d_wins,
                            E.d_groups[st_id], call);
