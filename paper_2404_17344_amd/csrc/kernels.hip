@@ -883,13 +883,15 @@ addk_status engine_gsi(Engine &E, const std::vector<const double *> &B64, const 
 // ---------------------------------------------------------------------------
 // host side
 
-// Lines per FFT block: 16 (FP32) or 8 (FP64) lines of up to 128 points; half
-// as many when a grid has 256 points per edge, so that the three line buffers
+// Lines per FFT block: 8 in FP32 (more blocks per CU than 16, and 64-byte
+// runs per access in the y and z passes; 4 was slower), 8 in FP64 for lines of
+// up to 128 points and 4 for 256-point grids, so that the three line buffers
 // stay within 64 KiB of LDS.
 static int lines_per_group(int precision, int nos_max)
 {
-    const int L = precision == ADDK_FP32 ? 16 : 8;
-    return nos_max > 128 ? L / 2 : L;
+    if (precision == ADDK_FP32)
+        return 8;
+    return nos_max > 128 ? 4 : 8;
 }
 
 static size_t real_size(int precision) { return precision == ADDK_FP32 ? sizeof(float) : sizeof(double); }
