@@ -116,6 +116,33 @@ def test_cg_solves_the_regularised_system(A):
     assert np.max(np.linalg.norm(res, axis=0) / np.linalg.norm(y, axis=0)) < 1e-8
 
 
+def test_cg_near_field_matern_one_rhs(A):
+    """CG on a near-field corrected Matern-1/2 plan with one right-hand side
+    (its products evaluate each close pair once, for both points): the residual
+    recomputed through the two-column product (each pair from both ends) meets
+    the tolerance, and the residual with the direct kernel matrix is the
+    product's error, (K - K_fast) x, about 1e-5 of |K x| <= 2 |y|."""
+    rng = np.random.default_rng(95)
+    N = 1200
+    X = WL.minmax_quarter(rng.standard_normal((N, 6)))
+    ell = [0.1, 0.07, 0.15]
+    sig = [1.0, 0.8, 0.6]
+    y = rng.standard_normal((N, 1))
+    beta = 0.05
+    _say("cg near field matern fp64")
+    plan = A.Plan(X, WINS, ell, sig, kernel="matern12", n=64, m=6, near_field=True)
+    x, it, rel = plan.cg(cuda(y), beta=beta, tol=1e-10, maxit=2000)
+    assert 0 < it < 2000 and rel[0] <= 1e-10
+    xn = x.cpu().numpy()
+    both = plan.matvec(cuda(np.concatenate([xn, xn], axis=1))).cpu().numpy()
+    for c in range(2):
+        r = both[:, c:c + 1] + beta * xn - y
+        assert np.linalg.norm(r) / np.linalg.norm(y) < 1e-9
+    K = oracle_direct(X, WINS, WL.MATERN12, ell, sig, np.eye(N))
+    r = K @ xn + beta * xn - y
+    assert np.linalg.norm(r) / np.linalg.norm(y) < 1e-4
+
+
 def test_cg_krr_additive_workload(A):
     """Kernel ridge regression on the additive 1e5-point workload (FP32 products,
     tolerance 1e-3 as in the paper's solver runs); the residual recomputed with
