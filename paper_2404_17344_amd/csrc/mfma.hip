@@ -327,27 +327,24 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             pvv[k] = (p < np && r < R) ? ((const float *)pio.Vp)[(int64_t)w.perm[it.start + p0 + p] * pio.ldvp + r] : 0.f;
         }
     };
+    // Straight-line code (selects, no branches) so that the compiler can
+    // interleave it with the matrix ops of the current round.
     auto store_raw = [&](Round &d, int p0) {
         const int np = min(PB, it.count - p0);
         float *pw = &d.pw[0][0];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
-            if (e < NWE) {
-                const int p = e / PS, o = e - p * PS;
-                float v = 0.f;
-                if (o < 2 * W) {
-                    const int dd = o < W ? 0 : 1;
-                    v = kb_psi_f(pcs[k] - (float)((dd == 0 ? bx : by) + o - dd * W), mm, kb, ie);
-                } else {
-                    // z slab oz of the item: inside the point's own window only
-                    const int oz = o - 2 * W;
-                    const int dz = (int)floorf(pcs[k]) - w.m + 1 - bz;
-                    if ((unsigned)(oz - dz) < (unsigned)W)
-                        v = kb_psi_f(pcs[k] - (float)(bz + oz), mm, kb, ie);
-                }
-                pw[e] = p < np ? v : 0.f;
-            }
+            const int p = e / PS, o = e - p * PS;
+            // x and y: tap o of the item's block; z: slab oz of the item, inside the
+            // point's own window only
+            const int oz = o - 2 * W;
+            const int dz = (int)floorf(pcs[k]) - w.m + 1 - bz;
+            const float c = o < W ? (float)(bx + o) : (o < 2 * W ? (float)(by + o - W) : (float)(bz + oz));
+            const bool live = p < np && (o < 2 * W || (unsigned)(oz - dz) < (unsigned)W);
+            const float v = kb_psi_f(pcs[k] - c, mm, kb, ie);
+            if (KW * kBlock == NWE || e < NWE)
+                pw[e] = live ? v : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -376,14 +373,22 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 
     load(0);
     store_raw(rd[0], 0);
+    if (PB < it.count)
+        load(PB);  // the registers run one round ahead of the window values
     __syncthreads();
     products(rd[0]);
     __syncthreads();
     int buf = 0;
     for (int p0 = 0; p0 < it.count; p0 += PB) {
         const bool more = p0 + PB < it.count;
-        if (more)
-            load(p0 + PB);  // in flight during this round's products
+        // the next round's window values go to the other buffer, which no wave
+        // reads any more (every wave passed the last round's closing barrier);
+        // then the registers take the round after it
+        if (more) {
+            store_raw(rd[buf ^ 1], p0 + PB);
+            if (p0 + 2 * PB < it.count)
+                load(p0 + 2 * PB);
+        }
         Round &cr = rd[buf];
         // Operands of one K step (four points): A = x-y weight products of the
         // M tiles, and the B factors (RHS value, z weights of the wave's slabs).
@@ -428,7 +433,6 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.ax[j], bx, accx[j], 0, 0, 0);
         }
         if (more) {
-            store_raw(rd[buf ^ 1], p0 + PB);
             __syncthreads();
             products(rd[buf ^ 1]);
         }
