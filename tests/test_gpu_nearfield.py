@@ -1,8 +1,9 @@
 """GPU parity of the near-field corrected Matern-1/2 products (ADDK_NEAR_FIELD):
 against the oracle of the same corrected method (FP64, tight), against the
 direct sum at the size of the derivative workload (N = 1e5, three d = 3
-windows, FP64 and FP32), for the vjp, for target points, inside a batch and
-on degenerate inputs."""
+windows, FP64 and FP32), for the vjp, for target points, inside a batch, for
+the symmetric one-right-hand-side kernel against the one-sided one, and on
+degenerate inputs."""
 import sys
 
 import numpy as np
@@ -173,6 +174,30 @@ def test_symmetric_pairs_equal_one_sided(A, prec, tol):
         for y, y0 in zip(B.outputs(), own):
             assert relerr(y.cpu().numpy(), y0) < tol
     B.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-5), ("fp32", 1e-5)])
+def test_targets_one_rhs(A, prec, tol):
+    """Separate target points with one right-hand side (the one-sided
+    close-pair kernel, since targets and sources differ): the targets' rows of
+    the stacked direct sum, for K v and the derivative products."""
+    rng = np.random.default_rng(310)
+    wins = [[0, 1, 2], [3, 4]]
+    Xs = WL.minmax_quarter(rng.standard_normal((5000, 5)))
+    Xt = rng.uniform(-0.2, 0.2, (700, 5))
+    V = rng.standard_normal((5000, 1))
+    ell, sig = [0.1, 0.06], [1.0, 0.7]
+    _say("near field targets R=1 %s" % prec)
+    pt = A.Plan(Xs, wins, ell, sig, kernel="matern12", n=64, m=6, precision=prec, near_field=True, targets=Xt)
+    Y, dl, ds = pt.dmatvec(cuda(V))
+    X = np.concatenate([Xs, Xt])
+    Vz = np.concatenate([V, np.zeros((Xt.shape[0], 1))])
+    rows = np.arange(5000, 5700)
+    Yo, dlo, dso = oracle_direct(X, wins, WL.MATERN12, ell, sig, Vz, rows=rows, want_derivs=True)
+    assert relerr(Y.cpu().numpy(), Yo) < tol
+    for w in range(2):
+        assert relerr(dl[w].cpu().numpy(), dlo[w]) < 2 * tol
+        assert relerr(ds[w].cpu().numpy(), dso[w]) < tol
 
 
 def test_degenerate_inputs_and_refusals(A):
