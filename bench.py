@@ -5,7 +5,8 @@ Workload (the large configuration): N = 1e6 points, D = 15 i.i.d. N(0,1)
 features min-max scaled to [-1/4, 1/4], 5 consecutive d = 3 windows, Gaussian
 kernel l_w = 0.1, sigma_w = 1, R = 16 right-hand sides, n = 64, m = 6,
 oversampling 2; FP32 spreading/FFT/interpolation, FP64 multipliers and window
-sums.  Synthetic data (seeded); inputs resident in HBM before timing.
+sums (``--precision fp64``: every step in FP64, against the FP64 vector peak).
+Synthetic data (seeded); inputs resident in HBM before timing.
 
 One step = one ``addk_dmatvec`` call producing K V and (dK/dl_w) V for all five
 windows for the 16 right-hand sides.  ``value`` = right-hand-side vectors per
@@ -102,7 +103,7 @@ def main():
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration) and exit")
     ap.add_argument("--workload", choices=["large", "matern-near-field"], default="large")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
-                    help="precision of the matern-near-field workload (the large one is FP32)")
+                    help="engine precision (FP32: FP32 grids with FP64 multipliers and sums; FP64: every step)")
     ap.add_argument("--n", type=int, default=64, help="bandwidth of the matern-near-field workload")
     args = ap.parse_args()
 
@@ -139,9 +140,10 @@ def main():
     V = torch.from_numpy(np.ascontiguousarray(p.V.T)).to(dev).t()
     torch.cuda.synchronize()
 
-    log("plan (fp32)")
+    fp64 = args.precision == "fp64"
+    log("plan (%s)" % args.precision)
     t0 = time.perf_counter()
-    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision="fp32")
+    plan = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision=args.precision)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
 
@@ -183,17 +185,18 @@ def main():
     tot_ms, launches = stages[dom]
     avg_ms = tot_ms / max(launches, 1)
     achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dom) if N == 1000000 else None,
+    peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(dom) if N == 1000000 and not fp64 else None,
                 "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops[dom],
                 "point_window_pairs": pts[dom]}
     stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
 
     accuracy = {}
-    Y32 = out[0].cpu().numpy()
+    Y32 = out[0].cpu().numpy()   # the timed path's outputs (FP64 values in either mode)
     dl32 = out[1].cpu().numpy()
-    if not args.no_accuracy:
+    if not args.no_accuracy and not fp64:
         log("fp64 reference run")
         del out
         plan64 = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision="fp64")
@@ -240,13 +243,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
         "config": {"workload": "large additive Gaussian: N=%d, D=15 N(0,1) features min-max scaled, 5 windows d=3, "
                                "l=0.1, sigma=1, R=16, n=64, m=6, oversampling 2" % N,
                    "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "oversampling": p.oversampling,
                    "step": "addk_dmatvec: K V and dK/dl_w V, all windows",
-                   "precision": "FP32 spread/FFT/interp, FP64 multipliers and window sums"},
+                   "precision": "FP64 every step" if fp64 else
+                                "FP32 spread/FFT/interp, FP64 multipliers and window sums"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,

@@ -187,8 +187,8 @@ struct Engine {
     int2 *d_dmap[2] = {nullptr, nullptr};        // base-cell maps of all windows (per 2m = 8, 12)
     LineGroup *d_gtiles[2] = {nullptr, nullptr};  // output tiles of the dense block gather
     int ngtiles[2] = {0, 0};
-    float *scratch[2] = {nullptr, nullptr};       // per-item dense spread blocks
-    int64_t scratch_cap[2] = {0, 0};              // floats
+    void *scratch[2] = {nullptr, nullptr};        // per-item dense spread blocks (engine precision, d = 3)
+    int64_t scratch_cap[2] = {0, 0};              // elements
     LineGroup *d_groups[ST_COUNT] = {};
     int ngroups[ST_COUNT] = {};
     int maxvol[4] = {0, 0, 0, 0};  // largest tile sub-grid volume per d

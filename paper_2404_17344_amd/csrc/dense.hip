@@ -74,10 +74,18 @@ constexpr int dense_block_cells()
 
 // ---------------------------------------------------------------------------
 // spread, dense cells.  blockDim.x = OUT * NRG threads; thread (q, rg) owns
-// outer tap q and RHS rg*RT .. rg*RT+RT-1 of the block's RHS range.
+// outer tap q and RHS rg*RT .. rg*RT+RT-1 of the block's RHS range.  The block
+// is added to the grid with atomics, or (d = 3, scratch given) stored into the
+// item's scratch slots for k_gather_blocks: slot item * nrb + r / 16 holds
+// [oz][oy][ox][r % 16] over the 2m + 1 slabs, the layout of the matrix-core
+// spread (the atomics are executed beyond L2 on this chip and are slow).
+// Blocks hold at most 4 RHS groups of OUT threads (see spread_dense_w): the
+// bound lets d = 3 keep its (2m + 1) x RT accumulators in registers.
 template <typename real, int D, int W, int RT>
-__global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                       IoArgs io, int R, int NRG)
+__global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const WinDev *__restrict__ wins,
+                                                                           const Chunk *__restrict__ items, IoArgs io,
+                                                                           int R, int NRG, real *__restrict__ scratch,
+                                                                           int nrb)
 {
     constexpr int OUT = D == 3 ? W * W : W;  // taps owned by thread groups
     constexpr int IN = D == 1 ? 1 : W;       // taps accumulated per thread (last dimension)
@@ -185,7 +193,11 @@ __global__ __launch_bounds__(1024) void k_spread_dense(const WinDev *__restrict_
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const int r = r0 + rg * RT + i;
-            if (r < R)
+            if (D == 3 && scratch != nullptr) {
+                if (r < R)
+                    scratch[(((int64_t)blockIdx.x * nrb + (r >> 4)) * ((W + 1) * W * W) + (k * W + oy) * W + ox) * 16 +
+                            (r & 15)] = acc[k][i];
+            } else if (r < R)
                 gadd(&G[((int64_t)(r >> 1) * w.szG + cell) * 2 + (r & 1)], acc[k][i]);
         }
     }
@@ -319,14 +331,23 @@ static void spread_dense_w(Engine &E, int R, IoArgs io, hipStream_t st)
     const int OUT = D == 3 ? W * W : W;
     const Chunk *items = E.d_dense_sp[D][E.cur_dense];
     const int nitems = E.ndense_sp[D][E.cur_dense];
+    // d = 3: per-item blocks in scratch (the block's RHS range lies in one
+    // 16-wide slot block: all R when R <= 16, else 16 per block)
+    real *scratch = D == 3 ? (real *)E.scratch[E.cur_dense] : nullptr;
+    const int nrb = (R + 15) / 16;
     if (R == 1) {
         dim3 grid(nitems, R);
-        hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, items, io, R, 1);
+        hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, items, io, R, 1, scratch,
+                           nrb);
         return;
     }
-    const int nrg = std::min(4, (R + 3) / 4);
-    dim3 grid(nitems, (R + 4 * nrg - 1) / (4 * nrg));
-    hipLaunchKernelGGL((k_spread_dense<real, D, W, 4>), grid, dim3(OUT * nrg), 0, st, E.d_wins, items, io, R, nrg);
+    // d = 3: two RHS per thread in FP32 and one in FP64, so that the (2m + 1) x RT
+    // accumulators stay in registers (more spill)
+    constexpr int RT = D == 3 ? (sizeof(real) == 4 ? 2 : 1) : 4;
+    const int nrg = std::min(4, (R + RT - 1) / RT);
+    dim3 grid(nitems, (R + RT * nrg - 1) / (RT * nrg));
+    hipLaunchKernelGGL((k_spread_dense<real, D, W, RT>), grid, dim3(OUT * nrg), 0, st, E.d_wins, items, io, R, nrg,
+                       scratch, nrb);
 }
 
 template <typename real, int D, int W, int RB>

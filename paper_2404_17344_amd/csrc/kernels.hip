@@ -1368,21 +1368,22 @@ addk_status engine_ensure_workspace(Engine &E, int R)
             off += E.probs[p].N * ld;
         }
     }
-    // per-item blocks of the matrix-core dense spread: items x RHS blocks x (2m)^3 x 16
+    // per-item blocks of the d = 3 dense spread (either kernel), in the engine's
+    // precision: items x RHS blocks x (2m + 1) (2m)^2 x 16
     for (int wi = 0; wi < 2; ++wi) {
         const int W = wi == 0 ? 8 : 12;
         const int64_t need = (int64_t)E.ndense_sp[3][wi] * ((rcap + 15) / 16) * (W + 1) * W * W * 16;
         free_dev(E.scratch[wi]);
         E.scratch[wi] = nullptr;
         E.scratch_cap[wi] = 0;
-        if (need > 0 && E.precision == ADDK_FP32 && !E.no_mfma) {
-            e = hipMalloc(&E.scratch[wi], need * sizeof(float));
+        if (need > 0) {
+            e = hipMalloc(&E.scratch[wi], need * (int64_t)real_size(E.precision));
             if (e != hipSuccess) {
                 set_error("dense spread scratch allocation failed");
                 return ADDK_ERR_OOM;
             }
             E.scratch_cap[wi] = need;
-            E.ws_bytes += need * (int64_t)sizeof(float);
+            E.ws_bytes += need * (int64_t)real_size(E.precision);
         }
     }
     char *p = (char *)E.ws;
@@ -1529,10 +1530,11 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         for (int wi = 0; wi < 2; ++wi) {
             if (!E.ndense_sp[d][wi])
                 continue;
-            if (d == 3 && use_mfma(E, ADDK_KNOB_SPREAD_MFMA, R) && E.scratch[wi]) {
+            if (d == 3 && E.scratch[wi]) {  // per-item blocks, then the gather
                 {
                     StageTimer t(E, PS_SPREAD_DENSE, st);
-                    launch_spread_mfma(E, wi, R, io, st);
+                    if (!(use_mfma(E, ADDK_KNOB_SPREAD_MFMA, R) && launch_spread_mfma(E, wi, R, io, st)))
+                        launch_spread_dense(E, d, wi, R, io, st);
                 }
                 StageTimer t(E, PS_GATHER, st);
                 launch_gather_blocks(E, wi, R, st);

@@ -491,11 +491,29 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 // (2m)^3 window block overlaps the tile and adds the overlapping part of each
 // of its items' blocks.  Every grid value is written by exactly one thread, so
 // no atomics are needed and the sum order is fixed.
-template <int W>
+template <typename real>
+struct GatherTypes;
+template <>
+struct GatherTypes<float> {
+    typedef f4 v4;
+    typedef float2 v2;
+    static constexpr int CB = 4;  // cells whose loads are in flight together
+};
+template <>
+struct GatherTypes<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    typedef double2 v2;
+    static constexpr int CB = 2;
+};
+
+template <int W, typename real>
 __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restrict__ wins,
                                                           const LineGroup *__restrict__ tiles,
-                                                          const float *__restrict__ scratch, int R)
+                                                          const real *__restrict__ scratch, int R)
 {
+    typedef typename GatherTypes<real>::v4 f4;  // four RHS values
+    typedef typename GatherTypes<real>::v2 r2;
+    constexpr int CB = GatherTypes<real>::CB;
     constexpr int WW = W * W;
     __shared__ f4 red[3][64][4];
     __shared__ int2 cand[(W + 3) * (W + 3) * (W + 4)];  // base-cell map of the candidate region
@@ -517,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     f4 acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+        acc[i] = f4{real(0), real(0), real(0), real(0)};
     // anchors: an item anchored at bz covers z cells bz .. bz + 2m - 2 + (nzc - 1)
     const int z0 = max(0, tz * 4 - W), z1 = min(nb2 - 1, tz * 4 + 3);
     const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
@@ -531,10 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     }
     __syncthreads();
     // Per row of candidate cells, the cells holding items (a ballot over the
-    // row) are taken four at a time: the loads of all four are issued before
-    // any is added, so that a wave keeps four cells' reads in flight.  The sum
+    // row) are taken CB at a time: the loads of all of them are issued before
+    // any is added, so that a wave keeps CB cells' reads in flight.  The sum
     // order is the row order, as in a plain loop over the cells.
-    const f4 zero4 = f4{0.f, 0.f, 0.f, 0.f};
+    const f4 zero4 = f4{real(0), real(0), real(0), real(0)};
     for (int dz = wave; dz < nz; dz += 4) {
         const int bz = z0 + dz, oz = gz - bz;
         for (int dy = 0; dy < ny; ++dy) {
@@ -542,11 +560,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
             const int2 *crow = cand + (dz * ny + dy) * nx;
             uint64_t live = __ballot(lane < nx && crow[lane < nx ? lane : 0].y != 0);
             while (live) {
-                int2 its[4];
-                bool in[4];
-                const f4 *src[4];
+                int2 its[CB];
+                bool in[CB];
+                const f4 *src[CB];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < CB; ++k) {
                     const int dx = live ? __builtin_ctzll(live) : 0;
                     const bool valid = live != 0;
                     live &= live - 1;
@@ -558,14 +576,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
                     const int tap = in[k] ? (oz * W + oy) * W + ox : 0;
                     src[k] = (const f4 *)(scratch + (((int64_t)its[k].x * nrb + rb) * ((W + 1) * WW) + tap) * 16);
                 }
-                f4 v[4][4];
+                f4 v[CB][4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < CB; ++k)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         v[k][j] = in[k] ? src[k][j] : zero4;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < CB; ++k) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         acc[j] += v[k][j];
@@ -599,13 +617,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
             acc[i] += red[k][lane][i];
     if (gx >= ex || gy >= ey || gz >= ez)
         return;
-    float *G = (float *)w.G;
+    real *G = (real *)w.G;
     const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
     // all loads of the cell's 8 complex grid values first, then the stores
-    float2 g[8];
+    r2 g[8];
 #pragma unroll
     for (int p = 0; p < 8; ++p)
-        g[p] = r0 + 2 * p < R ? *(const float2 *)(G + ((int64_t)((r0 >> 1) + p) * w.szG + c) * 2) : float2{0.f, 0.f};
+        g[p] = r0 + 2 * p < R ? *(const r2 *)(G + ((int64_t)((r0 >> 1) + p) * w.szG + c) * 2) : r2{real(0), real(0)};
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
         const int r = r0 + 2 * p;
@@ -742,13 +760,12 @@ bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
     if (E.precision != ADDK_FP32 || !E.ndense_sp[3][wi] || !E.scratch[wi])
         return false;
+    float *scratch = (float *)E.scratch[wi];
     dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16);
     if (wi == 0)
-        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R,
-                           E.scratch[wi]);
+        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R, scratch);
     else
-        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R,
-                           E.scratch[wi]);
+        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R, scratch);
     return true;
 }
 
@@ -757,11 +774,17 @@ void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st)
     if (!E.ngtiles[wi])
         return;
     dim3 grid(E.ngtiles[wi], (R + 15) / 16);
-    if (wi == 0)
-        hipLaunchKernelGGL(k_gather_blocks<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], E.scratch[wi], R);
+    const float *sf = (const float *)E.scratch[wi];
+    const double *sd = (const double *)E.scratch[wi];
+    const bool fp64 = E.precision == ADDK_FP64;
+    if (wi == 0 && !fp64)
+        hipLaunchKernelGGL((k_gather_blocks<8, float>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sf, R);
+    else if (wi == 0)
+        hipLaunchKernelGGL((k_gather_blocks<8, double>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sd, R);
+    else if (!fp64)
+        hipLaunchKernelGGL((k_gather_blocks<12, float>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sf, R);
     else
-        hipLaunchKernelGGL(k_gather_blocks<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], E.scratch[wi],
-                           R);
+        hipLaunchKernelGGL((k_gather_blocks<12, double>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sd, R);
 }
 
 }  // namespace addk
