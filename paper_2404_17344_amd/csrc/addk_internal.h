@@ -39,7 +39,12 @@ constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
 constexpr int kDenseChunk = 256; // maximal points per dense interp item
 constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item (one window block each;
                                    // bounds the FP32 accumulation length)
-constexpr int kMfmaMinR = 8;     // fewest RHS for which the matrix-core dense kernels are used
+// Fewest RHS for which untuned engines use a matrix-core variant (it always
+// computes 16 columns): where the autotuner's choice switches on the large
+// workload (1e6 points, five d = 3 windows, K and dK/dl outputs).
+constexpr int kMfmaMinRSpread = 3;       // dense spread
+constexpr int kMfmaMinRInterpTile = 3;   // sparse-tile interp
+constexpr int kMfmaMinRInterpDense = 6;  // dense interp
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).

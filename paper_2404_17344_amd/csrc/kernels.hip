@@ -1607,12 +1607,15 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
 
 // Matrix-core variant of a stage: off on FP64 engines and with
 // ADDK_VECTOR_ALU_ONLY; otherwise the knob decides, and untuned engines also
-// require enough RHS to fill most of a 16-wide block.
+// require the stage's fewest RHS (kMfmaMinR*).
 bool use_mfma(const Engine &E, uint32_t knob, int R)
 {
     if (E.no_mfma || E.precision != ADDK_FP32 || !(E.knobs & knob))
         return false;
-    return E.tuned || R >= kMfmaMinR;
+    const int rmin = knob == ADDK_KNOB_SPREAD_MFMA       ? kMfmaMinRSpread
+                     : knob == ADDK_KNOB_INTERP_TILE_MFMA ? kMfmaMinRInterpTile
+                                                          : kMfmaMinRInterpDense;
+    return E.tuned || R >= rmin;
 }
 
 addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io, hipStream_t st)
