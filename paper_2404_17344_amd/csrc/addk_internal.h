@@ -42,7 +42,7 @@ constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item
 // Fewest RHS for which untuned engines use a matrix-core variant (it always
 // computes 16 columns): where the autotuner's choice switches on the large
 // workload (1e6 points, five d = 3 windows, K and dK/dl outputs).
-constexpr int kMfmaMinRSpread = 3;       // dense spread
+constexpr int kMfmaMinRSpread = 3;       // dense spread (and R = 1, slabs as columns)
 constexpr int kMfmaMinRInterpTile = 3;   // sparse-tile interp
 constexpr int kMfmaMinRInterpDense = 6;  // dense interp
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;

@@ -265,7 +265,12 @@ __global__ __launch_bounds__(kBlock, NO == 2 ? 5 : 1) void k_interp_mfma(const W
 }
 
 // ---------------------------------------------------------------------------
-template <int W>
+//
+// Z1 (one RHS): the 2m + 1 z-slabs take the N dimension instead of the RHS,
+// D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
+// B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block, and the
+// flush writes RHS column 0 of the same scratch layout.
+template <int W, bool Z1>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
                                                         IoArgs io, int R, float *__restrict__ scratch)
 {
@@ -360,24 +365,40 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     };
 
     // wave `wave` owns slabs wave + 4 s of the first 2m and, for two-cell
-    // items, the M tiles wave + 4 j of slab 2m
-    f4 acc[SPW][MT], accx[XT];
+    // items, the M tiles wave + 4 j of slab 2m (Z1: the M tiles wave + 4 j of
+    // every slab, accz)
+    constexpr int JT = (MT + 3) / 4;
+    f4 acc[Z1 ? 1 : SPW][Z1 ? 1 : MT], accx[XT], accz[JT];
 #pragma unroll
-    for (int s = 0; s < SPW; ++s)
+    for (int s = 0; s < (Z1 ? 1 : SPW); ++s)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < (Z1 ? 1 : MT); ++mt)
             acc[s][mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < XT; ++j)
         accx[j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < JT; ++j)
+        accz[j] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // Z1 forms the x-y products of its few matrix ops on the fly (no products
+    // phase): lane mrow's tap of M tile wave + 4 j is (x, y) = (zx[j], zy[j] - W)
+    int zx[JT], zy[JT];
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+        const int c = min((wave + 4 * j) * 16 + mrow, WW - 1);
+        zx[j] = c % W;
+        zy[j] = W + c / W;
+    }
     load(0);
     store_raw(rd[0], 0);
     if (PB < it.count)
         load(PB);  // the registers run one round ahead of the window values
     __syncthreads();
-    products(rd[0]);
-    __syncthreads();
+    if constexpr (!Z1) {
+        products(rd[0]);
+        __syncthreads();
+    }
     int buf = 0;
     for (int p0 = 0; p0 < it.count; p0 += PB) {
         const bool more = p0 + PB < it.count;
@@ -390,6 +411,21 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 load(p0 + 2 * PB);
         }
         Round &cr = rd[buf];
+        if constexpr (Z1) {
+#pragma unroll
+            for (int ks = 0; ks < PB / 4; ++ks) {
+                const int pk = 4 * ks + q;
+                // B[point][slab mrow] = v wz(slab); zero past the item's 2m + 1 slabs
+                const float b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][2 * W + min(mrow, W)] : 0.f;
+#pragma unroll
+                for (int j = 0; j < JT; ++j) {
+                    const int mt = wave + 4 * j;
+                    if (mt < MT)
+                        accz[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pw[pk][zx[j]] * cr.pw[pk][zy[j]], b,
+                                                                         accz[j], 0, 0, 0);
+                }
+            }
+        } else {
         // Operands of one K step (four points): A = x-y weight products of the
         // M tiles, and the B factors (RHS value, z weights of the wave's slabs).
         // The next step's operands are read from LDS before this step's
@@ -432,7 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int j = 0; j < XT; ++j)
                 accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.ax[j], bx, accx[j], 0, 0, 0);
         }
-        if (more) {
+        }
+        if (!Z1 && more) {
             __syncthreads();
             products(rd[buf ^ 1]);
         }
@@ -445,6 +482,18 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // slab (or M tile of slab 2m) through a per-wave LDS transpose
     float *fl = (float *)lds + wave * FL;
     float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
+    if constexpr (Z1) {
+        // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow: RHS column 0
+#pragma unroll
+        for (int j = 0; j < JT; ++j) {
+            const int mt = wave + 4 * j;
+            if (mt < MT && mrow < NS)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    dst[((int64_t)mrow * WW + mt * 16 + 4 * q + i) * 16] = accz[j][i];
+        }
+        return;
+    }
     auto wsync = []() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -762,10 +811,15 @@ bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
         return false;
     float *scratch = (float *)E.scratch[wi];
     dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16);
-    if (wi == 0)
-        hipLaunchKernelGGL(k_spread_mfma<8>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R, scratch);
+    const Chunk *items = E.d_dense_sp[3][wi];
+    if (wi == 0 && R == 1)
+        hipLaunchKernelGGL((k_spread_mfma<8, true>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+    else if (wi == 0)
+        hipLaunchKernelGGL((k_spread_mfma<8, false>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+    else if (R == 1)
+        hipLaunchKernelGGL((k_spread_mfma<12, true>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
     else
-        hipLaunchKernelGGL(k_spread_mfma<12>, grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[3][wi], io, R, scratch);
+        hipLaunchKernelGGL((k_spread_mfma<12, false>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
     return true;
 }
 

@@ -150,11 +150,11 @@ def test_dense_cell_kernels_match_tile_kernels(A, prec, tol):
 
 
 @pytest.mark.parametrize("m", [4, 6])
-@pytest.mark.parametrize("R", [8, 16, 21])
+@pytest.mark.parametrize("R", [1, 3, 8, 16, 21])
 def test_matrix_core_kernels_match_vector_kernels(A, m, R):
     """FP32 dense-cell kernels on the matrix cores agree with the vector-ALU ones,
     the tile kernels and the oracle (RHS counts that fill, underfill and spill a
-    16-wide block)."""
+    16-wide block; one RHS takes the spread with the z-slabs as columns)."""
     rng = np.random.default_rng(111)
     X = np.concatenate([rng.normal(0, 0.02, size=(30000, 3)), rng.uniform(-0.25, 0.25, size=(700, 3))])
     V = rng.standard_normal((X.shape[0], R))
