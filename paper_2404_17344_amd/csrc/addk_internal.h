@@ -44,7 +44,7 @@ constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item
 // workload (1e6 points, five d = 3 windows, K and dK/dl outputs).
 constexpr int kMfmaMinRSpread = 3;       // dense spread (and R = 1, slabs as columns)
 constexpr int kMfmaMinRInterpTile = 3;   // sparse-tile interp
-constexpr int kMfmaMinRInterpDense = 6;  // dense interp
+constexpr int kMfmaMinRInterpDense = 6;  // dense interp (and R = 1, slabs as columns)
 constexpr uint32_t kFlagNoDense = ADDK_TILE_KERNELS_ONLY;
 
 // Per-window descriptor read by every stage kernel (device copy per engine).

@@ -1615,8 +1615,8 @@ bool use_mfma(const Engine &E, uint32_t knob, int R)
     const int rmin = knob == ADDK_KNOB_SPREAD_MFMA       ? kMfmaMinRSpread
                      : knob == ADDK_KNOB_INTERP_TILE_MFMA ? kMfmaMinRInterpTile
                                                           : kMfmaMinRInterpDense;
-    // one RHS: the spread's variant with the z-slabs as columns
-    return E.tuned || R >= rmin || (knob == ADDK_KNOB_SPREAD_MFMA && R == 1);
+    // one RHS: the dense variants with the z-slabs as columns
+    return E.tuned || R >= rmin || (knob != ADDK_KNOB_INTERP_TILE_MFMA && R == 1);
 }
 
 addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io, hipStream_t st)

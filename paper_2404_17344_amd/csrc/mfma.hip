@@ -236,6 +236,128 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
 }
 
 // ---------------------------------------------------------------------------
+// Dense interp with one RHS: the item's 2m + 1 z-slabs take the 16 columns.
+// T[point][slab] = sum over the slab's taps A[point][tap] H[tap][slab] is one
+// matrix product over the (2m)^2 x-y taps (K steps of four taps, lane q taking
+// tap 4 t + q as in the slab kernel), then Y[point] = sum_slab wz T, a sum over
+// the 16 lanes of a row.  The item's block of RHS 0 is staged in LDS once,
+// [o][slab][tap] with the row padded by one word; slabs past the item's are
+// zero.
+template <int W, int NO, int NG>
+__device__ __forceinline__ void interp_dense_item_z1(const WinDev &w, const Chunk &it, const float *hl, float *wy_lds)
+{
+    constexpr int WW = W * W, NT = W / 4, HS = WW + 1;
+    int bx, by, bz, nzc;
+    unpack_cell_m(it.tile, bx, by, bz, nzc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, mrow = lane & 15;
+    const float *coords = (const float *)w.coords;
+    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    float *wyl = wy_lds + wave * (4 * W * 16);
+    float wxq[NG][NT];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int p = (wave + 4 * g) * 16 + mrow;
+        const bool act = p < it.count;
+        const int j = it.start + (act ? p : 0);
+        const float ux = coords[j], uy = coords[w.N + j];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            wxq[g][t] = act ? kb_psi_f(ux - (float)(bx + 4 * t + q), mm, kb, ie) : 0.f;
+            wyl[(g * W + 4 * t + q) * 16 + mrow] = kb_psi_f(uy - (float)(by + 4 * t + q), mm, kb, ie);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f4 acc[NO][NG];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
+    // K step (oy, t): taps oy W + 4 t + q; B[tap][slab mrow] = hl[o][mrow][tap]
+#pragma unroll
+    for (int oy = 0; oy < W; ++oy) {
+        float wy[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            wy[g] = wyl[(g * W + oy) * 16 + mrow];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float b[NO];
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+                b[o] = hl[(o * 16 + mrow) * HS + oy * W + 4 * t + q];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const float a = wy[g] * wxq[g][t];
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    acc[o][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[o], acc[o][g], 0, 0, 0);
+            }
+        }
+    }
+    // lane (q, mrow) holds T[point 4 q + i][slab mrow]: weight by the point's z
+    // window at that slab, then sum the slabs over the 16 lanes of the row
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = (wave + 4 * g) * 16 + 4 * q + i;
+            const bool act = p < it.count;
+            const float uz = coords[2 * w.N + it.start + (act ? p : 0)];
+            const int dz = (int)floorf(uz) - w.m + 1 - bz;  // the point's first slab in the item
+            const bool in = act && (unsigned)(mrow - dz) < (unsigned)W;
+            const float wz = in ? kb_psi_f(uz - (float)(bz + mrow), mm, kb, ie) : 0.f;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                float v = wz * acc[o][g][i];
+#pragma unroll
+                for (int s = 8; s > 0; s >>= 1)
+                    v += __shfl_xor(v, s, 16);
+                if (act && mrow == 0)
+                    w.Yw[((int64_t)o * w.N + w.perm[it.start + p]) * w.Rcap] = (double)v;
+            }
+        }
+    }
+}
+
+template <int W, int NO>
+__global__ __launch_bounds__(kBlock) void k_interp_mfma_z1(const WinDev *__restrict__ wins,
+                                                           const Chunk *__restrict__ items)
+{
+    constexpr int WW = W * W, HS = WW + 1;
+    __shared__ __align__(16) float hl[NO * 16 * HS];
+    __shared__ __align__(16) float wy_lds[4 * 4 * W * 16];
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    int bx, by, bz, nzc;
+    unpack_cell_m(it.tile, bx, by, bz, nzc);
+    const int NS = W + nzc - 1;
+    // stage RHS 0 (the real part of pair 0) of the item's block, zero outside
+    // the grid box and past the item's slabs
+    const float *H = (const float *)w.H;
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    for (int e = threadIdx.x; e < NO * 16 * WW; e += kBlock) {
+        const int o = e / (16 * WW), rem = e - o * (16 * WW), oz = rem / WW, tap = rem - oz * WW;
+        const int gx = bx + tap % W, gy = by + tap / W, gz = bz + oz;
+        float v = 0.f;
+        if (oz < NS && gx < ex && gy < ey && gz < ez)
+            v = H[((int64_t)o * w.npair_cap * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2];
+        hl[(o * 16 + oz) * HS + tap] = v;
+    }
+    __syncthreads();
+    const int ng = (((it.count + 15) >> 4) + 3) >> 2;
+    switch (ng) {
+    case 1: interp_dense_item_z1<W, NO, 1>(w, it, hl, wy_lds); break;
+    case 2: interp_dense_item_z1<W, NO, 2>(w, it, hl, wy_lds); break;
+    case 3: interp_dense_item_z1<W, NO, 3>(w, it, hl, wy_lds); break;
+    default: interp_dense_item_z1<W, NO, 4>(w, it, hl, wy_lds); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dense interp: one block per dense item (<= 256 points) and 16 RHS, NO
 // outputs at once.  The number of groups per wave is uniform in the block, so
 // the dispatch below is a uniform branch and every wave runs the same slab
@@ -794,6 +916,17 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
         return false;
     dim3 grid(E.ndense[3][wi], (R + 15) / 16);
     const Chunk *items = E.d_dense[3][wi];
+    if (R == 1) {  // the z-slabs as columns
+        if (wi == 0 && nout == 1)
+            hipLaunchKernelGGL((k_interp_mfma_z1<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items);
+        else if (wi == 0)
+            hipLaunchKernelGGL((k_interp_mfma_z1<8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items);
+        else if (nout == 1)
+            hipLaunchKernelGGL((k_interp_mfma_z1<12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items);
+        else
+            hipLaunchKernelGGL((k_interp_mfma_z1<12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items);
+        return true;
+    }
     if (wi == 0 && nout == 1)
         hipLaunchKernelGGL((k_interp_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     else if (wi == 0)
