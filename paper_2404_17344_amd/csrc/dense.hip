@@ -78,14 +78,15 @@ constexpr int dense_block_cells()
 // is added to the grid with atomics, or (d = 3, scratch given) stored into the
 // item's scratch slots for k_gather_blocks: slot item * nrb + r / 16 holds
 // [oz][oy][ox][r % 16] over the 2m + 1 slabs, the layout of the matrix-core
-// spread (the atomics are executed beyond L2 on this chip and are slow).
+// spread, with rows of 16 RHS (one when R = 1: rw) (the atomics are executed
+// beyond L2 on this chip and are slow).
 // Blocks hold at most 4 RHS groups of OUT threads (see spread_dense_w): the
 // bound lets d = 3 keep its (2m + 1) x RT accumulators in registers.
 template <typename real, int D, int W, int RT>
 __global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const WinDev *__restrict__ wins,
                                                                            const Chunk *__restrict__ items, IoArgs io,
                                                                            int R, int NRG, real *__restrict__ scratch,
-                                                                           int nrb)
+                                                                           int nrb, int rw)
 {
     constexpr int OUT = D == 3 ? W * W : W;  // taps owned by thread groups
     constexpr int IN = D == 1 ? 1 : W;       // taps accumulated per thread (last dimension)
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const
             const int r = r0 + rg * RT + i;
             if (D == 3 && scratch != nullptr) {
                 if (r < R)
-                    scratch[(((int64_t)blockIdx.x * nrb + (r >> 4)) * ((W + 1) * W * W) + (k * W + oy) * W + ox) * 16 +
+                    scratch[(((int64_t)blockIdx.x * nrb + (r >> 4)) * ((W + 1) * W * W) + (k * W + oy) * W + ox) * rw +
                             (r & 15)] = acc[k][i];
             } else if (r < R)
                 gadd(&G[((int64_t)(r >> 1) * w.szG + cell) * 2 + (r & 1)], acc[k][i]);
@@ -338,7 +339,7 @@ static void spread_dense_w(Engine &E, int R, IoArgs io, hipStream_t st)
     if (R == 1) {
         dim3 grid(nitems, R);
         hipLaunchKernelGGL((k_spread_dense<real, D, W, 1>), grid, dim3(OUT), 0, st, E.d_wins, items, io, R, 1, scratch,
-                           nrb);
+                           nrb, 1);
         return;
     }
     // d = 3: two RHS per thread in FP32 and one in FP64, so that the (2m + 1) x RT
@@ -347,7 +348,7 @@ static void spread_dense_w(Engine &E, int R, IoArgs io, hipStream_t st)
     const int nrg = std::min(4, (R + RT - 1) / RT);
     dim3 grid(nitems, (R + RT * nrg - 1) / (RT * nrg));
     hipLaunchKernelGGL((k_spread_dense<real, D, W, RT>), grid, dim3(OUT * nrg), 0, st, E.d_wins, items, io, R, nrg,
-                       scratch, nrb);
+                       scratch, nrb, 16);
 }
 
 template <typename real, int D, int W, int RB>

@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kBlock, NO == 2 ? 5 : 1) void k_interp_mfma(const W
 // Z1 (one RHS): the 2m + 1 z-slabs take the N dimension instead of the RHS,
 // D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
 // B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block, and the
-// flush writes RHS column 0 of the same scratch layout.
+// flush writes the block with one value per tap (the gather's one-RHS layout).
 template <int W, bool Z1>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
                                                         IoArgs io, int R, float *__restrict__ scratch)
@@ -603,19 +603,18 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // stores; the blocks of all items are summed by k_gather_blocks), each
     // slab (or M tile of slab 2m) through a per-wave LDS transpose
     float *fl = (float *)lds + wave * FL;
-    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
     if constexpr (Z1) {
-        // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow: RHS column 0
+        // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow; one RHS per tap
+        float *dz = scratch + (int64_t)blockIdx.x * ((W + 1) * WW);
 #pragma unroll
         for (int j = 0; j < JT; ++j) {
             const int mt = wave + 4 * j;
             if (mt < MT && mrow < NS)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    dst[((int64_t)mrow * WW + mt * 16 + 4 * q + i) * 16] = accz[j][i];
+                *(f4 *)(dz + mrow * WW + mt * 16 + 4 * q) = accz[j];
         }
         return;
     }
+    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
     auto wsync = []() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -805,6 +804,91 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     }
 }
 
+// One RHS: the same sum over blocks with one value per tap (the one-RHS
+// scratch layout), into the real part of pair 0.
+template <int W, typename real>
+__global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__restrict__ wins,
+                                                            const LineGroup *__restrict__ tiles,
+                                                            const real *__restrict__ scratch)
+{
+    constexpr int WW = W * W, CB = 8;
+    __shared__ real red[3][64];
+    __shared__ int2 cand[(W + 3) * (W + 3) * (W + 4)];
+    const LineGroup tg = tiles[blockIdx.x];
+    const WinDev &w = wins[tg.win];
+    const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
+    const int nt0 = (ex + 3) / 4, nt1 = (ey + 3) / 4;
+    const int tx = tg.grp % nt0, ty = (tg.grp / nt0) % nt1, tz = tg.grp / (nt0 * nt1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gx = tx * 4 + (lane & 3), gy = ty * 4 + ((lane >> 2) & 3), gz = tz * 4 + (lane >> 4);
+    const int nb0 = w.nbase[0], nb1 = w.nbase[1], nb2 = w.nbase[2];
+    const int2 *map = w.dmap;
+    real acc = real(0);
+    const int z0 = max(0, tz * 4 - W), z1 = min(nb2 - 1, tz * 4 + 3);
+    const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
+    const int x0 = max(0, tx * 4 - (W - 1)), x1 = min(nb0 - 1, tx * 4 + 3);
+    const bool any = x1 >= x0 && y1 >= y0 && z1 >= z0;
+    const int nx = any ? x1 - x0 + 1 : 0, ny = any ? y1 - y0 + 1 : 0, nz = any ? z1 - z0 + 1 : 0;
+    for (int idx = threadIdx.x; idx < nx * ny * nz; idx += kBlock) {
+        const int dx = idx % nx, dy = (idx / nx) % ny, dz = idx / (nx * ny);
+        cand[idx] = map[((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx];
+    }
+    __syncthreads();
+    for (int dz = wave; dz < nz; dz += 4) {
+        const int bz = z0 + dz, oz = gz - bz;
+        for (int dy = 0; dy < ny; ++dy) {
+            const int by = y0 + dy, oy = gy - by;
+            const int2 *crow = cand + (dz * ny + dy) * nx;
+            uint64_t live = __ballot(lane < nx && crow[lane < nx ? lane : 0].y != 0);
+            while (live) {
+                int2 its[CB];
+                bool in[CB];
+                const real *src[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const int dx = live ? __builtin_ctzll(live) : 0;
+                    const bool valid = live != 0;
+                    live &= live - 1;
+                    its[k] = valid ? crow[dx] : int2{0, 0};
+                    const int nzc = (its[k].y >> 16) + 1;
+                    const int ox = gx - x0 - dx;
+                    in[k] = valid && (unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
+                            (unsigned)oz < (unsigned)(W + nzc - 1);
+                    const int tap = in[k] ? (oz * W + oy) * W + ox : 0;
+                    src[k] = scratch + (int64_t)its[k].x * ((W + 1) * WW) + tap;
+                }
+                real v[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k)
+                    v[k] = in[k] ? *src[k] : real(0);
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    acc += v[k];
+                    const int cnt = its[k].y & 0xffff;  // further items of the cell (rare)
+                    for (int i = 1; i < cnt; ++i) {
+                        if (!in[k])
+                            break;
+                        acc += src[k][(int64_t)i * ((W + 1) * WW)];
+                    }
+                }
+            }
+        }
+    }
+    if (wave > 0)
+        red[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave > 0)
+        return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        acc += red[k][lane];
+    if (gx >= ex || gy >= ey || gz >= ez)
+        return;
+    real *G = (real *)w.G;
+    const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
+    G[c * 2] += acc;
+}
+
 // ---------------------------------------------------------------------------
 // interp for the sparsely populated cells of one tile on the matrix cores: the
 // tile's sub-grid (tile + window halo, x padded to 16) plays the role of the
@@ -964,6 +1048,18 @@ void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st)
     const float *sf = (const float *)E.scratch[wi];
     const double *sd = (const double *)E.scratch[wi];
     const bool fp64 = E.precision == ADDK_FP64;
+    if (R == 1) {  // one value per tap
+        if (wi == 0 && !fp64)
+            hipLaunchKernelGGL((k_gather_blocks_1<8, float>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sf);
+        else if (wi == 0)
+            hipLaunchKernelGGL((k_gather_blocks_1<8, double>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sd);
+        else if (!fp64)
+            hipLaunchKernelGGL((k_gather_blocks_1<12, float>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sf);
+        else
+            hipLaunchKernelGGL((k_gather_blocks_1<12, double>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi],
+                               sd);
+        return;
+    }
     if (wi == 0 && !fp64)
         hipLaunchKernelGGL((k_gather_blocks<8, float>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_gtiles[wi], sf, R);
     else if (wi == 0)
