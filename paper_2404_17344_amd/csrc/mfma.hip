@@ -387,7 +387,9 @@ __global__ __launch_bounds__(kBlock, NO == 2 ? 5 : 1) void k_interp_mfma(const W
 }
 
 // ---------------------------------------------------------------------------
-//
+// Dense spread: one block per spread item (one or two dense cells) and 16 RHS;
+// the item's (2m)^2 x (2m + 1) block is written to its scratch slot and summed
+// into the grid by k_gather_blocks.
 // Z1 (one RHS): the 2m + 1 z-slabs take the N dimension instead of the RHS,
 // D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
 // B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block, and the
