@@ -108,7 +108,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested; run with --gpus 1)" % args.gpus, flush=True)
         sys.exit(0)
 
