@@ -659,6 +659,46 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
 // ---------------------------------------------------------------------------
 // FP64 window sum, derivative scalings, caller order
 
+// Few RHS (R <= kCombineRowsMaxR): one thread per output row and all its RHS.
+// A wave's reads of the point-major window products cover one contiguous run
+// and its writes of each caller column are contiguous, so no LDS transpose is
+// needed; the 16-RHS tiles of k_combine would leave most lanes idle here.
+constexpr int kCombineRowsMaxR = 4;
+
+__global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
+{
+    const ProbDev p = get_prob(io, blockIdx.y);
+    const int nwin = p.wend - p.wbeg;
+    const bool want_y = (mode & 1) && p.Y, want_ds = (mode & 2) && p.dYs, want_dl = (mode & 4) && p.dYl;
+    for (int64_t i = p.yoff + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < p.N; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t iy = i - p.yoff;  // output row
+        double y[kCombineRowsMaxR] = {};
+        for (int k = 0; k < nwin; ++k) {
+            const WinDev &w = wins[p.wbeg + k];
+            const double *src = w.Yw + i * w.Rcap;
+            const double *dsrc = w.Yw + ((int64_t)w.N + i) * w.Rcap;
+            const int64_t blk = (int64_t)k * p.ldy * R;  // window k's block of dY/dl, dY/dsigma
+#pragma unroll
+            for (int r = 0; r < kCombineRowsMaxR; ++r) {
+                if (r >= R)
+                    break;
+                const double v = src[r];
+                const int64_t at = blk + iy + (int64_t)r * p.ldy;
+                y[r] += w.sig2 * v;
+                if (want_ds)
+                    p.dYs[at] = w.dsig * v;
+                if (want_dl)
+                    p.dYl[at] = w.der_scale * dsrc[r];
+            }
+        }
+        if (want_y)
+#pragma unroll
+            for (int r = 0; r < kCombineRowsMaxR; ++r)
+                if (r < R)
+                    p.Y[iy + (int64_t)r * p.ldy] = y[r];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
 {
     // Tiles of 64 points x 16 RHS: the window products (point-major) are read
@@ -1646,10 +1686,15 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
         maxN = io.single.N - io.single.yoff;
     if (maxN <= 0 || R == 0)
         return ADDK_OK;
-    const int bx = (int)std::min<int64_t>((maxN + 63) / 64, 16384);
     const int ny = io.table ? E.nprob : 1;
     StageTimer t(E, PS_COMBINE, st);
-    hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+    if (R <= kCombineRowsMaxR) {
+        const int bx1 = (int)std::min<int64_t>((maxN + kBlock - 1) / kBlock, 16384);
+        hipLaunchKernelGGL(k_combine_rows, dim3(bx1, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+    } else {
+        const int bx = (int)std::min<int64_t>((maxN + 63) / 64, 16384);
+        hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return hip_fail(e, "combine launch");

@@ -43,10 +43,12 @@ def cuda(a):
 MIXED = [[0, 1, 2], [3, 4], [5]]
 
 
+@pytest.mark.parametrize("R", [1, 3, 4, 5])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
-def test_dmatvec_gaussian_vs_direct(A, prec, tol):
-    p = WL.small_problem(800, 6, MIXED, seed=201, R=3, n=32, m=6)
-    _say("dmatvec gaussian %s" % prec)
+def test_dmatvec_gaussian_vs_direct(A, prec, tol, R):
+    """R <= 4 combines row by row, R = 5 through the 16-RHS tiles."""
+    p = WL.small_problem(800, 6, MIXED, seed=201, R=R, n=32, m=6)
+    _say("dmatvec gaussian %s R=%d" % (prec, R))
     Y, dl, ds = make_plan(A, p, prec).dmatvec(cuda(p.V))
     Yo, dlo, dso = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, want_derivs=True)
     assert relerr(Y.cpu().numpy(), Yo) < tol
