@@ -115,6 +115,25 @@ def test_c2_full_size_sampled_rows(A, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-10)])
+def test_c5_full_size_dmatvec_sampled_rows(A, prec, tol):
+    """The large workload in the timed launch configuration (N = 1e6, 5 windows
+    d = 3, R = 16 column-major, n = 64, m = 6): K V and dK/dl_w V on sampled
+    rows against the direct sums."""
+    p = WL.large_c5()
+    _say("c5 full size %s" % prec)
+    V = torch.from_numpy(np.ascontiguousarray(p.V.T)).cuda().t()
+    plan = make_plan(A, p, prec)
+    Y, dl, _ = plan.dmatvec(V, want_y=True, want_dell=True, want_dsigma=False)
+    Y, dl = Y.cpu().numpy(), dl.cpu().numpy()
+    plan.close()
+    rows = np.random.default_rng(11).choice(p.N, 96, replace=False)
+    Yo, dlo, _ = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=rows, want_derivs=True)
+    errs = [relerr(Y[rows], Yo)] + [relerr(dl[w][rows], dlo[w]) for w in range(p.P)]
+    print("c5 %s rel errs %s" % (prec, " ".join("%.2e" % e for e in errs)))
+    assert max(errs) < tol
+
+
 def test_many_rhs_and_ragged_blocks(A):
     """R = 19 spans several RHS blocks and an odd last complex grid."""
     p = WL.small_problem(900, 6, MIXED, seed=104, R=19, n=32, m=6)
