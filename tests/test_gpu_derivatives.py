@@ -184,12 +184,15 @@ def _batch_problems(seed=301, count=6):
     return probs
 
 
+@pytest.mark.parametrize("R", [1, 4])
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-6)])
-def test_batch_graph_matches_plans_and_oracle(A, prec, tol):
+def test_batch_graph_matches_plans_and_oracle(A, prec, tol, R):
     probs = _batch_problems()
-    _say("batch %s" % prec)
+    for p in probs:
+        p.V = np.ascontiguousarray(p.V[:, :R])
+    _say("batch %s R=%d" % (prec, R))
     plans = [make_plan(A, p, prec) for p in probs]
-    B = A.Batch(plans, R=4)
+    B = A.Batch(plans, R=R)
     B.set_inputs([cuda(p.V) for p in probs])
     B.launch()
     torch.cuda.synchronize()
