@@ -20,6 +20,10 @@
  *              (derivative from the "Implementing the NFFT approach" section)
  *   Matern-1/2 kappa(r) = exp(-r / l),          d kappa/d l = r / l^2 * kappa
  *              (section "Extension to other kernels")
+ *   Matern-3/2 kappa(r) = (1 + a r) exp(-a r),  a = sqrt(3) / l,
+ *              d kappa/d l = 3 r^2 / l^3 * exp(-a r)
+ *              (the further kernel that section names; the standard
+ *              Matern form with smoothness 3/2, differentiated in l)
  *
  *   Y[i, r]          = sum_w sigma_w^2 sum_j kappa_w(i, j) V[j, r]
  *   dY_dl[w][i, r]   = sigma_w^2 sum_j d kappa_w(i, j)/d l_w V[j, r]
@@ -43,7 +47,7 @@
 #define ORACLE_BLOCK 256
 #define ORACLE_MAXD 8
 
-enum { ORACLE_GAUSSIAN = 1, ORACLE_MATERN12 = 3 };
+enum { ORACLE_GAUSSIAN = 1, ORACLE_MATERN12 = 3, ORACLE_MATERN32 = 5 };
 
 typedef struct {
     double s;
@@ -67,11 +71,16 @@ static inline void kernel_eval(int kernel, double r2, double ell, double *k, dou
         double e = exp(-r2 / (2.0 * ell * ell));
         *k = e;
         *dk = r2 / (ell * ell * ell) * e;
-    } else {
+    } else if (kernel == ORACLE_MATERN12) {
         double r = sqrt(r2);
         double e = exp(-r / ell);
         *k = e;
         *dk = r / (ell * ell) * e;
+    } else {
+        double ar = sqrt(3.0 * r2) / ell;
+        double e = exp(-ar);
+        *k = (1.0 + ar) * e;
+        *dk = ar * ar / ell * e;
     }
 }
 
@@ -90,7 +99,7 @@ int oracle_direct(int64_t N, int32_t D, const double *X, int64_t ldx,
 {
     if (N < 0 || D <= 0 || P <= 0 || R <= 0 || nrows < 0 || ldx < D || ldv < N || ldy < nrows)
         return -1;
-    if (kernel != ORACLE_GAUSSIAN && kernel != ORACLE_MATERN12)
+    if (kernel != ORACLE_GAUSSIAN && kernel != ORACLE_MATERN12 && kernel != ORACLE_MATERN32)
         return -2;
     for (int32_t w = 0; w < P; ++w) {
         int32_t dw = win_off[w + 1] - win_off[w];

@@ -2,7 +2,8 @@
 
 The C source follows the kernel definitions of eq. (3) and eqs. (7)-(8), the l- and
 sigma-derivatives of the section "Implementing the NFFT approach" (Gaussian)
-and of "Extension to other kernels" (Matern-1/2).
+and of "Extension to other kernels" (Matern-1/2, and the Matern-3/2 kernel that
+section names as a further kernel).
 """
 from __future__ import annotations
 

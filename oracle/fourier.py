@@ -10,7 +10,10 @@ Every function follows a passage of the paper:
   eq. (ghat) and the tensor split of the "Derivative Gaussian kernel"
   subsection.  The Matern-1/2 kernel of "Extension to other kernels" has no
   transform in the paper; the textbook transform of exp(-|x|/l) in R^d is
-  used (a reading, listed in the design notes).
+  used (a reading, listed in the design notes).  The same holds for the
+  Matern-3/2 kernel (1 + sqrt3 r/l) e^{-sqrt3 r/l}, which that subsection names
+  as a further kernel: its transform is the Matern spectral density with
+  smoothness 3/2.
 * Periodised Fourier coefficients on a torus of period T:
   - ``coeffs_sampled``: discrete coefficients from n^d equidistant kernel
     samples of the simple periodic continuation (Lemma 1, "Fourier theory"
@@ -40,16 +43,21 @@ from scipy.special import erfc as _erfc, wofz as _wofz
 
 GAUSSIAN = 1
 MATERN12 = 3
+MATERN32 = 5
 
 # ----------------------------------------------------------------------------
 # kernels and their continuous Fourier transforms
 
 
 def kernel_value(kernel: int, r2, ell: float):
-    """kappa(r): Gaussian exp(-r^2/(2l^2)) (eq. (3)); Matern-1/2 exp(-r/l)."""
+    """kappa(r): Gaussian exp(-r^2/(2l^2)) (eq. (3)); Matern-1/2 exp(-r/l);
+    Matern-3/2 (1 + a r) exp(-a r) with a = sqrt(3)/l."""
     r2 = np.asarray(r2, dtype=np.float64)
     if kernel == GAUSSIAN:
         return np.exp(-r2 / (2.0 * ell * ell))
+    if kernel == MATERN32:
+        ar = np.sqrt(3.0 * r2) / ell
+        return (1.0 + ar) * np.exp(-ar)
     return np.exp(-np.sqrt(r2) / ell)
 
 
@@ -58,21 +66,27 @@ def kernel_der_value(kernel: int, r2, ell: float):
 
     Gaussian (eq. (implement_der_gaussian_kernel)): r^2/(2 l^2) exp(-r^2/(2 l^2)),
     so that dK/dl = (2/l) K_der.  Matern-1/2 ("der_laplacian_rbf"): (r/l) exp(-r/l),
-    so that dK/dl = (1/l) K_der.
+    so that dK/dl = (1/l) K_der.  Matern-3/2, by the same convention
+    (K_der = l dK/dl): (a r)^2 exp(-a r) = 3 (r/l)^2 exp(-a r).
     """
     r2 = np.asarray(r2, dtype=np.float64)
     if kernel == GAUSSIAN:
         return r2 / (2.0 * ell * ell) * np.exp(-r2 / (2.0 * ell * ell))
+    if kernel == MATERN32:
+        ar = np.sqrt(3.0 * r2) / ell
+        return ar * ar * np.exp(-ar)
     r = np.sqrt(r2)
     return r / ell * np.exp(-r / ell)
 
 
 def der_scale(kernel: int, ell: float) -> float:
-    """dK_w/dl_w = der_scale * K_der_w (Gaussian 2/l, Matern-1/2 1/l)."""
+    """dK_w/dl_w = der_scale * K_der_w (Gaussian 2/l, Matern 1/l)."""
     return 2.0 / ell if kernel == GAUSSIAN else 1.0 / ell
 
 
 _MATERN_CD = {1: 2.0, 2: 2.0 * math.pi, 3: 8.0 * math.pi}
+# Matern-3/2: int_{R^d} (1 + a|x|) e^{-a|x|} dx = c_d l^d with a = sqrt(3)/l
+_MATERN32_CD = {1: 4.0 / math.sqrt(3.0), 2: 2.0 * math.pi, 3: 32.0 * math.pi / 3.0 ** 1.5}
 
 
 def kernel_ft(kernel: int, xi2, ell: float, d: int):
@@ -81,6 +95,8 @@ def kernel_ft(kernel: int, xi2, ell: float, d: int):
     if kernel == GAUSSIAN:
         return (ell * math.sqrt(2.0 * math.pi)) ** d * np.exp(-2.0 * math.pi ** 2 * ell * ell * xi2)
     u = 4.0 * math.pi ** 2 * ell * ell * xi2
+    if kernel == MATERN32:
+        return _MATERN32_CD[d] * ell ** d / (1.0 + u / 3.0) ** ((d + 3) / 2.0)
     return _MATERN_CD[d] * ell ** d / (1.0 + u) ** ((d + 1) / 2.0)
 
 
@@ -90,13 +106,16 @@ def kernel_der_ft(kernel: int, xi2, ell: float, d: int):
     Gaussian: (d/2 - 2 pi^2 l^2 |xi|^2) times the Gaussian's transform
     (eq. (ghat) per coordinate, summed over the tensor split).
     Matern-1/2: l * d/dl of the transform = (d - (d+1) u/(1+u)) times it,
-    u = 4 pi^2 l^2 |xi|^2.
+    u = 4 pi^2 l^2 |xi|^2.  Matern-3/2: l * d/dl of its transform =
+    (d - (d+3) (u/3)/(1 + u/3)) times it.
     """
     xi2 = np.asarray(xi2, dtype=np.float64)
     base = kernel_ft(kernel, xi2, ell, d)
     if kernel == GAUSSIAN:
         return (d / 2.0 - 2.0 * math.pi ** 2 * ell * ell * xi2) * base
     u = 4.0 * math.pi ** 2 * ell * ell * xi2
+    if kernel == MATERN32:
+        return (d - (d + 3) * (u / 3.0) / (1.0 + u / 3.0)) * base
     return (d - (d + 1) * u / (1.0 + u)) * base
 
 
@@ -113,10 +132,14 @@ def torus_period_auto(kernel: int, L: float, ell: float, n: int) -> float:
     balanced, exp(-(T-L)^2/(2 l^2)) = exp(-2 pi^2 l^2 (n/2)^2 / T^2), giving
     T = (L + sqrt(L^2 + 4 pi l^2 n)) / 2.  For Matern-1/2 the image error
     exp(-(T-L)/l) is set to the algebraic truncation level ~ 1/n:
-    T = L + l ln n.
+    T = L + l ln n.  For Matern-3/2 (coefficients decaying like |k|^-(d+3),
+    truncation ~ n^-3) the image factor exp(-sqrt3 (T-L)/l) is set to n^-3:
+    T = L + sqrt3 l ln n.
     """
     if kernel == GAUSSIAN:
         return 0.5 * (L + math.sqrt(L * L + 4.0 * math.pi * ell * ell * n))
+    if kernel == MATERN32:
+        return L + math.sqrt(3.0) * ell * math.log(n)
     return L + ell * math.log(n)
 
 

@@ -16,7 +16,7 @@ from scipy import integrate, special
 from oracle import fourier as F
 from oracle.direct import oracle_direct, oracle_vjp
 
-G, M = F.GAUSSIAN, F.MATERN12
+G, M, M3 = F.GAUSSIAN, F.MATERN12, F.MATERN32
 
 
 def _pts(N, D, seed):
@@ -32,7 +32,7 @@ def _kmat(X, windows, kernel, ell, sigma):
 # ---------------------------------------------------------------- direct sums
 
 
-@pytest.mark.parametrize("kernel", [G, M])
+@pytest.mark.parametrize("kernel", [G, M, M3])
 def test_diagonal_is_sum_of_sigma_squared(kernel):
     X = _pts(40, 7, 1)
     wins = [[0, 1, 2], [3, 4], [5], [6, 0]]
@@ -41,7 +41,7 @@ def test_diagonal_is_sum_of_sigma_squared(kernel):
     np.testing.assert_allclose(np.diag(K), sum(s * s for s in sig), rtol=1e-15)
 
 
-@pytest.mark.parametrize("kernel", [G, M])
+@pytest.mark.parametrize("kernel", [G, M, M3])
 def test_symmetry_and_linearity(kernel):
     X = _pts(200, 6, 2)
     wins = [[0, 1, 2], [3, 4, 5]]
@@ -90,9 +90,9 @@ def test_two_point_special_values():
     assert Km[0, 1] == pytest.approx(math.exp(-5.0), rel=1e-14)
 
 
-@pytest.mark.parametrize("kernel", [G, M])
+@pytest.mark.parametrize("kernel", [G, M, M3])
 def test_rotation_invariance(kernel):
-    """Both kernels depend on the Euclidean distance only."""
+    """The kernels depend on the Euclidean distance only."""
     X = _pts(80, 3, 10)
     Q, _ = np.linalg.qr(np.random.default_rng(11).standard_normal((3, 3)))
     v = np.random.default_rng(12).standard_normal((80, 1))
@@ -113,7 +113,7 @@ def test_matern_1d_has_tridiagonal_inverse():
     assert np.max(np.abs(offg)) > 1e-3 * np.max(np.abs(Kgi))
 
 
-@pytest.mark.parametrize("kernel", [G, M])
+@pytest.mark.parametrize("kernel", [G, M, M3])
 def test_derivatives_match_central_differences(kernel):
     X = _pts(300, 6, 14)
     wins = [[0, 1, 2], [3, 4, 5]]
@@ -184,6 +184,65 @@ def test_rejects_bad_arguments():
         oracle_direct(X, [[0]], G, -0.1, 1.0, np.ones((10, 1)))
 
 
+def _matern_bessel(r, ell, nu):
+    """The Matern kernel of smoothness nu in its general form
+    2^(1-nu)/Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / l (SciPy's modified
+    Bessel function of the second kind), with the limit 1 at r = 0."""
+    r = np.asarray(r, dtype=np.float64)
+    z = math.sqrt(2.0 * nu) * r / ell
+    out = np.ones_like(z)
+    nz = z > 0
+    out[nz] = 2.0 ** (1.0 - nu) / special.gamma(nu) * z[nz] ** nu * special.kv(nu, z[nz])
+    return out
+
+
+def _explicit_matrix(Xw, kernel, ell):
+    """N x N kernel matrix of one window assembled with NumPy from pairwise distances."""
+    D = Xw[:, None, :] - Xw[None, :, :]
+    r = np.sqrt((D * D).sum(-1))
+    if kernel == G:
+        return np.exp(-r * r / (2.0 * ell * ell))
+    return _matern_bessel(r, ell, 0.5 if kernel == M else 1.5)
+
+
+@pytest.mark.parametrize("kernel", [G, M, M3])
+def test_direct_sums_equal_explicit_numpy_matrices(kernel):
+    """N = 48: the direct sums equal products with kernel matrices built
+    explicitly in NumPy (Matern kernels from the Bessel-function form of the
+    Matern family, smoothness 1/2 and 3/2); the l-derivative matrices are
+    Richardson-extrapolated central differences of those matrices."""
+    X = _pts(48, 6, 40)
+    wins = [[0, 1, 2], [3, 4], [5]]
+    ell, sig = np.array([0.09, 0.17, 0.3]), np.array([1.1, 0.6, 0.8])
+    V = np.random.default_rng(41).standard_normal((48, 3))
+    Y, dl, ds = oracle_direct(X, wins, kernel, ell, sig, V, want_derivs=True)
+    Ye = np.zeros_like(V)
+    for w, feats in enumerate(wins):
+        Kw = _explicit_matrix(X[:, feats], kernel, ell[w])
+        Ye += sig[w] ** 2 * Kw @ V
+        np.testing.assert_allclose(ds[w], 2.0 * sig[w] * Kw @ V, rtol=1e-12, atol=1e-13)
+        h = 1e-3 * ell[w]
+
+        def cd(step):
+            return (_explicit_matrix(X[:, feats], kernel, ell[w] + step)
+                    - _explicit_matrix(X[:, feats], kernel, ell[w] - step)) / (2 * step)
+        dK = (4.0 * cd(h / 2) - cd(h)) / 3.0
+        np.testing.assert_allclose(dl[w], sig[w] ** 2 * dK @ V, rtol=1e-8, atol=1e-9 * np.abs(dl[w]).max())
+    np.testing.assert_allclose(Y, Ye, rtol=1e-12, atol=1e-13)
+
+
+def test_matern32_two_point_values():
+    """(1 + sqrt3 r/l) e^{-sqrt3 r/l} at r = 0 (1) and at r = l / sqrt3 (2/e),
+    and its l-derivative vanishing at r = 0."""
+    ell = 0.2
+    X = np.array([[0.0, 0.0], [ell / math.sqrt(3.0), 0.0]])
+    v = np.array([[0.0], [1.0]])
+    y, dl, _ = oracle_direct(X, [[0, 1]], M3, ell, 1.0, v, want_derivs=True)
+    assert y[0, 0] == pytest.approx(2.0 / math.e, rel=1e-15)
+    assert y[1, 0] == pytest.approx(1.0, rel=1e-15)
+    assert dl[0, 1, 0] == 0.0
+
+
 # ---------------------------------------------------------------- Fourier side
 
 
@@ -215,7 +274,7 @@ def test_matern_ft_matches_quadrature(ell, xi):
     assert F.kernel_ft(M, xi * xi, ell, 2) == pytest.approx(v2, rel=1e-7)
 
 
-@pytest.mark.parametrize("kernel", [G, M])
+@pytest.mark.parametrize("kernel", [G, M, M3])
 @pytest.mark.parametrize("xi", [0.0, 2.5, 6.0])
 def test_derivative_kernel_ft_matches_quadrature(kernel, xi):
     ell = 0.08
