@@ -164,6 +164,26 @@ addk_status addk_matvec(addk_plan plan, int32_t R, const double *V, int64_t ldv,
                         double *Y, int64_t ldy, void *stream);
 
 /*
+ * addk_matvec for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, products and errors as addk_matvec, and the same stage
+ * kernels; the per-call workspace (grids, per-window FP64 products, the
+ * point-major RHS copy, the dense spread's per-item blocks, near-field
+ * close-pair sums) is taken from one fixed array of 256 MiB per GPU that the
+ * library holds from load until the process ends, instead of from buffers the
+ * plan allocates.  The call allocates nothing; it uploads the plan's window
+ * descriptors with a synchronous copy (so it synchronises the device first)
+ * and then queues the kernels on `stream`.  The plan's device must be the
+ * current device.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams or two threads) race; results of calls
+ * queued on one stream are independent.  Errors: as addk_matvec, and
+ * INVALID_ARG when the workspace for this plan and R exceeds 256 MiB (the
+ * message gives the size needed; call addk_matvec or split the RHS).
+ */
+addk_status addk_matvec_noalloc(addk_plan plan, int32_t R, const double *V, int64_t ldv,
+                                double *Y, int64_t ldy, void *stream);
+
+/*
  * Derivative products ("Implementing the NFFT approach", "Extension to other
  * kernels"): one spreading and forward FFT per window feed both the kernel's
  * and the derivative kernel's multipliers.

@@ -249,6 +249,17 @@ class Plan:
                                          max(self.N_out, 1), _stream(stream)), "addk_matvec")
         return Yc.t()
 
+    def matvec_noalloc(self, V, out, stream=None):
+        """K V into the caller's column-major (R, N) buffer ``out`` with no device
+        allocation: the workspace is the library's fixed per-GPU array."""
+        Vc = _colmajor(V)
+        R = Vc.shape[0]
+        if tuple(out.shape) != (R, self.N_out) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (R, N_out) float64 CUDA tensor")
+        _lib.check(self._lib.addk_matvec_noalloc(self._h, R, Vc.data_ptr(), max(self.N, 1), out.data_ptr(),
+                                                 max(self.N_out, 1), _stream(stream)), "addk_matvec_noalloc")
+        return out.t()
+
     def cg(self, Y, beta: float, tol: float = 1e-3, maxit: int = 500, X0=None, stream=None):
         """Solve (K + beta I) X = Y by conjugate gradients (eq. (9)); returns (X, iterations, relres)."""
         torch = _torch()

@@ -62,6 +62,7 @@ _SIGS = {
     "addk_plan_create": [ctypes.POINTER(_vp), _i64, _i32, _vp, _i64, _i32, _pi32, _pi32, _i32, _pd, _pd,
                          _i32, _i32, _d, _i32, _u32, _vp],
     "addk_matvec": [_vp, _i32, _vp, _i64, _vp, _i64, _vp],
+    "addk_matvec_noalloc": [_vp, _i32, _vp, _i64, _vp, _i64, _vp],
     "addk_dmatvec": [_vp, _i32, _vp, _i64, _vp, _vp, _vp, _i64, _vp],
     "addk_vjp": [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp],
     "addk_plan_update_params": [_vp, _pd, _pd, _vp],

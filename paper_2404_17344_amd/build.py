@@ -33,7 +33,7 @@ COMMON = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["kernels.hip", "dense.hip", "mfma.hip", "plan.hip", "api.hip", "solve.hip", "nearfield.hip"]
+SOURCES = ["kernels.hip", "dense.hip", "mfma.hip", "plan.hip", "api.hip", "solve.hip", "nearfield.hip", "noalloc.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

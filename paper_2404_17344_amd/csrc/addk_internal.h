@@ -243,6 +243,16 @@ struct Plan {
     int device = 0;
 };
 
+// Per-call workspace of an engine for cap complex grids per window and rcap
+// right-hand sides (bytes; dense spread blocks in elements of the engine's
+// precision).
+struct WsLayout {
+    int cap = 0;
+    int64_t rcap = 0;
+    int64_t grid_bytes = 0, y_bytes = 0, nys_bytes = 0, vpack_bytes = 0, vpack_ld = 0;
+    int64_t scratch_elems[2] = {0, 0};
+};
+
 // ---- helpers implemented in the .hip files --------------------------------
 void set_error(const std::string &msg);
 addk_status hip_fail(hipError_t e, const char *what);
@@ -250,8 +260,13 @@ addk_status hip_fail(hipError_t e, const char *what);
 // kernels.hip
 addk_status engine_build_device(Engine &E, int device_precision);
 addk_status engine_ensure_workspace(Engine &E, int R);
+WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap);
+void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *nys, void *vpack, void *scr0,
+                    void *scr1);
 addk_status engine_run(Engine &E, int R, int nout, bool store_vmodes_only, bool store_gmodes,
                        IoArgs io, hipStream_t st);
+addk_status engine_run_bound(Engine &E, int R, int nout, bool store_vmodes_only, bool store_gmodes,
+                             IoArgs io, hipStream_t st);
 addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st);
 addk_status engine_mode_dot(Engine &E, int npair, double *grad_ell, double *grad_sig, hipStream_t st);
 addk_status engine_gsi(Engine &E, const std::vector<const double *> &B64, const double *psi, int n, double *theta,
@@ -280,5 +295,8 @@ addk_status engine_near_dot(Engine &E, int R, IoArgs io, const double *V, int64_
 
 // plan.hip
 addk_status plan_compute_multipliers(Plan &pl, hipStream_t st);
+
+// api.hip: a device FP64 matrix argument (ld >= N, device memory; NULL allowed unless required)
+addk_status check_mat(const void *p, int64_t ld, int64_t N, const char *name, bool required);
 
 }  // namespace addk

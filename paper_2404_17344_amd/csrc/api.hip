@@ -31,7 +31,7 @@ static bool on_device(const void *p)
     return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
 }
 
-static addk_status check_mat(const void *p, int64_t ld, int64_t N, const char *name, bool required)
+addk_status check_mat(const void *p, int64_t ld, int64_t N, const char *name, bool required)
 {
     if (!p) {
         if (required)

@@ -1314,7 +1314,104 @@ addk_status engine_build_device(Engine &E, int precision)
                 return hip_fail(e, "hipMemcpy(groups)");
         }
     }
+    // the descriptor table (uploaded with the workspace pointers)
+    if (!E.d_wins) {
+        hipError_t e = hipMalloc(&E.d_wins, std::max<size_t>(1, E.wdev.size()) * sizeof(WinDev));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(descriptors)");
+    }
     return ADDK_OK;
+}
+
+// Sizes of the per-call workspace for cap complex grids per window and rcap
+// right-hand sides (also fills the per-window grid sizes of the descriptors).
+WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
+{
+    WsLayout L;
+    L.cap = cap;
+    L.rcap = rcap;
+    const size_t cs = 2 * real_size(E.precision);
+    int64_t total = 0, ytotal = 0, ys = 0;
+    for (WinDev &w : E.wdev) {
+        const int64_t ex = w.ext[0], ey = w.ext[1], ez = w.ext[2], n1 = w.n1;
+        w.szG = ex * ey * ez;
+        w.szH = w.szG;
+        w.szA1 = w.d >= 2 ? n1 * ey * ez : 0;
+        w.szA2 = w.d == 3 ? n1 * n1 * ez : 0;
+        w.szA3 = w.d == 3 ? n1 * n1 * ez : (w.d == 2 ? n1 * ey : 0);
+        w.szA4 = w.d == 3 ? n1 * ey * ez : 0;
+        w.szM = w.d == 3 ? n1 * n1 * n1 : (w.d == 2 ? n1 * n1 : n1);
+        total += (int64_t)cap * (w.szG + w.szA1 + w.szA2 + 2 * (w.szA3 + w.szA4 + w.szH) + 2 * w.szM);
+        ytotal += 2 * rcap * w.N;
+        ys += w.nf ? 2 * w.N : 0;
+    }
+    L.grid_bytes = std::max<int64_t>(total * (int64_t)cs, 256);
+    L.y_bytes = std::max<int64_t>(ytotal * (int64_t)sizeof(double), 256);
+    L.nys_bytes = ys * (int64_t)sizeof(double);
+    int64_t packN = 0;
+    for (const Plan *pl : E.plans)
+        packN += pl->N;
+    L.vpack_ld = (rcap + 15) / 16 * 16;
+    L.vpack_bytes = std::max<int64_t>(packN * L.vpack_ld * (int64_t)real_size(E.precision), 256);
+    for (int wi = 0; wi < 2; ++wi) {
+        const int W = wi == 0 ? 8 : 12;
+        L.scratch_elems[wi] = (int64_t)E.ndense_sp[3][wi] * ((rcap + 15) / 16) * (W + 1) * W * W * 16;
+    }
+    return L;
+}
+
+// Point the engine's descriptors and problem records at workspace buffers of
+// layout L (grids, per-window products, close-pair sums, RHS staging, dense
+// spread blocks).  Host-side only: the descriptors still need an upload.
+void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *nys, void *vpack, void *scr0,
+                    void *scr1)
+{
+    const size_t cs = 2 * real_size(E.precision);
+    E.ws = ws;
+    E.ws_bytes = L.grid_bytes + L.nys_bytes + L.vpack_bytes +
+                 (L.scratch_elems[0] + L.scratch_elems[1]) * (int64_t)real_size(E.precision);
+    E.yw = yw;
+    E.yw_bytes = L.y_bytes;
+    E.d_near_ys = nys;
+    E.vpack = vpack;
+    E.vpack_bytes = L.vpack_bytes;
+    E.vpack_ld = L.vpack_ld;
+    E.scratch[0] = L.scratch_elems[0] > 0 ? scr0 : nullptr;
+    E.scratch[1] = L.scratch_elems[1] > 0 ? scr1 : nullptr;
+    E.scratch_cap[0] = E.scratch[0] ? L.scratch_elems[0] : 0;
+    E.scratch_cap[1] = E.scratch[1] ? L.scratch_elems[1] : 0;
+    int64_t off = 0;
+    for (size_t p = 0; p < E.probs.size(); ++p) {
+        E.probs[p].Vp = (const char *)vpack + off * real_size(E.precision);
+        E.probs[p].ldvp = L.vpack_ld;
+        off += E.probs[p].N * L.vpack_ld;
+    }
+    char *p = (char *)ws;
+    double *yp = yw, *q = nys;
+    for (WinDev &w : E.wdev) {
+        auto take = [&](int64_t n) {
+            void *r = p;
+            p += n * cs;
+            return r;
+        };
+        w.G = take(L.cap * w.szG);
+        w.A1 = take(L.cap * w.szA1);
+        w.A2 = take(L.cap * w.szA2);
+        w.A3 = take(2 * L.cap * w.szA3);
+        w.A4 = take(2 * L.cap * w.szA4);
+        w.H = take(2 * L.cap * w.szH);
+        w.Vm = take(L.cap * w.szM);
+        w.Gm = take(L.cap * w.szM);
+        w.npair_cap = L.cap;
+        w.Rcap = L.rcap;
+        w.Yw = yp;
+        yp += 2 * L.rcap * w.N;
+        w.nf_ys = w.nf ? q : nullptr;
+        q += w.nf ? 2 * w.N : 0;
+    }
+    E.npair_cap = L.cap;
+    E.rcap = L.rcap;
+    E.dirty = true;
 }
 
 // Allocate grids for at least ceil(R/2) complex grids per window and the FP64
@@ -1328,127 +1425,63 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess)
         return hip_fail(e, "hipDeviceSynchronize");
-    const int cap = std::max(npair, E.npair_cap);
-    const int64_t rcap = std::max<int64_t>(R, E.rcap);
-    const size_t cs = 2 * real_size(E.precision);
-    int64_t total = 0, ytotal = 0;
-    for (WinDev &w : E.wdev) {
-        const int64_t ex = w.ext[0], ey = w.ext[1], ez = w.ext[2], n1 = w.n1;
-        w.szG = ex * ey * ez;
-        w.szH = w.szG;
-        w.szA1 = w.d >= 2 ? n1 * ey * ez : 0;
-        w.szA2 = w.d == 3 ? n1 * n1 * ez : 0;
-        w.szA3 = w.d == 3 ? n1 * n1 * ez : (w.d == 2 ? n1 * ey : 0);
-        w.szA4 = w.d == 3 ? n1 * ey * ez : 0;
-        w.szM = w.d == 3 ? n1 * n1 * n1 : (w.d == 2 ? n1 * n1 : n1);
-        total += (int64_t)cap * (w.szG + w.szA1 + w.szA2 + 2 * (w.szA3 + w.szA4 + w.szH) + 2 * w.szM);
-        ytotal += 2 * rcap * w.N;
-    }
+    const WsLayout L = engine_ws_layout(E, std::max(npair, E.npair_cap), std::max<int64_t>(R, E.rcap));
     free_dev(E.ws);
     free_dev(E.yw);
-    E.ws = nullptr;
-    E.yw = nullptr;
-    const int64_t bytes = std::max<int64_t>(total * (int64_t)cs, 256);
-    e = hipMalloc(&E.ws, bytes);
-    if (e != hipSuccess) {
-        set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    free_dev(E.d_near_ys);
+    free_dev(E.vpack);
+    free_dev(E.scratch[0]);
+    free_dev(E.scratch[1]);
+    E.ws = E.yw = nullptr;
+    E.d_near_ys = nullptr;
+    E.vpack = E.scratch[0] = E.scratch[1] = nullptr;
+    void *ws = nullptr, *vp = nullptr, *scr[2] = {nullptr, nullptr};
+    double *yw = nullptr, *nys = nullptr;
+    auto release = [&]() {
+        free_dev(ws);
+        free_dev(yw);
+        free_dev(nys);
+        free_dev(vp);
+        free_dev(scr[0]);
+        free_dev(scr[1]);
+    };
+    if (hipMalloc(&ws, L.grid_bytes) != hipSuccess) {
+        release();
+        set_error("workspace allocation of " + std::to_string(L.grid_bytes) + " bytes failed");
         return ADDK_ERR_OOM;
     }
-    const int64_t ybytes = std::max<int64_t>(ytotal * (int64_t)sizeof(double), 256);
-    e = hipMalloc(&E.yw, ybytes);
-    if (e != hipSuccess) {
+    if (hipMalloc(&yw, L.y_bytes) != hipSuccess) {
+        release();
         set_error("per-window product buffer allocation failed");
         return ADDK_ERR_OOM;
     }
-    E.ws_bytes = bytes;
-    E.yw_bytes = ybytes;
     // close-pair sums of the near-field windows by sorted position, cleared here
     // once and by every pass that reads them
-    {
-        int64_t ys = 0;
-        for (const WinDev &w : E.wdev)
-            ys += w.nf ? 2 * w.N : 0;
-        free_dev(E.d_near_ys);
-        E.d_near_ys = nullptr;
-        if (ys > 0) {
-            e = hipMalloc(&E.d_near_ys, ys * sizeof(double));
-            if (e == hipSuccess)
-                e = hipMemset(E.d_near_ys, 0, ys * sizeof(double));
-            if (e != hipSuccess)
-                return hip_fail(e, "near-field sum buffer");
-            E.ws_bytes += ys * (int64_t)sizeof(double);
-        }
-        double *q = E.d_near_ys;
-        for (WinDev &w : E.wdev) {
-            w.nf_ys = w.nf ? q : nullptr;
-            q += w.nf ? 2 * w.N : 0;
+    if (L.nys_bytes > 0) {
+        e = hipMalloc(&nys, L.nys_bytes);
+        if (e == hipSuccess)
+            e = hipMemset(nys, 0, L.nys_bytes);
+        if (e != hipSuccess) {
+            release();
+            return hip_fail(e, "near-field sum buffer");
         }
     }
     // point-major copy of the right-hand sides of every problem
-    {
-        int64_t packN = 0;
-        for (const Plan *pl : E.plans)
-            packN += pl->N;
-        const int64_t ld = (rcap + 15) / 16 * 16;
-        const int64_t vb = std::max<int64_t>(packN * ld * (int64_t)real_size(E.precision), 256);
-        free_dev(E.vpack);
-        E.vpack = nullptr;
-        e = hipMalloc(&E.vpack, vb);
-        if (e != hipSuccess) {
-            set_error("right-hand side staging allocation failed");
-            return ADDK_ERR_OOM;
-        }
-        E.vpack_bytes = vb;
-        E.vpack_ld = ld;
-        E.ws_bytes += vb;
-        int64_t off = 0;
-        for (size_t p = 0; p < E.probs.size(); ++p) {
-            E.probs[p].Vp = (const char *)E.vpack + off * real_size(E.precision);
-            E.probs[p].ldvp = ld;
-            off += E.probs[p].N * ld;
-        }
+    if (hipMalloc(&vp, L.vpack_bytes) != hipSuccess) {
+        release();
+        set_error("right-hand side staging allocation failed");
+        return ADDK_ERR_OOM;
     }
     // per-item blocks of the d = 3 dense spread (either kernel), in the engine's
     // precision: items x RHS blocks x (2m + 1) (2m)^2 x 16
-    for (int wi = 0; wi < 2; ++wi) {
-        const int W = wi == 0 ? 8 : 12;
-        const int64_t need = (int64_t)E.ndense_sp[3][wi] * ((rcap + 15) / 16) * (W + 1) * W * W * 16;
-        free_dev(E.scratch[wi]);
-        E.scratch[wi] = nullptr;
-        E.scratch_cap[wi] = 0;
-        if (need > 0) {
-            e = hipMalloc(&E.scratch[wi], need * (int64_t)real_size(E.precision));
-            if (e != hipSuccess) {
-                set_error("dense spread scratch allocation failed");
-                return ADDK_ERR_OOM;
-            }
-            E.scratch_cap[wi] = need;
-            E.ws_bytes += need * (int64_t)real_size(E.precision);
+    for (int wi = 0; wi < 2; ++wi)
+        if (L.scratch_elems[wi] > 0 && hipMalloc(&scr[wi], L.scratch_elems[wi] * (int64_t)real_size(E.precision)) !=
+                                           hipSuccess) {
+            release();
+            set_error("dense spread scratch allocation failed");
+            return ADDK_ERR_OOM;
         }
-    }
-    char *p = (char *)E.ws;
-    double *yp = E.yw;
-    for (WinDev &w : E.wdev) {
-        auto take = [&](int64_t n) {
-            void *q = p;
-            p += n * cs;
-            return q;
-        };
-        w.G = take(cap * w.szG);
-        w.A1 = take(cap * w.szA1);
-        w.A2 = take(cap * w.szA2);
-        w.A3 = take(2 * cap * w.szA3);
-        w.A4 = take(2 * cap * w.szA4);
-        w.H = take(2 * cap * w.szH);
-        w.Vm = take(cap * w.szM);
-        w.Gm = take(cap * w.szM);
-        w.npair_cap = cap;
-        w.Rcap = rcap;
-        w.Yw = yp;
-        yp += 2 * rcap * w.N;
-    }
-    E.npair_cap = cap;
-    E.rcap = rcap;
+    engine_bind_ws(E, L, ws, yw, nys, vp, scr[0], scr[1]);
     return engine_upload(E);
 }
 
@@ -1664,6 +1697,13 @@ addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_
     addk_status s = engine_ensure_workspace(E, R);
     if (s != ADDK_OK)
         return s;
+    return engine_run_bound(E, R, nout, vmodes_only, store_gmodes, io, st);
+}
+
+// engine_run on the workspace already bound and uploaded (room for R RHS).
+addk_status engine_run_bound(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io,
+                             hipStream_t st)
+{
     const int modes_sel = vmodes_only ? 1 : (store_gmodes ? 2 : 0);
     const int no = vmodes_only ? 0 : nout;
     if (!io.table) {
