@@ -11,7 +11,7 @@
  * with (K_w)_ij = kappa(||x_i^{W_w} - x_j^{W_w}||; l_w).  The kernel is the
  * windowed additive kernel of eqs. (3), (7)-(8) of Wagner, Nestler & Stoll, "Fast
  * evaluation of additive kernels" (Gaussian, "Implementing the NFFT approach";
- * Matern-1/2, "Extension to other kernels"); its derivatives are those of the
+ * Matern-1/2 and Matern-3/2, "Extension to other kernels"); its derivatives are those of the
  * same sections.  Each window's product is evaluated by the NFFT-based fast
  * summation of eqs. (4)-(6): window-function spreading onto an oversampled
  * torus grid, FFT, multiplication by the kernel's periodised Fourier
@@ -54,7 +54,10 @@ typedef enum {
 
 typedef enum {
     ADDK_GAUSSIAN = 1, /* kappa(r) = exp(-r^2/(2 l^2)); derivative kernel r^2/(2l^2) kappa */
-    ADDK_MATERN12 = 3  /* kappa(r) = exp(-r/l);        derivative kernel (r/l) kappa       */
+    ADDK_MATERN12 = 3, /* kappa(r) = exp(-r/l);        derivative kernel (r/l) kappa       */
+    ADDK_MATERN32 = 5  /* kappa(r) = (1 + a r) exp(-a r), a = sqrt(3)/l ("Extension to other
+                          kernels" names it as a further kernel); derivative kernel
+                          l dkappa/dl = (a r)^2 exp(-a r)                                   */
 } addk_kernel;
 
 typedef enum {
@@ -74,11 +77,13 @@ typedef enum {
                                      kernels); same results up to rounding, for comparison     */
 #define ADDK_VECTOR_ALU_ONLY 16u  /* FP32 plans: run the dense-cell kernels on the vector ALUs
                                      instead of the matrix cores; for comparison              */
-#define ADDK_NEAR_FIELD 32u       /* ADDK_MATERN12 only: near-field corrected products (below) */
+#define ADDK_NEAR_FIELD 32u       /* Matern kernels only: near-field corrected products (below) */
 
 /*
  * ADDK_NEAR_FIELD.  The Matern-1/2 kernel has a cusp at r = 0, so its
- * truncated Fourier series alone stays near 1e-2 (relative) at n = 64.  With
+ * truncated Fourier series alone stays near 1e-2 (relative) at n = 64; the
+ * Matern-3/2 kernel is smooth at r = 0 only to second order (an r^3 term), so
+ * its series stays near 1e-3.  With
  * this flag (regularisation for non-smooth kernels in NFFT-based fast
  * summation, which the kernel extension of section 5 builds on):
  *  - each window's torus period is T_w = 5 L_w / 2 and the periodic kernel has
@@ -112,7 +117,7 @@ typedef struct addk_batch_s *addk_batch;
  *  P, win_offsets, win_features
  *                   window w uses features win_features[win_offsets[w] ..
  *                   win_offsets[w+1]-1]; 1 <= d_w <= 3; host memory.
- *  kernel           ADDK_GAUSSIAN or ADDK_MATERN12.
+ *  kernel           ADDK_GAUSSIAN, ADDK_MATERN12 or ADDK_MATERN32.
  *  ell, sigma       P length scales (> 0) and P amplitudes sigma_w (>= 0), host.
  *                   ell is in the units of X.
  *  n                Fourier bandwidth per dimension (even, >= 4): modes
@@ -189,7 +194,7 @@ addk_status addk_matvec_noalloc(addk_plan plan, int32_t R, const double *V, int6
  * and the derivative kernel's multipliers.
  *   dY_dell  : P blocks of N x R, block w at dY_dell + w * ldy * R:
  *              sigma_w^2 (dK_w/dl_w) V = sigma_w^2 (2/l_w) K_der,w V (Gaussian)
- *                                      = sigma_w^2 (1/l_w) K_derM,w V (Matern-1/2)
+ *                                      = sigma_w^2 (1/l_w) K_derM,w V (Matern-1/2, -3/2)
  *   dY_dsigma: P blocks, 2 sigma_w K_w V
  *   Y        : sum_w sigma_w^2 K_w V
  * Any of the three may be NULL (not all three).  All use leading dimension ldy.
@@ -244,6 +249,23 @@ addk_status addk_cg(addk_plan plan, double beta, int32_t R, const double *Y, int
  */
 addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *stream);
 
+/*
+ * The global sensitivity indices of Algorithm 1 (section "Computing the GSI
+ * in the kernel setting") over all windows: addk_gsi's theta summed, per
+ * feature subset u (of the plan's feature indices), over every window and
+ * support mask whose features are u, divided by the total over all nonempty
+ * subsets, so the indices sum to 1 (all 0 if the total is 0).
+ *   v        N doubles, device (one right-hand side)
+ *   cap      room in subsets / rho (at most 7 P subsets occur)
+ *   subsets  host int32 [cap][3]: the subset's features ascending, -1 padded
+ *   rho      host double [cap]: the index of each subset
+ *   count    host: the number of subsets (set also when it exceeds cap)
+ * Subsets are listed in order of first appearance (windows in order, masks
+ * ascending).  Synchronous.  Errors: as addk_gsi; INVALID_ARG when count > cap.
+ */
+addk_status addk_gsi_indices(addk_plan plan, const double *v, int32_t cap, int32_t *subsets, double *rho,
+                             int32_t *count, void *stream);
+
 /* Replace l_w and sigma_w (host arrays of P) and recompute the multipliers; the
  * torus periods, grids and point sort are kept, so products stay differentiable
  * in l.  Errors: INVALID_ARG, ACCURACY (as in addk_plan_create). */
@@ -288,6 +310,9 @@ addk_status addk_plan_destroy(addk_plan plan);
  *  R         RHS per problem (same for all)
  *  V[p], ldv[p], Y[p], ldy[p]   device buffers bound to the graph (host arrays
  *            of nprob device pointers / leading dimensions).
+ * addk_plan_update_params on a plan of the batch takes effect at the batch's
+ * next launch (launch, eager run or autotune), which then uploads the new
+ * parameters synchronously before queueing the work; the graph is kept.
  * Errors: INVALID_ARG, OOM, HIP.
  */
 addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *plans, int32_t R,
@@ -348,6 +373,18 @@ addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, u
  * Errors: INVALID_ARG; ACCURACY when no supported n reaches tol. */
 addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, double oversampling, double tol,
                           int32_t *n, double *err_estimate);
+
+/* The bandwidth for a whole plan: addk_choose_n for every window, with L the
+ * largest per-feature range of the window's points, and the largest of those
+ * n.  X is N x D row-major (X[j*ldx + f]), host or device memory (device: the
+ * ranges are reduced on the GPU, on `stream`); windows as in addk_plan_create.
+ * err_estimate (optional) receives the largest per-window estimate at the
+ * chosen n.  Synchronous.  Errors: INVALID_ARG; ACCURACY when some window
+ * reaches tol with no supported n; OOM, HIP. */
+addk_status addk_choose_n_windows(int32_t kernel, int64_t N, int32_t D, const double *X, int64_t ldx, int32_t P,
+                                  const int32_t *win_offsets, const int32_t *win_features, const double *ell,
+                                  int32_t m, double oversampling, double tol, int32_t *n, double *err_estimate,
+                                  void *stream);
 
 /* Fourier transform of the normalised Kaiser-Bessel window used for spreading,
  * Psi(k) = int psi(z) e^{-2 pi i z k / n_os} dz, evaluated by Gauss-Legendre

@@ -16,15 +16,15 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, AddkError,  # noqa: F401
+from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, ADDK_MATERN32, AddkError,  # noqa: F401
                    ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK, ADDK_KNOB_SPREAD_MFMA,
                    ADDK_KNOB_INTERP_DENSE_MFMA, ADDK_KNOB_INTERP_TILE_MFMA, ADDK_KNOB_ALL_MFMA)
 
 __all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "choose_n", "choose_n_for",
            "KernelMatvec"]
 
-_KERNELS = {"gaussian": ADDK_GAUSSIAN, "matern12": ADDK_MATERN12, ADDK_GAUSSIAN: ADDK_GAUSSIAN,
-            ADDK_MATERN12: ADDK_MATERN12}
+_KERNELS = {"gaussian": ADDK_GAUSSIAN, "matern12": ADDK_MATERN12, "matern32": ADDK_MATERN32,
+            ADDK_GAUSSIAN: ADDK_GAUSSIAN, ADDK_MATERN12: ADDK_MATERN12, ADDK_MATERN32: ADDK_MATERN32}
 _PREC = {"fp64": ADDK_FP64, "fp32": ADDK_FP32, ADDK_FP64: ADDK_FP64, ADDK_FP32: ADDK_FP32}
 
 
@@ -78,17 +78,39 @@ def choose_n(kernel, L: float, ell: float, m: int = 6, oversampling: float = 2.0
     return n.value, err.value
 
 
+def _win_arrays(windows):
+    off = [0]
+    feat = []
+    for w in windows:
+        feat.extend(int(f) for f in w)
+        off.append(len(feat))
+    return (ctypes.c_int32 * len(off))(*off), (ctypes.c_int32 * max(1, len(feat)))(*feat)
+
+
 def choose_n_for(X, windows: Sequence[Sequence[int]], ell, kernel="gaussian", m: int = 6,
-                 oversampling: float = 2.0, tol: float = 1e-5) -> int:
-    """Bandwidth for a whole plan: the largest per-window choice (host X, (N, D))."""
-    X = np.asarray(X, dtype=np.float64)
-    ell = np.broadcast_to(np.asarray(ell, dtype=np.float64), (len(windows),))
-    best = 0
-    for w, feats in enumerate(windows):
-        sub_x = X[:, list(feats)]
-        L = float((sub_x.max(axis=0) - sub_x.min(axis=0)).max()) if X.shape[0] else 0.0
-        best = max(best, choose_n(kernel, L, ell[w], m, oversampling, tol)[0])
-    return best
+                 oversampling: float = 2.0, tol: float = 1e-5, with_estimate: bool = False):
+    """Bandwidth for a whole plan (addk_choose_n_windows): the largest per-window
+    choice.  X: (N, D) host array or CUDA tensor.  Returns n, or (n, estimate)."""
+    lib = _lib.load()
+    torch = _torch()
+    if isinstance(X, torch.Tensor):
+        Xk = X.detach().to(torch.float64).contiguous()
+        N, D = Xk.shape
+        xptr = Xk.data_ptr() if N else None
+        st = _stream()
+    else:
+        Xk = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+        N, D = Xk.shape
+        xptr = Xk.ctypes.data if N else None
+        st = ctypes.c_void_p(0)
+    off_a, feat_a = _win_arrays(windows)
+    ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (len(windows),)))
+    n = ctypes.c_int32()
+    err = ctypes.c_double()
+    _lib.check(lib.addk_choose_n_windows(_KERNELS[kernel], N, D, xptr, D, len(windows), off_a, feat_a,
+                                         ell_a.ctypes.data_as(_lib._pd), int(m), float(oversampling), float(tol),
+                                         ctypes.byref(n), ctypes.byref(err), st), "addk_choose_n_windows")
+    return (n.value, err.value) if with_estimate else n.value
 
 
 class Plan:
@@ -100,7 +122,7 @@ class Plan:
                  targets=None, near_field: bool = False, stream=None):
         """X: sources (N, D), host array or CUDA tensor.  targets: optional (Nt, D)
         prediction points; the plan's products then map N-row V to Nt-row Y.
-        near_field (Matern-1/2 only): regularised multipliers on an image-free
+        near_field (Matern kernels only): regularised multipliers on an image-free
         torus plus a direct sum over close pairs (ADDK_NEAR_FIELD), which
         brings the products to ~1e-5 of the direct sum."""
         lib = _lib.load()
@@ -118,17 +140,11 @@ class Plan:
             self._tkeep, Nt, Dt, tptr = _points(targets)
             if Dt != D:
                 raise ValueError("targets must have the sources' number of features")
-        off = [0]
-        feat = []
-        for w in windows:
-            feat.extend(int(f) for f in w)
-            off.append(len(feat))
         self.P = len(windows)
         self.N = int(N)  # rows of V
         self.N_out = int(Nt) if targets is not None else int(N)  # rows of Y
         self.windows = [list(w) for w in windows]
-        off_a = (ctypes.c_int32 * len(off))(*off)
-        feat_a = (ctypes.c_int32 * max(1, len(feat)))(*feat)
+        off_a, feat_a = _win_arrays(windows)
         ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))
         sig_a = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (self.P,)))
         flags = 0
@@ -203,15 +219,18 @@ class Plan:
         return th.reshape(self.P, 8)
 
     def gsi(self, v, stream=None) -> dict:
-        """Global sensitivity indices {feature tuple: rho} over all windows and their subsets."""
-        th = self.gsi_theta(v, stream)
-        acc = {}
-        for w, feats in enumerate(self.windows):
-            for mask in range(1, 1 << len(feats)):
-                key = tuple(sorted(feats[i] for i in range(len(feats)) if mask >> i & 1))
-                acc[key] = acc.get(key, 0.0) + th[w, mask]
-        total = sum(acc.values())
-        return {k: (val / total if total > 0 else 0.0) for k, val in acc.items()}
+        """Global sensitivity indices {feature tuple: rho} over all windows and
+        their subsets (addk_gsi_indices)."""
+        vc = _colmajor(v)
+        if vc.shape[0] != 1:
+            raise ValueError("gsi takes one right-hand side")
+        cap = 7 * self.P
+        subsets = (ctypes.c_int32 * (3 * cap))()
+        rho = np.zeros(cap)
+        count = ctypes.c_int32()
+        _lib.check(self._lib.addk_gsi_indices(self._h, vc.data_ptr(), cap, subsets, rho.ctypes.data_as(_lib._pd),
+                                              ctypes.byref(count), _stream(stream)), "addk_gsi_indices")
+        return {tuple(f for f in subsets[3 * j:3 * j + 3] if f >= 0): float(rho[j]) for j in range(count.value)}
 
     def autotune(self, R: int, nout: int = 1, reps: int = 3, stream=None) -> int:
         """Time the kernel-variant combinations on this plan and keep the fastest (ADDK_KNOB_* mask)."""

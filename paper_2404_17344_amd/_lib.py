@@ -20,6 +20,7 @@ ADDK_ERR_HIP = 5
 
 ADDK_GAUSSIAN = 1
 ADDK_MATERN12 = 3
+ADDK_MATERN32 = 5
 ADDK_FP64 = 0
 ADDK_FP32 = 1
 
@@ -67,6 +68,7 @@ _SIGS = {
     "addk_vjp": [_vp, _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp],
     "addk_plan_update_params": [_vp, _pd, _pd, _vp],
     "addk_gsi": [_vp, _vp, _pd, _vp],
+    "addk_gsi_indices": [_vp, _vp, _i32, _pi32, _pd, _pi32, _vp],
     "addk_cg": [_vp, _d, _i32, _vp, _i64, _vp, _i64, _d, _i32, _pi32, _pd, _vp],
     "addk_plan_create_targets": [ctypes.POINTER(_vp), _i64, _i64, _i32, _vp, _i64, _vp, _i64, _i32, _pi32, _pi32,
                                  _i32, _pd, _pd, _i32, _i32, _d, _i32, _u32, _vp],
@@ -85,6 +87,7 @@ _SIGS = {
     "addk_torus_period": [_i32, _d, _d, _i32, _u32, _i32, _pd],
     "addk_window_ft": [_i32, _i32, _d, _d, _pd],
     "addk_choose_n": [_i32, _d, _d, _i32, _d, _d, _pi32, _pd],
+    "addk_choose_n_windows": [_i32, _i64, _i32, _vp, _i64, _i32, _pi32, _pi32, _pd, _i32, _d, _d, _pi32, _pd, _vp],
     "addk_status_string": [_i32],
     "addk_last_error": [],
     "addk_version": [],

@@ -241,6 +241,7 @@ struct Plan {
     double *d_psi = nullptr;
     Engine eng;
     int device = 0;
+    uint64_t param_gen = 0;  // counts addk_plan_update_params calls (batches refresh their copies)
 };
 
 // Per-call workspace of an engine for cap complex grids per window and rcap

@@ -60,11 +60,50 @@ static ProbDev single_prob(const Plan &pl)
 struct Batch {
     Engine eng;
     std::vector<Plan *> plans;
+    std::vector<uint64_t> gens;  // each plan's parameter generation the descriptors hold
     int R = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
 };
+
+// The batch holds copies of its plans' window descriptors.  After
+// addk_plan_update_params on a plan, copy its new parameters (amplitude
+// factors, near-field polynomials, multiplier pointers) into the batch's
+// descriptors and upload them; the graph reads them from device memory, so
+// it needs no new capture.
+static addk_status batch_refresh_params(Batch &b)
+{
+    bool stale = false;
+    for (size_t p = 0; p < b.plans.size(); ++p) {
+        const Plan &pl = *b.plans[p];
+        if (b.gens[p] == pl.param_gen)
+            continue;
+        stale = true;
+        const int wbeg = b.eng.probs[p].wbeg;
+        for (int w = 0; w < pl.P; ++w) {
+            const WinDev &src = pl.eng.wdev[w];
+            WinDev &dst = b.eng.wdev[wbeg + w];
+            dst.sig2 = src.sig2;
+            dst.der_scale = src.der_scale;
+            dst.dsig = src.dsig;
+            dst.Bk = src.Bk;
+            dst.Bd = src.Bd;
+            dst.nf_eps2 = src.nf_eps2;
+            dst.nf_inv_eps2 = src.nf_inv_eps2;
+            dst.nf_hl = src.nf_hl;
+            for (int j = 0; j <= kNearQ; ++j) {
+                dst.nf_a[j] = src.nf_a[j];
+                dst.nf_ad[j] = src.nf_ad[j];
+            }
+        }
+        b.gens[p] = pl.param_gen;
+    }
+    if (!stale)
+        return ADDK_OK;
+    b.eng.dirty = true;
+    return engine_upload(b.eng);
+}
 
 static addk_status batch_enqueue(Batch &b, hipStream_t st)
 {
@@ -326,6 +365,56 @@ addk_status addk_gsi(addk_plan plan, const double *v, double *theta, void *strea
     return s;
 }
 
+addk_status addk_gsi_indices(addk_plan plan, const double *v, int32_t cap, int32_t *subsets, double *rho,
+                             int32_t *count, void *stream)
+{
+    if (!plan)
+        return fail2(ADDK_ERR_INVALID_ARG, "plan is NULL");
+    if (!count || cap < 0 || (cap > 0 && (!subsets || !rho)))
+        return fail2(ADDK_ERR_INVALID_ARG, "addk_gsi_indices: count, and subsets and rho for cap > 0, are required");
+    Plan &pl = *(Plan *)plan;
+    std::vector<double> theta(8 * (size_t)pl.P, 0.0);
+    addk_status s = addk_gsi(plan, v, theta.data(), stream);
+    if (s != ADDK_OK)
+        return s;
+    // Algorithm 1, last steps: the variance of every feature subset u is the sum
+    // of theta over the windows and support masks whose features are u; the
+    // indices divide by the total over all nonempty subsets.
+    std::vector<std::vector<int32_t>> keys;
+    std::vector<double> var;
+    for (int w = 0; w < pl.P; ++w) {
+        const WinHost &wh = pl.wins[w];
+        for (int mask = 1; mask < (1 << wh.d); ++mask) {
+            std::vector<int32_t> k;
+            for (int i = 0; i < wh.d; ++i)
+                if (mask >> i & 1)
+                    k.push_back(wh.feat[i]);
+            std::sort(k.begin(), k.end());
+            size_t j = 0;
+            while (j < keys.size() && keys[j] != k)
+                ++j;
+            if (j == keys.size()) {
+                keys.push_back(k);
+                var.push_back(0.0);
+            }
+            var[j] += theta[8 * (size_t)w + mask];
+        }
+    }
+    double total = 0.0;
+    for (double x : var)
+        total += x;
+    *count = (int32_t)keys.size();
+    if ((int32_t)keys.size() > cap)
+        return fail2(ADDK_ERR_INVALID_ARG, "addk_gsi_indices: " + std::to_string(keys.size()) +
+                                               " feature subsets, more than cap = " + std::to_string(cap));
+    for (size_t j = 0; j < keys.size(); ++j) {
+        for (int i = 0; i < 3; ++i)
+            subsets[3 * j + i] = i < (int)keys[j].size() ? keys[j][i] : -1;
+        rho[j] = total > 0.0 ? var[j] / total : 0.0;
+    }
+    return ADDK_OK;
+}
+
 addk_status addk_plan_profile(addk_plan plan, int32_t enable)
 {
     if (!plan)
@@ -384,6 +473,7 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
     for (int p = 0; p < nprob; ++p) {
         Plan *pl = (Plan *)plans[p];
         b->plans.push_back(pl);
+        b->gens.push_back(pl->param_gen);
         E.plans.push_back(pl);
         ProbDev &pd = E.probs[p];
         std::memset(&pd, 0, sizeof(pd));
@@ -504,6 +594,11 @@ addk_status addk_batch_autotune(addk_batch batch, int32_t reps, uint32_t *knobs,
     Batch &b = *(Batch *)batch;
     Engine &E = b.eng;
     hipStream_t st = (hipStream_t)stream;
+    {
+        addk_status s0 = batch_refresh_params(b);
+        if (s0 != ADDK_OK)
+            return s0;
+    }
     const std::vector<uint32_t> cand = knob_candidates(E);
     const uint32_t saved = E.knobs;
     const bool saved_tuned = E.tuned;
@@ -542,6 +637,9 @@ addk_status addk_batch_launch(addk_batch batch, void *stream)
     if (!batch)
         return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
     Batch &b = *(Batch *)batch;
+    addk_status s = batch_refresh_params(b);
+    if (s != ADDK_OK)
+        return s;
     hipError_t e = hipGraphLaunch(b.exec, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "hipGraphLaunch");
@@ -552,7 +650,11 @@ addk_status addk_batch_run_eager(addk_batch batch, void *stream)
 {
     if (!batch)
         return fail2(ADDK_ERR_INVALID_ARG, "batch is NULL");
-    return batch_enqueue(*(Batch *)batch, (hipStream_t)stream);
+    Batch &b = *(Batch *)batch;
+    addk_status s = batch_refresh_params(b);
+    if (s != ADDK_OK)
+        return s;
+    return batch_enqueue(b, (hipStream_t)stream);
 }
 
 addk_status addk_batch_destroy(addk_batch batch)

@@ -103,6 +103,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
         bmax[a] = wave_max(own ? (float)u[a] : -3.0e38f);
     }
     const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
+    const bool m32 = w.nf == 2;  // Matern-3/2: (1 + a r) e^{-a r} and (a r)^2 e^{-a r}, with rl = a r
     const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;  // slightly generous for the box tests
     real pa[kNearQ + 1], pd[kNearQ + 1];
 #pragma unroll
@@ -220,8 +221,9 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
                                 const real rl = nf_sqrt(d2) * hl;
                                 const real ex = nf_exp(-rl);
                                 const real t2 = d2 * ie2;
-                                const real kn = ex - horner(pa, t2);
-                                const real kd = (NO > 1 || DOT) ? rl * ex - horner(pd, t2) : real(0);
+                                const real kn = (m32 ? real(1) + rl : real(1)) * ex - horner(pa, t2);
+                                const real kd =
+                                    (NO > 1 || DOT) ? rl * (m32 ? rl : real(1)) * ex - horner(pd, t2) : real(0);
                                 if (DOT) {
                                     real dot = real(0);
 #pragma unroll
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
         bmax[a] = uniform(wave_max(own ? (float)u[a] : -3.0e38f));
     }
     const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
+    const bool m32 = w.nf == 2;  // Matern-3/2: (1 + a r) e^{-a r} and (a r)^2 e^{-a r}, with rl = a r
     const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;
     real pa[kNearQ + 1], pd[kNearQ + 1];
 #pragma unroll
@@ -386,10 +389,10 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
                     const real rl = nf_sqrt(d2v[q]) * hl;
                     const real ex = nf_exp(-rl);
                     const real t2 = d2v[q] * ie2;
-                    kn = ex - horner(pa, t2);
+                    kn = (m32 ? real(1) + rl : real(1)) * ex - horner(pa, t2);
                     acc[0] += kn * s4[q][3];
                     if (NO > 1) {
-                        kd = rl * ex - horner(pd, t2);
+                        kd = rl * (m32 ? rl : real(1)) * ex - horner(pd, t2);
                         acc[NO > 1 ? 1 : 0] += kd * s4[q][3];
                     }
                 }

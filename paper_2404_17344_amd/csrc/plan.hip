@@ -139,6 +139,8 @@ static double torus_period(int kernel, double L, double ell, int n, uint32_t rul
         return 2.0 * L * std::sqrt((double)dmax);
     if (kernel == ADDK_GAUSSIAN)
         return 0.5 * (L + std::sqrt(L * L + 4.0 * M_PI * ell * ell * n));
+    if (kernel == ADDK_MATERN32)  // image factor e^{-sqrt3 (T - L) / l} at the n^-3 truncation level
+        return L + std::sqrt(3.0) * ell * std::log((double)n);
     return L + ell * std::log((double)n);
 }
 
@@ -166,9 +168,12 @@ static double near_fold_width(double L, double ell) { return L > 0.0 ? L : ell; 
 
 // Solve sum_j a_j C(2j, s) = eps^s kappa^(s)(eps) / s!, s = 0..q (the Taylor
 // conditions at t = r / eps = 1, rows divided by s!), by Gaussian elimination
-// with partial pivoting.  kappa^(s)(r) = (-1/l)^s e^{-r/l} for exp(-r/l) and
-// (-1/l)^s e^{-r/l} (r - s l) / l for (r/l) e^{-r/l}.
-static void near_poly(double ell, double eps, bool der, double *a)
+// with partial pivoting.  Matern-1/2: kappa^(s)(r) = (-1/l)^s e^{-r/l} for
+// exp(-r/l) and (-1/l)^s e^{-r/l} (r - s l) / l for (r/l) e^{-r/l}.
+// Matern-3/2, a = sqrt3 / l: (-a)^s e^{-a r} (1 + a r - s) for (1 + a r) e^{-a r}
+// and (-a)^s e^{-a r} ((a r)^2 - 2 s a r + s (s - 1)) for (a r)^2 e^{-a r}
+// (Leibniz on r^k e^{-a r}).
+static void near_poly(int kernel, double ell, double eps, bool der, double *a)
 {
     constexpr int Q = kNearQ + 1;
     double A[Q][Q + 1];
@@ -185,8 +190,14 @@ static void near_poly(double ell, double eps, bool der, double *a)
             }
             A[s][j] = c;
         }
-        const double e = std::exp(-eps / ell) * std::pow(-eps / ell, (double)s);
-        A[s][Q] = (der ? e * (eps - s * ell) / ell : e) / fact;
+        if (kernel == ADDK_MATERN32) {
+            const double ae = std::sqrt(3.0) * eps / ell;
+            const double e = std::exp(-ae) * std::pow(-ae, (double)s);
+            A[s][Q] = (der ? e * (ae * ae - 2.0 * s * ae + s * (s - 1.0)) : e * (1.0 + ae - s)) / fact;
+        } else {
+            const double e = std::exp(-eps / ell) * std::pow(-eps / ell, (double)s);
+            A[s][Q] = (der ? e * (eps - s * ell) / ell : e) / fact;
+        }
     }
     for (int c = 0; c < Q; ++c) {
         int piv = c;
@@ -209,11 +220,11 @@ static void near_poly(double ell, double eps, bool der, double *a)
     }
 }
 
-static void near_setup(WinHost &w, int n)
+static void near_setup(WinHost &w, int kernel, int n)
 {
     w.nf_eps = kNearRadius * w.T / n;
-    near_poly(w.ell, w.nf_eps, false, w.nf_a);
-    near_poly(w.ell, w.nf_eps, true, w.nf_ad);
+    near_poly(kernel, w.ell, w.nf_eps, false, w.nf_a);
+    near_poly(kernel, w.ell, w.nf_eps, true, w.nf_ad);
 }
 
 // A-priori relative error estimate of one window: image + truncation + window terms.
@@ -223,6 +234,13 @@ static double error_estimate(int kernel, double L, double T, double ell, int n, 
     if (kernel == ADDK_GAUSSIAN) {
         img = std::exp(-(T - L) * (T - L) / (2.0 * ell * ell));
         trunc = std::exp(-2.0 * M_PI * M_PI * ell * ell * (n / 2.0) * (n / 2.0) / (T * T));
+    } else if (kernel == ADDK_MATERN32) {
+        // kernel value at the nearest image; tail of the transform beyond n / (2T)
+        // (coefficients decaying like |k|^-(d+3)), in one dimension
+        const double ai = std::sqrt(3.0) * (T - L) / ell;
+        img = (1.0 + ai) * std::exp(-ai);
+        const double q = T / (ell * n);
+        trunc = 12.0 / (std::sqrt(3.0) * M_PI * M_PI * M_PI * M_PI) * q * q * q;
     } else {
         img = std::exp(-(T - L) / ell);
         trunc = T / (M_PI * M_PI * ell * n);
@@ -336,8 +354,16 @@ __device__ double kernel_ft_dev(int kernel, double xi2, double ell, int d, int d
         const double base = pow(ell * sqrt(2.0 * pi), (double)d) * exp(-2.0 * pi * pi * ell * ell * xi2);
         return der ? (0.5 * d - 2.0 * pi * pi * ell * ell * xi2) * base : base;
     }
-    const double cd = d == 1 ? 2.0 : (d == 2 ? 2.0 * pi : 8.0 * pi);
     const double u = 4.0 * pi * pi * ell * ell * xi2;
+    if (kernel == ADDK_MATERN32) {
+        // the Matern spectral density at smoothness 3/2: c_d l^d (1 + u/3)^{-(d+3)/2},
+        // c_d = int_{R^d} (1 + a|x|) e^{-a|x|} dx / l^d with a = sqrt3 / l
+        const double cd = d == 1 ? 4.0 / sqrt(3.0) : (d == 2 ? 2.0 * pi : 32.0 * pi / (3.0 * sqrt(3.0)));
+        const double u3 = u / 3.0;
+        const double base = cd * pow(ell, (double)d) / pow(1.0 + u3, 0.5 * (d + 3));
+        return der ? (d - (d + 3) * u3 / (1.0 + u3)) * base : base;  // l d/dl of the transform
+    }
+    const double cd = d == 1 ? 2.0 : (d == 2 ? 2.0 * pi : 8.0 * pi);
     const double base = cd * pow(ell, (double)d) / pow(1.0 + u, 0.5 * (d + 1));
     return der ? (d - (d + 1) * u / (1.0 + u)) * base : base;
 }
@@ -396,6 +422,10 @@ __global__ void k_samples(double2 *s, int d, int n, double T, double ell, int ke
         if (kernel == ADDK_GAUSSIAN) {
             const double e = exp(-r2 / (2.0 * ell * ell));
             v = der ? r2 / (2.0 * ell * ell) * e : e;
+        } else if (kernel == ADDK_MATERN32) {
+            const double ar = sqrt(3.0 * r2) / ell;
+            const double e = exp(-ar);
+            v = der ? ar * ar * e : (1.0 + ar) * e;
         } else {
             const double rr = sqrt(r2);
             const double e = exp(-rr / ell);
@@ -424,8 +454,19 @@ struct NearPoly {
 // Samples of the regularised near-field kernel at T j / M, j in I_M^d (array
 // index j + M/2, axis 0 fastest): kappa(sqrt(sum_i s(x_i))) - K_NE(|x|) with
 // the folded squares s and K_NE(r) = kappa(r) - p(r) for r < eps.
+__device__ __forceinline__ double matern_value(int kernel, double r, double ell, int der)
+{
+    if (kernel == ADDK_MATERN32) {
+        const double ar = sqrt(3.0) * r / ell;
+        const double e = exp(-ar);
+        return der ? ar * ar * e : (1.0 + ar) * e;
+    }
+    const double e = exp(-r / ell);
+    return der ? r / ell * e : e;
+}
+
 __global__ void k_samples_near(double2 *s, int d, int M, double T, double L, double ell, double eps, NearPoly p,
-                               int der)
+                               int der, int kernel)
 {
     int64_t tot = M;
     for (int i = 1; i < d; ++i)
@@ -447,15 +488,14 @@ __global__ void k_samples_near(double2 *s, int d, int M, double T, double L, dou
             }
         }
         const double rf = sqrt(sf);
-        double v = der ? rf / ell * exp(-rf / ell) : exp(-rf / ell);
+        double v = matern_value(kernel, rf, ell, der);
         const double r0 = sqrt(r2);
         if (r0 < eps) {
             const double t2 = r2 / (eps * eps);
             double q = p.a[kNearQ];
             for (int k = kNearQ - 1; k >= 0; --k)
                 q = q * t2 + p.a[k];
-            const double k0 = der ? r0 / ell * exp(-r0 / ell) : exp(-r0 / ell);
-            v -= k0 - q;
+            v -= matern_value(kernel, r0, ell, der) - q;
         }
         s[idx] = make_double2(v, 0.0);
     }
@@ -604,7 +644,7 @@ addk_status plan_compute_multipliers(Plan &pl, hipStream_t st)
                 for (int j = 0; j <= kNearQ; ++j)
                     p.a[j] = der ? w.nf_ad[j] : w.nf_a[j];
                 hipLaunchKernelGGL(k_samples_near, dim3(nbs), dim3(256), 0, st, s0, w.d, M, w.T, w.nf_Lf, w.ell,
-                                   w.nf_eps, p, der);
+                                   w.nf_eps, p, der, pl.kernel);
                 double2 *a = s0, *bb = s1;
                 for (int ax = 0; ax < w.d; ++ax) {
                     hipLaunchKernelGGL(k_dft_axis, dim3(nbs), dim3(256), 0, st, a, bb, w.d, M, ax, dtw);
@@ -679,14 +719,15 @@ static bool is_device_ptr(const void *p)
 
 static void fill_near(const Plan &pl, const WinHost &w, WinDev &d)
 {
-    d.nf = w.nf ? 1 : 0;
+    d.nf = !w.nf ? 0 : (pl.kernel == ADDK_MATERN32 ? 2 : 1);
     d.tile_off = w.d_tile_off;
     if (!w.nf)
         return;
     const double eg = w.nf_eps * pl.nos / w.T;  // radius in grid units
     d.nf_eps2 = eg * eg;
     d.nf_inv_eps2 = 1.0 / (eg * eg);
-    d.nf_hl = w.T / pl.nos / w.ell;
+    // r / l (Matern-1/2) or sqrt3 r / l (Matern-3/2) per grid unit of distance
+    d.nf_hl = w.T / pl.nos / w.ell * (pl.kernel == ADDK_MATERN32 ? std::sqrt(3.0) : 1.0);
     for (int j = 0; j <= kNearQ; ++j) {
         d.nf_a[j] = w.nf_a[j];
         d.nf_ad[j] = w.nf_ad[j];
@@ -783,7 +824,7 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         w.nf_Lf = near_fold_width(L, w.ell);
     w.T = w.nf ? kNearFold * w.nf_Lf : torus_period(pl.kernel, L, w.ell, pl.n, pl.flags & ADDK_TORUS_PAPER, dmax);
     if (w.nf)
-        near_setup(w, pl.n);
+        near_setup(w, pl.kernel, pl.n);
     w.eta = M_PI * pl.n * w.ell / (std::sqrt(2.0) * w.T);
     if (w.eta < 1.0 && !(pl.flags & ADDK_NO_ACCURACY_CHECK))
         return fail(ADDK_ERR_ACCURACY, "window length scale too small for the grid: eta = pi n l / (sqrt2 T) = " +
@@ -1014,7 +1055,8 @@ const char *addk_version(void) { return "addk 0.1 (gfx950)"; }
 
 addk_status addk_torus_period(int32_t kernel, double L, double ell, int32_t n, uint32_t rule, int32_t dmax, double *T)
 {
-    if (!T || !(L >= 0.0) || !(ell > 0.0) || n < 2 || dmax < 1 || (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12))
+    if (!T || !(L >= 0.0) || !(ell > 0.0) || n < 2 || dmax < 1 ||
+        (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12 && kernel != ADDK_MATERN32))
         return fail(ADDK_ERR_INVALID_ARG, "addk_torus_period: bad argument");
     *T = torus_period(kernel, L, ell, n, rule, dmax);
     return ADDK_OK;
@@ -1025,7 +1067,7 @@ addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, doubl
 {
     if (!n || !(L >= 0.0) || !std::isfinite(L) || !(ell > 0.0) || !std::isfinite(ell) || m < 2 || m > kMaxW / 2 ||
         !(oversampling > 1.0) || !std::isfinite(oversampling) || !(tol > 0.0) ||
-        (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12))
+        (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12 && kernel != ADDK_MATERN32))
         return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n: bad argument");
     // Candidates: even n whose oversampled grid round(sigma n) is a power of two
     // in [16, 256] with room for the window; the first (smallest, cheapest) one
@@ -1054,6 +1096,90 @@ addk_status addk_choose_n(int32_t kernel, double L, double ell, int32_t m, doubl
                                        std::to_string(best_err) + "; increase m or l)");
 }
 
+addk_status addk_choose_n_windows(int32_t kernel, int64_t N, int32_t D, const double *X, int64_t ldx, int32_t P,
+                                  const int32_t *win_offsets, const int32_t *win_features, const double *ell,
+                                  int32_t m, double oversampling, double tol, int32_t *n, double *err_estimate,
+                                  void *stream)
+{
+    if (!n || N < 0 || D <= 0 || (N > 0 && (!X || ldx < D)) || P <= 0 || !win_offsets || !win_features || !ell ||
+        win_offsets[0] != 0)
+        return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n_windows: bad sizes or NULL pointers");
+    for (int w = 0; w < P; ++w) {
+        const int dw = win_offsets[w + 1] - win_offsets[w];
+        if (dw <= 0 || dw > 3)
+            return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n_windows: window dimensions must be 1..3");
+        for (int q = win_offsets[w]; q < win_offsets[w + 1]; ++q)
+            if (win_features[q] < 0 || win_features[q] >= D)
+                return fail(ADDK_ERR_INVALID_ARG, "addk_choose_n_windows: feature index out of range");
+    }
+    // per-feature ranges of the points (host loop, or one reduction kernel per
+    // window for device memory)
+    std::vector<double> L(P, 0.0);
+    if (N > 0) {
+        hipStream_t st = (hipStream_t)stream;
+        const bool dev = is_device_ptr(X);
+        for (int w = 0; w < P; ++w) {
+            const int dw = win_offsets[w + 1] - win_offsets[w];
+            int f[3] = {0, 0, 0};
+            for (int i = 0; i < dw; ++i)
+                f[i] = win_features[win_offsets[w] + i];
+            double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+            if (dev) {
+                const int nb = (int)std::min<int64_t>((N + 255) / 256, 512);
+                double *part = nullptr;
+                hipError_t e = hipMalloc(&part, nb * 6 * sizeof(double));
+                if (e != hipSuccess)
+                    return fail(ADDK_ERR_OOM, "allocation failed");
+                hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(256), 0, st, X, ldx, N, dw, f[0], f[1], f[2], part);
+                std::vector<double> hp(nb * 6);
+                e = hipMemcpyAsync(hp.data(), part, nb * 6 * sizeof(double), hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess)
+                    e = hipStreamSynchronize(st);
+                (void)hipFree(part);
+                if (e != hipSuccess)
+                    return hip_fail(e, "feature ranges");
+                for (int i = 0; i < dw; ++i)
+                    for (int b = 0; b < nb; ++b) {
+                        mn[i] = std::min(mn[i], hp[b * 6 + i]);
+                        mx[i] = std::max(mx[i], hp[b * 6 + 3 + i]);
+                    }
+            } else {
+                for (int64_t j = 0; j < N; ++j)
+                    for (int i = 0; i < dw; ++i) {
+                        const double x = X[j * ldx + f[i]];
+                        mn[i] = std::min(mn[i], x);
+                        mx[i] = std::max(mx[i], x);
+                    }
+            }
+            for (int i = 0; i < dw; ++i) {
+                if (!std::isfinite(mn[i]) || !std::isfinite(mx[i]))
+                    return fail(ADDK_ERR_INVALID_ARG, "point coordinates must be finite");
+                L[w] = std::max(L[w], mx[i] - mn[i]);
+            }
+        }
+    }
+    // the plan's bandwidth is the largest per-window choice; its estimate is the
+    // largest per-window estimate at that bandwidth
+    int32_t best = 0;
+    for (int w = 0; w < P; ++w) {
+        int32_t nw = 0;
+        addk_status s = addk_choose_n(kernel, L[w], ell[w], m, oversampling, tol, &nw, nullptr);
+        if (s != ADDK_OK)
+            return s;
+        best = std::max(best, nw);
+    }
+    const long nos = std::lround(oversampling * best);
+    double est = 0.0;
+    for (int w = 0; w < P; ++w) {
+        const double T = torus_period(kernel, L[w], ell[w], best, 0, 1);
+        est = std::max(est, error_estimate(kernel, L[w], T, ell[w], best, m, (double)nos / best));
+    }
+    *n = best;
+    if (err_estimate)
+        *err_estimate = est;
+    return ADDK_OK;
+}
+
 addk_status addk_window_ft(int32_t m, int32_t n_os, double oversampling, double k, double *value)
 {
     if (!value || m < 1 || n_os < 2 || !(oversampling > 1.0))
@@ -1074,16 +1200,16 @@ static addk_status plan_create_impl(addk_plan *out, int64_t N, int64_t nsrc, boo
     if (N < 0 || N > INT32_MAX || D <= 0 || (N > 0 && (!X || ldx < D)) || P <= 0 || !win_offsets || !win_features ||
         !ell || !sigma)
         return fail(ADDK_ERR_INVALID_ARG, "bad sizes or NULL pointers");
-    if (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12)
-        return fail(ADDK_ERR_INVALID_ARG, "kernel must be ADDK_GAUSSIAN or ADDK_MATERN12");
+    if (kernel != ADDK_GAUSSIAN && kernel != ADDK_MATERN12 && kernel != ADDK_MATERN32)
+        return fail(ADDK_ERR_INVALID_ARG, "kernel must be ADDK_GAUSSIAN, ADDK_MATERN12 or ADDK_MATERN32");
     if (precision != ADDK_FP64 && precision != ADDK_FP32)
         return fail(ADDK_ERR_INVALID_ARG, "precision must be ADDK_FP64 or ADDK_FP32");
     if (flags & ~(ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER | ADDK_NO_ACCURACY_CHECK | ADDK_TILE_KERNELS_ONLY |
                   ADDK_VECTOR_ALU_ONLY | ADDK_NEAR_FIELD))
         return fail(ADDK_ERR_INVALID_ARG, "unknown flags");
     if (flags & ADDK_NEAR_FIELD) {
-        if (kernel != ADDK_MATERN12)
-            return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD applies to the Matern-1/2 kernel only");
+        if (kernel != ADDK_MATERN12 && kernel != ADDK_MATERN32)
+            return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD applies to the Matern kernels only");
         if (flags & (ADDK_COEF_SAMPLED | ADDK_TORUS_PAPER))
             return fail(ADDK_ERR_UNSUPPORTED, "ADDK_NEAR_FIELD sets its own period and multipliers (no "
                                               "ADDK_COEF_SAMPLED / ADDK_TORUS_PAPER)");
@@ -1281,7 +1407,7 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
         pl.wins[w].sigma = sigma[w];
         pl.wins[w].eta = M_PI * pl.n * ell[w] / (std::sqrt(2.0) * pl.wins[w].T);
         if (pl.wins[w].nf)
-            near_setup(pl.wins[w], pl.n);  // T and the radius stay, the polynomials follow l
+            near_setup(pl.wins[w], pl.kernel, pl.n);  // T and the radius stay, the polynomials follow l
     }
     addk_status s = plan_compute_multipliers(pl, (hipStream_t)stream);
     if (s != ADDK_OK)
@@ -1293,6 +1419,7 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
         d.dsig = 2.0 * sigma[w];
         fill_near(pl, pl.wins[w], d);
     }
+    ++pl.param_gen;
     pl.eng.dirty = true;
     return engine_upload(pl.eng);
 }

@@ -24,6 +24,7 @@ import numpy as np
 
 GAUSSIAN = 1
 MATERN12 = 3
+MATERN32 = 5
 
 
 @dataclasses.dataclass
@@ -157,3 +158,13 @@ def small_problem(N: int, D: int, windows: List[List[int]], seed: int, R: int = 
     ell_a = np.asarray(ell if ell is not None else rng.uniform(0.08, 0.3, size=P), dtype=np.float64)
     sig_a = np.asarray(sigma if sigma is not None else rng.uniform(0.5, 1.5, size=P), dtype=np.float64)
     return Problem("small_N%d_D%d_s%d" % (N, D, seed), X, V, windows, ell_a, sig_a, kernel, n=n, m=m)
+
+
+def derivative_c3_rhs(N: int = 100000, R: int = 8, seed: int = 17346) -> np.ndarray:
+    """R right-hand sides for the derivative workload: column 0 is that
+    workload's own v (seed 17343), the others N(0,1) from ``seed``."""
+    v0 = derivative_c3(N=N).V
+    if R == 1:
+        return v0.copy()
+    rng = np.random.default_rng(seed)
+    return np.concatenate([v0, rng.standard_normal(size=(N, R - 1))], axis=1)
