@@ -156,3 +156,23 @@ def test_near_field_flag_is_validated_before_any_device_work():
     assert create(L.ADDK_MATERN12, 8, nf) == L.ADDK_ERR_UNSUPPORTED
     assert create(L.ADDK_MATERN12, 32, 1 << 20) == L.ADDK_ERR_INVALID_ARG
     assert lib.addk_stage_name(L.ADDK_NSTAGES - 1).decode() == "near"
+
+
+def test_choose_n_windows_is_the_largest_window_choice():
+    """addk_choose_n_windows over a plan's windows (host points): the largest of
+    the per-window choices, with the window extent taken as the largest
+    per-feature range of its points."""
+    import paper_2404_17344_amd as A
+    _lib()
+    rng = np.random.default_rng(6)
+    X = np.concatenate([rng.uniform(-0.25, 0.25, (400, 3)), rng.uniform(-0.1, 0.1, (400, 2)),
+                        rng.uniform(-0.05, 0.3, (400, 1))], axis=1)
+    wins = [[0, 1, 2], [3, 4], [5]]
+    ell = [0.08, 0.05, 0.2]
+    per = []
+    for w, f in enumerate(wins):
+        L = float((X[:, f].max(axis=0) - X[:, f].min(axis=0)).max())
+        per.append(A.choose_n(F.GAUSSIAN, L, ell[w], m=6, oversampling=2.0, tol=1e-6))
+    n, est = A.choose_n_for(X, wins, ell, m=6, tol=1e-6, with_estimate=True)
+    assert n == max(q[0] for q in per)
+    assert est <= 1e-6 and est >= max(q[1] for q in per if q[0] == n) * (1 - 1e-12)

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from _parity import relerr
 from oracle import fourier as F
 from oracle.direct import oracle_direct, oracle_vjp
 
@@ -25,12 +26,6 @@ def A():
     return A
 
 
-def relerr(a, b):
-    a = np.asarray(a).reshape(len(a), -1)
-    b = np.asarray(b).reshape(len(b), -1)
-    return max(np.linalg.norm(a[:, r] - b[:, r]) / np.linalg.norm(b[:, r]) for r in range(b.shape[1]))
-
-
 def make_plan(A, p, precision="fp64", **kw):
     return A.Plan(p.X, p.windows, p.ell, p.sigma, kernel=p.kernel, n=p.n, m=p.m, oversampling=p.oversampling,
                   precision=precision, **kw)
@@ -44,7 +39,7 @@ MIXED = [[0, 1, 2], [3, 4], [5]]
 
 
 @pytest.mark.parametrize("R", [1, 3, 4, 5])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_dmatvec_gaussian_vs_direct(A, prec, tol, R):
     """R <= 4 combines row by row, R = 5 through the 16-RHS tiles."""
     p = WL.small_problem(800, 6, MIXED, seed=201, R=R, n=32, m=6)
@@ -68,7 +63,7 @@ def test_dmatvec_matern_vs_trigonometric_sum(A, coef):
                                      want_derivs=True)
     assert relerr(Y.cpu().numpy(), Yt) < 1e-10
     for w in range(p.P):
-        assert relerr(dl[w].cpu().numpy(), dlt[w]) < 1e-9
+        assert relerr(dl[w].cpu().numpy(), dlt[w]) < 1e-10
         assert relerr(ds[w].cpu().numpy(), dst[w]) < 1e-10
 
 
@@ -114,7 +109,7 @@ def test_derivative_is_fd_of_fast_operator(A):
     plan.update_params(p.ell, p.sigma)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
 def test_vjp_vs_oracle(A, prec, tol):
     p = WL.small_problem(700, 6, MIXED, seed=204, R=3, n=32, m=6)
     G = np.random.default_rng(205).standard_normal(p.V.shape)
@@ -122,8 +117,10 @@ def test_vjp_vs_oracle(A, prec, tol):
     gV, gl, gs = make_plan(A, p, prec).vjp(cuda(p.V), cuda(G))
     gVo, glo, gso = oracle_vjp(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, G)
     assert relerr(gV.cpu().numpy(), gVo) < tol
-    np.testing.assert_allclose(gl.cpu().numpy(), glo, rtol=tol * 10)
-    np.testing.assert_allclose(gs.cpu().numpy(), gso, rtol=tol * 10)
+    print("vjp %s: grad_ell rel %s grad_sigma rel %s" % (prec, np.abs(gl.cpu().numpy() / glo - 1),
+                                                        np.abs(gs.cpu().numpy() / gso - 1)))
+    np.testing.assert_allclose(gl.cpu().numpy(), glo, rtol=tol)
+    np.testing.assert_allclose(gs.cpu().numpy(), gso, rtol=tol)
 
 
 def test_vjp_scalars_equal_interpolation_inner_products(A):

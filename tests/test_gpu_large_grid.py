@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from _parity import relerr
 from oracle import fourier as F
 from oracle.direct import oracle_direct
 
@@ -27,12 +28,6 @@ def A():
         pytest.skip("no GPU")
     import paper_2404_17344_amd as A
     return A
-
-
-def relerr(a, b):
-    a = np.asarray(a).reshape(len(a), -1)
-    b = np.asarray(b).reshape(len(b), -1)
-    return max(np.linalg.norm(a[:, r] - b[:, r]) / np.linalg.norm(b[:, r]) for r in range(b.shape[1]))
 
 
 def cuda(a):
@@ -67,7 +62,7 @@ def test_d3_small_length_scale_vs_direct(A, prec, tol):
     Yo, dlo, _ = oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=rows, want_derivs=True)
     assert relerr(Y.cpu().numpy()[rows], Yo) < tol
     for w in range(2):
-        assert relerr(dl[w].cpu().numpy()[rows], dlo[w]) < (10 * tol if prec == "fp64" else tol)
+        assert relerr(dl[w].cpu().numpy()[rows], dlo[w]) < tol
 
 
 def test_batch_mixing_grid_sizes(A):

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
+from _parity import relerr
 from oracle import nearfield as NF
 from oracle.direct import oracle_direct, oracle_vjp
 
@@ -28,12 +29,6 @@ def A():
         pytest.skip("no GPU")
     import paper_2404_17344_amd as A
     return A
-
-
-def relerr(a, b):
-    a = np.asarray(a).reshape(len(a), -1)
-    b = np.asarray(b).reshape(len(b), -1)
-    return max(np.linalg.norm(a[:, r] - b[:, r]) / np.linalg.norm(b[:, r]) for r in range(b.shape[1]))
 
 
 def cuda(a):
