@@ -504,3 +504,68 @@ def test_gsi_indices_sum_to_one_and_follow_the_data():
     assert sum(rho.values()) == pytest.approx(1.0, rel=1e-12)
     assert set(rho) == {(0,), (1,), (0, 1), (2,), (3,), (2, 3)}
     assert all(r >= 0 for r in rho.values())
+
+
+# ------------------------------------------- the bound components, one by one
+#
+# Each component of the Theorem 1/2 bounds bounds a specific quantity of the
+# one-dimensional truncated functions f(x) = e^{-x^2/2l^2} and
+# g(x) = x^2/(2 l^2) f(x) on [-1/2, 1/2] (Theorem 1 and 2 proofs):
+#   gamma >= |c_{m/2}(f)|,  A >= sum_{k > m/2} |c_k(f)|,
+#   xi    >= |c_{m/2}(g)|,  S >= sum_{k > m/2} |c_k(g)|.
+# The coefficients here come from adaptive quadrature of their defining
+# integrals (independent of every formula in the oracle).  Where e^{-1/8l^2}
+# is negligible the coefficients are the sampled continuous transforms, so
+# gamma and xi are then tight: their leading terms must equal the quadrature
+# value up to the one-sided term of xi, (eta^2 + 1/2) / (eta^2 - 1/2).  A
+# wrong constant in a leading term fails the tightness check; one in a tail
+# term fails the bound check in the regime where that term dominates.
+
+
+def _quad_coeff(fun, k):
+    """int_{-1/2}^{1/2} fun(x) cos(2 pi k x) dx (fun even), by QUADPACK's
+    oscillatory rule."""
+    if k == 0:
+        return integrate.quad(fun, -0.5, 0.5, limit=400, epsabs=1e-17, epsrel=1e-13)[0]
+    return integrate.quad(fun, -0.5, 0.5, weight="cos", wvar=2 * math.pi * k, limit=400, epsabs=1e-18)[0]
+
+
+def _fg(ell):
+    f = lambda x: math.exp(-x * x / (2 * ell * ell))  # noqa: E731
+    g = lambda x: x * x / (2 * ell * ell) * math.exp(-x * x / (2 * ell * ell))  # noqa: E731
+    return f, g
+
+
+@pytest.mark.parametrize("ell,n", [(0.05, 10), (0.05, 16), (0.08, 12), (0.2, 8), (0.3, 16), (0.45, 8),
+                                   (0.6, 6), (1.0, 8), (2.0, 4)])
+def test_bound_components_bound_their_quantities(ell, n):
+    et = F.eta(ell, n)
+    if et < 1:
+        pytest.skip("eta < 1")
+    f, g = _fg(ell)
+    cf = abs(_quad_coeff(f, n // 2))
+    cg = abs(_quad_coeff(g, n // 2))
+    kmax = n // 2 + 400
+    tf = sum(abs(_quad_coeff(f, k)) for k in range(n // 2 + 1, kmax))
+    tg = sum(abs(_quad_coeff(g, k)) for k in range(n // 2 + 1, kmax))
+    assert cf <= F.gamma_bound(et, ell) * (1 + 1e-9)
+    assert tf <= F.A_bound(et, ell) * (1 + 1e-9)
+    assert cg <= F.xi_bound(et, ell) * (1 + 1e-9)
+    assert tg <= F.S_bound(et, ell) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("ell,n", [(0.05, 10), (0.05, 14), (0.06, 12), (0.04, 16)])
+def test_bound_components_tight_where_the_gaussian_term_dominates(ell, n):
+    et = F.eta(ell, n)
+    lead = ell * math.sqrt(2 * math.pi) * math.exp(-et ** 2)
+    assert et >= 1 and math.exp(-1 / (8 * ell * ell)) < 1e-12 * lead
+    f, g = _fg(ell)
+    cf = abs(_quad_coeff(f, n // 2))
+    cg = abs(_quad_coeff(g, n // 2))
+    assert F.gamma_bound(et, ell) / cf == pytest.approx(1.0, abs=1e-8)
+    assert F.xi_bound(et, ell) / cg == pytest.approx((et ** 2 + 0.5) / (et ** 2 - 0.5), rel=1e-8)
+    # the tails: within the integral comparison's slack (a few terms' worth)
+    tf = sum(abs(_quad_coeff(f, k)) for k in range(n // 2 + 1, n // 2 + 60))
+    tg = sum(abs(_quad_coeff(g, k)) for k in range(n // 2 + 1, n // 2 + 60))
+    assert 1.0 <= F.A_bound(et, ell) / tf < 4.0
+    assert 1.0 <= F.S_bound(et, ell) / tg < 8.0
