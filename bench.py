@@ -18,6 +18,19 @@ Printed as one JSON line, with
   cpu_baseline : the FP64 CPU oracle timed on a bounded sample of output rows,
   accuracy     : FP32 result vs the FP64 GPU path and vs the oracle rows.
 
+Also in the line: ``rates`` (the joint rate and the K-only ``addk_matvec`` rate
+over the same steps) and ``stage_hbm`` (algorithmic bytes and HBM rate of the
+spread, interpolation and window-sum kernels).
+
+``--workload d1``: the same points with each of the 15 features its own d = 1
+window (12 taps per point and window), where spreading and interpolation move
+more bytes than they compute on; its roofline is the dominant kernel's
+algorithmic HBM rate against the 8 TB/s peak.
+
+``--workload batched``: 64 uneven problems (N log-uniform in [5e3, 2e5], 1-5
+windows of d in {1, 2, 3}, 8 RHS, FP32, m = 4) replayed as one autotuned
+hipGraph.
+
 ``--workload matern-near-field`` measures the near-field corrected Matern-1/2
 product instead: the derivative workload's shape (N = 1e5 points, D = 9 N(0,1)
 features min-max scaled, 3 windows d = 3, l = (0.05, 0.1, 0.2), R = 1, n = 64,
@@ -43,9 +56,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "kernel matvecs/s and ∂K/∂ℓ matvecs/s at N=1e6, 5×d=3 windows, at rel err ≤1e-5"
+METRIC_D1 = "kernel matvecs/s and ∂K/∂ℓ matvecs/s at N=1e6, 15×d=1 windows, at rel err ≤1e-5"
 METRIC_MATERN = "Matérn-1/2 kernel matvecs/s and ∂K/∂ℓ, ∂K/∂σ matvecs/s at N=1e5, 3×d=3 windows, at rel err ≤1e-5"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_BPS = 8.0e12
 
 
 def relerr_cols(a: np.ndarray, b: np.ndarray) -> float:
@@ -65,11 +80,12 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(stage: str):
-    """HBM bytes per launch of a stage's kernel, from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
-    None when the summary is missing or the device sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "c5_dmatvec_hbm_traffic.txt")
+def measured_traffic(stage: str, fname: str = "c5_dmatvec_hbm_traffic.txt"):
+    """HBM bytes per launch of a stage's kernel, from a committed rocprofv3 counter
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when the summary is missing or the device sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     digest, table = None, {}
@@ -101,7 +117,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration) and exit")
-    ap.add_argument("--workload", choices=["large", "matern-near-field"], default="large")
+    ap.add_argument("--workload", choices=["large", "d1", "batched", "matern-near-field"], default="large")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="engine precision (FP32: FP32 grids with FP64 multipliers and sums; FP64: every step)")
     ap.add_argument("--n", type=int, default=64, help="bandwidth of the matern-near-field workload")
@@ -110,7 +126,7 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested; run with --gpus 1)" % args.gpus, flush=True)
-        sys.exit(0)
+        sys.exit(2)
 
     import torch
 
@@ -132,15 +148,55 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "matern-near-field":
         return matern_main(args, A, WL, torch)
+    if args.workload == "batched":
+        return batched_main(args, A, WL, torch)
+    return additive_main(args, A, WL, torch)
+
+
+def stage_hbm(stages, q, d, R, P, N, rs, nout, traffic_file):
+    """Per-stage HBM rates of the spread, interpolation and window-sum kernels.
+
+    Algorithmic bytes per launch (the point side; the grid boxes, at most a few
+    percent at these sizes, are left out, so these are lower bounds):
+      spread (tile or dense-cell):  pairs x (d coordinates + R RHS values) x rs
+      interp (tile or dense-cell):  pairs x (d x rs + nout x R x 8) (FP64 products written)
+      combine:                      nout P N R x 8 read + (1 + P) N R x 8 written
+    with rs the engine's real size and pairs the point-window pairs each kernel
+    handles.  "measured" is the counter-based traffic where a summary exists."""
+    pairs = {"spread": q["tile_points"], "spread_dense": q["dense_points"], "interp": q["tile_points"],
+             "interp_dense": q["dense_points"]}
+    alg = {k: pairs[k] * (d + R) * rs for k in ("spread", "spread_dense")}
+    alg.update({k: pairs[k] * (d * rs + nout * R * 8) for k in ("interp", "interp_dense")})
+    alg["combine"] = (nout * P + 1 + P) * N * R * 8
+    out = {}
+    for k, b in alg.items():
+        if stages.get(k, (0, 0))[1] == 0:
+            continue
+        ms = stages[k][0] / stages[k][1]
+        e = {"algorithmic_bytes": int(b), "avg_launch_ms": round(ms, 4),
+             "GBps": round(b / (ms * 1e-3) / 1e9, 1), "frac_of_hbm_peak": round(b / (ms * 1e-3) / HBM_PEAK_BPS, 4)}
+        t = measured_traffic(k, traffic_file)
+        if t is not None:
+            e["measured_bytes"] = int(t["bytes"])
+            e["measured_GBps"] = round(t["bytes"] / (ms * 1e-3) / 1e9, 1)
+        out[k] = e
+    return out
+
+
+def additive_main(args, A, WL, torch):
+    """The large workloads: five d = 3 windows (default) or fifteen d = 1 windows."""
     dev = torch.device("cuda:0")
+    d1 = args.workload == "d1"
     log("generating inputs")
-    p = WL.large_c5(N=args.N)
+    p = WL.large_d1(N=args.N) if d1 else WL.large_c5(N=args.N)
     N, R, P, W = p.N, p.R, p.P, 2 * p.m
+    d = len(p.windows[0])
     # column-major N x R, the layout the library takes: no copy inside the step
     V = torch.from_numpy(np.ascontiguousarray(p.V.T)).to(dev).t()
     torch.cuda.synchronize()
 
     fp64 = args.precision == "fp64"
+    rs = 8 if fp64 else 4
     log("plan (%s)" % args.precision)
     t0 = time.perf_counter()
     plan = A.Plan(p.X, p.windows, p.ell, p.sigma, n=p.n, m=p.m, oversampling=p.oversampling, precision=args.precision)
@@ -171,31 +227,61 @@ def main():
     plan.profile(False)
     value = R / (ms_per_step * 1e-3)
 
+    # K V alone (addk_matvec): the same number of steps after the derivative run
+    log("timing %d K-only steps" % args.steps)
+    Yk = torch.empty((R, N), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.matvec(V, out=Yk)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.matvec(V, out=Yk)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_k = ev0.elapsed_time(ev1) / args.steps
+
     # Algorithmic FLOPs per launch: one FMA (2 flop) per tap, point-window pair and
     # RHS; interpolation launches produce two outputs (kernel and derivative kernel).
     # Dense-cell and tile kernels split the point-window pairs between them.
     q = plan.query()
-    taps = W ** 3
+    taps = W ** d
     pts = {"spread_dense": q["dense_points"], "spread": q["tile_points"],
            "interp_dense": q["dense_points"], "interp": q["tile_points"]}
     outs = {"spread_dense": 1, "spread": 1, "interp_dense": 2, "interp": 2}
     flops = {k: 2.0 * taps * pts[k] * R * outs[k] for k in pts}
-    cand = [k for k in flops if stages[k][1] > 0]
-    dom = max(cand, key=lambda s: stages[s][0])
-    tot_ms, launches = stages[dom]
-    avg_ms = tot_ms / max(launches, 1)
-    achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+    traffic_file = "d1_dmatvec_hbm_traffic.txt" if d1 else "c5_dmatvec_hbm_traffic.txt"
+    hbm = stage_hbm(stages, q, d, R, P, N, rs, 2, traffic_file)
     peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(dom) if N == 1000000 and not fp64 else None,
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops[dom],
-                "point_window_pairs": pts[dom]}
+    full = N == 1000000 and not fp64
+    if d1:
+        # 12 taps per point and window: the spread and interpolation kernels are
+        # bound by the bytes they move; the dominant one by time is reported
+        # against the HBM peak
+        cand = [k for k in hbm if k != "combine"]
+        dom = max(cand, key=lambda s: stages[s][0])
+        e = hbm[dom]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": e["GBps"], "peak": HBM_PEAK_BPS / 1e9,
+                    "unit": "GB/s", "frac": e["frac_of_hbm_peak"],
+                    "traffic": measured_traffic(dom, traffic_file) if full else None,
+                    "avg_launch_ms": e["avg_launch_ms"], "algorithmic_bytes_per_launch": e["algorithmic_bytes"],
+                    "point_window_pairs": pts[dom]}
+    else:
+        cand = [k for k in flops if stages[k][1] > 0]
+        dom = max(cand, key=lambda s: stages[s][0])
+        tot_ms, launches = stages[dom]
+        avg_ms = tot_ms / max(launches, 1)
+        achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": measured_traffic(dom, traffic_file) if full else None,
+                    "avg_launch_ms": round(avg_ms, 4), "algorithmic_flop_per_launch": flops[dom],
+                    "point_window_pairs": pts[dom]}
     stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
 
     accuracy = {}
     Y32 = out[0].cpu().numpy()   # the timed path's outputs (FP64 values in either mode)
     dl32 = out[1].cpu().numpy()
+    accuracy["rel_err_K_only_vs_dmatvec_Y"] = relerr_cols(Yk.t().cpu().numpy(), Y32)
     if not args.no_accuracy and not fp64:
         log("fp64 reference run")
         del out
@@ -211,7 +297,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.direct import oracle_direct, oracle_threads
-        rng = np.random.default_rng(17345)
+        rng = np.random.default_rng(17347 if d1 else 17345)
         log("cpu baseline (oracle)")
         probe = rng.choice(N, 64, replace=False)
         oracle_direct(p.X, p.windows, p.kernel, p.ell, p.sigma, p.V, rows=probe[:8], want_derivs=True)  # threads up
@@ -225,15 +311,23 @@ def main():
         t_cpu = time.perf_counter() - t0
         cpu = {"value": round(R * (nrows / N) / t_cpu, 6), "unit": "matvecs/s", "cores": oracle_threads(),
                "kind": "oracle",
-               "sample": "%d of %d output rows, all 5 windows, 16 RHS, K v and dK/dl_w v, FP64 direct sums; "
-                         "%.1f s; rate scaled by N/rows" % (nrows, N, t_cpu)}
+               "sample": "%d of %d output rows, all %d windows, %d RHS, K v and dK/dl_w v, FP64 direct sums; "
+                         "%.1f s; rate scaled by N/rows" % (nrows, N, P, R, t_cpu)}
         if not args.no_accuracy:
             accuracy["rel_err_Y_vs_oracle_rows"] = relerr_cols(Y32[rows], Yo)
             accuracy["rel_err_dY_dell_vs_oracle_rows"] = max(relerr_cols(dl32[w][rows], dlo[w]) for w in range(P))
             accuracy["oracle_rows"] = nrows
 
+    if d1:
+        metric = METRIC_D1
+        wl = ("large additive Gaussian, d=1 windows: N=%d, D=15 N(0,1) features min-max scaled, 15 windows d=1, "
+              "l=0.1, sigma=1, R=16, n=64, m=6, oversampling 2" % N)
+    else:
+        metric = METRIC
+        wl = ("large additive Gaussian: N=%d, D=15 N(0,1) features min-max scaled, 5 windows d=3, "
+              "l=0.1, sigma=1, R=16, n=64, m=6, oversampling 2" % N)
     result = {
-        "metric": METRIC,
+        "metric": metric,
         "value": round(value, 3),
         "unit": "matvecs/s",
         "n_gpus": 1,
@@ -245,16 +339,70 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "large additive Gaussian: N=%d, D=15 N(0,1) features min-max scaled, 5 windows d=3, "
-                               "l=0.1, sigma=1, R=16, n=64, m=6, oversampling 2" % N,
-                   "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "oversampling": p.oversampling,
+        "config": {"workload": wl, "N": N, "R": R, "P": P, "n": p.n, "m": p.m, "oversampling": p.oversampling,
                    "step": "addk_dmatvec: K V and dK/dl_w V, all windows",
                    "precision": "FP64 every step" if fp64 else
-                                "FP32 spread/FFT/interp, FP64 multipliers and window sums"},
+                                "FP32 spread/FFT/interp with FP64-computed multipliers applied in FP32; "
+                                "FP64 window sums and outputs"},
+        "rates": {"K_and_dK_dl_matvecs_per_s": round(value, 3),
+                  "K_only_matvecs_per_s": round(R / (ms_k * 1e-3), 3), "K_only_ms_per_step": round(ms_k, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "stage_avg_ms": stage_ms,
+        "stage_hbm": hbm,
+        "plan_ms": round(plan_ms, 2),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def batched_main(args, A, WL, torch):
+    """The batched workload: 64 independent problems (N log-uniform in [5e3, 2e5],
+    1-5 windows of d in {1, 2, 3}, Gaussian l ~ U(0.05, 0.3), 8 RHS each, FP32,
+    m = 4, n per problem from the error model at 1e-5) replayed as one autotuned
+    hipGraph.  value = problem right-hand sides delivered per second (one
+    matvec = one RHS of one problem through all its windows)."""
+    probs = WL.batched_c4()
+    R = probs[0].R
+    log("batched: %d problems, %d points" % (len(probs), sum(p.N for p in probs)))
+    plans = []
+    t0 = time.perf_counter()
+    for p in probs:
+        n = A.choose_n_for(p.X, p.windows, p.ell, m=4, oversampling=2.0, tol=1e-5)
+        plans.append(A.Plan(p.X, p.windows, p.ell, p.sigma, n=n, m=4, precision="fp32"))
+    B = A.Batch(plans, R=R)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    B.set_inputs([torch.from_numpy(np.ascontiguousarray(p.V)).cuda() for p in probs])
+    knobs = B.autotune(reps=3)
+    for _ in range(args.warmup):
+        B.launch()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        B.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    ev0.record()
+    for _ in range(args.steps):
+        B.run_eager()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_eager = ev0.elapsed_time(ev1) / args.steps
+    nmat = len(probs) * R
+    result = {
+        "metric": "batched problem matvecs/s (64 uneven problems, 8 RHS, one hipGraph replay)",
+        "value": round(nmat / (ms * 1e-3), 3), "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched: 64 problems, N log-uniform in [5e3, 2e5], 1-5 windows of d in {1,2,3}, "
+                               "l ~ U(0.05, 0.3), R=8, m=4, n per problem at 1e-5, FP32",
+                   "problems": len(probs), "points": int(sum(p.N for p in probs)),
+                   "windows": int(sum(p.P for p in probs)), "R": R, "knobs": knobs},
+        "eager_ms_per_step": round(ms_eager, 4),
         "plan_ms": round(plan_ms, 2),
     }
     print(json.dumps(result), flush=True)

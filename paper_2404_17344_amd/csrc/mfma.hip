@@ -55,9 +55,15 @@ __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return 
 // Products of one z-slab for NG point groups and NO outputs (kernel and
 // derivative-kernel grids).  One A fragment (the weights of 16 points at 4
 // taps) feeds NO MFMAs and one B fragment (16 RHS at 4 taps) feeds NG MFMAs;
-// the NG * NO accumulator chains are independent.
+// the NG * NO accumulator chains are independent.  With one output, NA = 2
+// accumulators per group take the even and odd y rows, so that there are
+// still 2 NG independent chains to cover the matrix op's latency (they are
+// summed at the end).
+template <int NO>
+constexpr int acc_rows() { return NO == 1 ? 2 : NO; }
+
 template <int SW, int NT, int SX, int NG, int NO>
-__device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&wxq)[NG][NT], const float *wyl,
+__device__ __forceinline__ void slab_products(f4 (&acc)[acc_rows<NO>()][NG], const float (&wxq)[NG][NT], const float *wyl,
                                               const float (&wz)[NG], const bool (&live)[NG], const float (*sl)[16],
                                               int ny, int q, int mrow)
 {
@@ -82,8 +88,10 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
                     continue;
                 const float a = wyz[g] * wxq[g][t];
 #pragma unroll
-                for (int o = 0; o < NO; ++o)
-                    acc[o][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[o], acc[o][g], 0, 0, 0);
+                for (int o = 0; o < NO; ++o) {
+                    const int ai = NO == 1 ? (oy & 1) : o;
+                    acc[ai][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[o], acc[ai][g], 0, 0, 0);
+                }
             }
         }
     }
@@ -98,7 +106,8 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[NO][NG], const float (&w
 // barriers inside match.
 template <int SW, int SX, int NT, int NG, int NO, int NB = 2>
 __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
-                                             int y0, int z0, int sx, int sy, int nz, f4 (&acc)[NO][NG],
+                                             int y0, int z0, int sx, int sy, int nz,
+                                             f4 (&acc)[acc_rows<NO>()][NG],
                                              const float (&wxq)[NG][NT], const float *wyl,
                                              const float (&uzr)[NG], const int (&lbz)[NG], bool zmask)
 {
@@ -208,9 +217,10 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    f4 acc[NO][NG];
+    constexpr int NA = acc_rows<NO>();
+    f4 acc[NA][NG];
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
+    for (int o = 0; o < NA; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
@@ -219,6 +229,10 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
     // is applied in this FP32 kernel; a group whose points all lie in one of
     // the cells skips its outside slab altogether.
     stream_slabs<W, W, NT, NG, NO, 1>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
+    if (NO == 1)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            acc[0][g] += acc[NA - 1][g];
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -363,12 +377,12 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma_z1(const WinDev *__restr
 // the dispatch below is a uniform branch and every wave runs the same slab
 // loop (and barriers).
 template <int W, int NO>
-__global__ __launch_bounds__(kBlock, NO == 2 ? 5 : 1) void k_interp_mfma(const WinDev *__restrict__ wins,
-                                                                         const Chunk *__restrict__ items, int R)
+__global__ __launch_bounds__(kBlock, 5) void k_interp_mfma(const WinDev *__restrict__ wins,
+                                                          const Chunk *__restrict__ items, int R)
 {
     // one slab buffer (31 KB of LDS with the y weights at 2m = 12, two outputs)
-    // and, with two outputs, at most 96 registers (a few spills at the slab
-    // barriers): five blocks per CU
+    // and at most 96 registers (a few spills at the slab barriers): five blocks
+    // per CU
     __shared__ __align__(16) float slab[1][NO][W * W][16];
     __shared__ __align__(16) float wy_lds[4 * 4 * W * 16];
     const Chunk it = items[blockIdx.x];
@@ -933,14 +947,19 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    f4 acc[NO][NG];
+    constexpr int NA = acc_rows<NO>();
+    f4 acc[NA][NG];
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
+    for (int o = 0; o < NA; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
     stream_slabs<SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz, lbz,
                                        true);
+    if (NO == 1)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            acc[0][g] += acc[NA - 1][g];
     if (mrow >= nr)
         return;
 #pragma unroll
@@ -961,11 +980,11 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
 // cells of the tile) against the tile's (4 + 2m - 1)^3 sub-grid, taken as one
 // super-cell with x padded to 16; weights outside a point's support are zero.
 template <int W, int NO>
-__global__ __launch_bounds__(kBlock, NO == 2 ? 3 : 1) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
-                                                                              const Chunk *__restrict__ chunks, int R)
+__global__ __launch_bounds__(kBlock, 3) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
+                                                               const Chunk *__restrict__ chunks, int R)
 {
     // one slab buffer (46 KB of LDS with the y weights at 2m = 12, two outputs)
-    // and, with two outputs, at most 168 registers: three blocks per CU
+    // and at most 168 registers: three blocks per CU
     __shared__ __align__(16) float slab[1][NO][(3 + W) * 16][16];
     __shared__ __align__(16) float wy_lds[4 * 4 * (3 + W) * 16];
     const Chunk ch = chunks[blockIdx.x];

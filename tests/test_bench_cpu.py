@@ -1,5 +1,5 @@
 """Host-side contract of bench.py (no GPU needed): more than one GPU is refused
-with a message and a zero exit status, before any device work."""
+with a message and a nonzero exit status, before any device work."""
 import os
 import subprocess
 import sys
@@ -10,6 +10,6 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_multi_gpu_request_exits_with_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
-    assert r.returncode == 0
+    assert r.returncode == 2
     assert "one GPU only" in r.stdout
     assert "--gpus 2" in r.stdout

@@ -211,6 +211,10 @@ def test_matrix_core_kernels_match_vector_kernels(A, m, R):
         assert relerr(a[0].cpu().numpy(), dl64[0].cpu().numpy()) < tol
     for a, b in [(Ym, Yv), (Ym, Yt), (dlm[0], dlv[0]), (dlm[0], dlt[0])]:
         assert relerr(a.cpu().numpy(), b.cpu().numpy()) < 0.6 * tol
+    # K V alone runs the one-output variants of the same kernels
+    Yk = pm.matvec(torch.from_numpy(V).cuda())
+    assert relerr(Yk.cpu().numpy(), Y64.cpu().numpy()) < tol
+    assert relerr(Yk.cpu().numpy(), Ym.cpu().numpy()) < 0.6 * tol
     rows = np.arange(0, X.shape[0], 61)
     Yo = oracle_direct(X, [[0, 1, 2]], WL.GAUSSIAN, [0.1], [1.0], V, rows=rows)
     assert relerr(Ym.cpu().numpy()[rows], Yo) < (1e-5 if m == 6 else 2e-5)

@@ -168,3 +168,15 @@ def derivative_c3_rhs(N: int = 100000, R: int = 8, seed: int = 17346) -> np.ndar
         return v0.copy()
     rng = np.random.default_rng(seed)
     return np.concatenate([v0, rng.standard_normal(size=(N, R - 1))], axis=1)
+
+
+def large_d1(N: int = 1000000, seed: int = 17347, R: int = 16, D: int = 15) -> Problem:
+    """The large workload's points with every feature its own d = 1 window:
+    N(0,1) features min-max scaled, l = 0.1, sigma_w = 1, n = 64, m = 6 (12 taps
+    per point and window: the spread and interpolation move more bytes than
+    they compute on)."""
+    rng = np.random.default_rng(seed)
+    X = minmax_quarter(rng.standard_normal(size=(N, D)))
+    V = rng.standard_normal(size=(N, R))
+    return Problem("large_%dxd1_N%d_R%d" % (D, N, R), X, V, consecutive_windows(D, 1),
+                   np.full(D, 0.1), np.ones(D), GAUSSIAN, n=64, m=6)
