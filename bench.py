@@ -159,15 +159,16 @@ def stage_hbm(stages, q, d, R, P, N, rs, nout, traffic_file):
     Algorithmic bytes per launch (the point side; the grid boxes, at most a few
     percent at these sizes, are left out, so these are lower bounds):
       spread (tile or dense-cell):  pairs x (d coordinates + R RHS values) x rs
-      interp (tile or dense-cell):  pairs x (d x rs + nout x R x 8) (FP64 products written)
-      combine:                      nout P N R x 8 read + (1 + P) N R x 8 written
+      interp (tile or dense-cell):  pairs x (d + nout x R) x rs (coordinates read,
+                                    per-window products written in the engine's precision)
+      combine:                      nout P N R x rs read + (1 + P) N R x 8 written (FP64)
     with rs the engine's real size and pairs the point-window pairs each kernel
     handles.  "measured" is the counter-based traffic where a summary exists."""
     pairs = {"spread": q["tile_points"], "spread_dense": q["dense_points"], "interp": q["tile_points"],
              "interp_dense": q["dense_points"]}
     alg = {k: pairs[k] * (d + R) * rs for k in ("spread", "spread_dense")}
-    alg.update({k: pairs[k] * (d * rs + nout * R * 8) for k in ("interp", "interp_dense")})
-    alg["combine"] = (nout * P + 1 + P) * N * R * 8
+    alg.update({k: pairs[k] * (d + nout * R) * rs for k in ("interp", "interp_dense")})
+    alg["combine"] = nout * P * N * R * rs + (1 + P) * N * R * 8
     out = {}
     for k, b in alg.items():
         if stages.get(k, (0, 0))[1] == 0:

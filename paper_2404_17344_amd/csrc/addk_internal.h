@@ -14,8 +14,9 @@
 //   A4  [o][pair][ez][ey][n1]         after the inverse y pass
 //   H   [o][pair][ez][ey][ex]         after the inverse x pass, read by interpolation
 //   Vp  [N][ceil16(Rcap)] (real)      the RHS, point-major, converted once per call
-//   Yw  [o][N][Rcap] (FP64)           per-window interpolated products, caller point
-//                                     order, point-major (one point's RHS contiguous)
+//   Yw  [o][N][Rcap] (real)           per-window interpolated products in the engine's
+//                                     precision, caller point order, point-major (one
+//                                     point's RHS contiguous); summed over windows in FP64
 // Lower-dimensional windows use the same arrays with unit extents.
 #pragma once
 
@@ -68,7 +69,7 @@ struct WinDev {
     const void *Bd;
     void *G, *A1, *A2, *A3, *A4, *H, *Gm, *Vm;  // workspace (complex interleaved)
     int64_t szG, szA1, szA2, szA3, szA4, szH, szM;  // complex elements per pair
-    double *Yw;     // [2][N][Rcap]
+    void *Yw;       // [2][N][Rcap], engine precision
     int64_t Rcap;
     int npair_cap;
     int nbase[3];        // base cells per dimension: ext - 2m + 1 (unit for unused dims)
@@ -200,7 +201,7 @@ struct Engine {
     int rb[4] = {0, 0, 0, 0};      // RHS per spread/interp pass per d (capacity)
     void *ws = nullptr;            // grid workspace
     int64_t ws_bytes = 0;
-    double *yw = nullptr;          // per-window FP64 products
+    void *yw = nullptr;            // per-window products (engine precision)
     int64_t yw_bytes = 0;
     void *d_tw = nullptr;          // twiddle tables for n_os = 16, 32, 64, 128 (engine precision)
     void *vpack = nullptr;         // point-major copies of the problems' V (see ProbDev::Vp)
@@ -262,7 +263,7 @@ addk_status hip_fail(hipError_t e, const char *what);
 addk_status engine_build_device(Engine &E, int device_precision);
 addk_status engine_ensure_workspace(Engine &E, int R);
 WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap);
-void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *nys, void *vpack, void *scr0,
+void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, void *yw, double *nys, void *vpack, void *scr0,
                     void *scr1);
 addk_status engine_run(Engine &E, int R, int nout, bool store_vmodes_only, bool store_gmodes,
                        IoArgs io, hipStream_t st);

@@ -314,11 +314,260 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
         }
     }
     const int orig = w.perm[j];
-    double *dst = w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+    real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
         if (i < nr)
-            dst[i] = (double)acc[i];
+            dst[i] = acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// d = 1, dense cells.  With 2m taps per point the work per point is small and
+// these kernels are bound by the bytes they move: the RHS rows of the spread
+// (a point-major row of 16 values, gathered through the permutation) and the
+// interpolated rows (written back through it).  Four lanes share a point, each
+// taking four of its 16 RHS, so that a point's row is one contiguous 64-byte
+// (FP32) access of the four lanes; each lane evaluates W/4 of the point's
+// window values and the four lanes exchange them within their quad.
+
+// value of lane (lane & ~3) + K, K = 0..3, within a quad (a DPP quad
+// permutation: a register move, no LDS)
+template <int K>
+__device__ __forceinline__ float quad_bcast(float v)
+{
+    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xf, 0xf, false));
+}
+
+template <int K>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+    const int2 b = *reinterpret_cast<int2 *>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_mov_dpp(b.x, ctrl, 0xf, 0xf, false);
+    r.y = __builtin_amdgcn_mov_dpp(b.y, ctrl, 0xf, 0xf, false);
+    return *reinterpret_cast<double *>(&r);
+}
+
+// the W window values of a quad's point, lane k of the quad holding values
+// k WQ .. k WQ + WQ - 1 in wq
+template <int W, typename real>
+__device__ __forceinline__ void quad_gather(const real (&wq)[W / 4], real (&wv)[W])
+{
+    constexpr int WQ = W / 4;
+#pragma unroll
+    for (int k = 0; k < WQ; ++k) {
+        wv[k] = quad_bcast<0>(wq[k]);
+        wv[WQ + k] = quad_bcast<1>(wq[k]);
+        wv[2 * WQ + k] = quad_bcast<2>(wq[k]);
+        wv[3 * WQ + k] = quad_bcast<3>(wq[k]);
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ void load4(const real *p, real (&v)[4])
+{
+    if constexpr (sizeof(real) == 4) {
+        const float4 t = *(const float4 *)p;
+        v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+    } else {
+        const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+        v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+    }
+}
+
+template <typename real>
+__device__ __forceinline__ void store4(real *p, const real (&v)[4])
+{
+    if constexpr (sizeof(real) == 4) {
+        *(float4 *)p = float4{v[0], v[1], v[2], v[3]};
+    } else {
+        *(double2 *)p = double2{v[0], v[1]};
+        *(double2 *)(p + 2) = double2{v[2], v[3]};
+    }
+}
+
+// Spread: one block (256 threads) per dense item (<= kSpreadChunk points of one
+// base cell) and 16 RHS.  Thread (slot = t / 4, rq = t % 4) accumulates the
+// item's W x 4 block (taps x its RHS) over points slot, slot + 64, ...; the
+// 64 slots are then summed (shuffles within the wave, LDS across waves) and
+// the W x 16 block is added to the grid.
+template <typename real, int W>
+__global__ __launch_bounds__(kBlock) void k_spread_dense1(const WinDev *__restrict__ wins,
+                                                          const Chunk *__restrict__ items, IoArgs io, int R)
+{
+    constexpr int WQ = W / 4;  // window values evaluated per lane
+    __shared__ real red[4][W][16];
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    const int r0 = blockIdx.y * 16;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, rq = t & 3, slot = t >> 2;
+    int bx, by, bz, nzc;
+    unpack_cell(it.tile, bx, by, bz, nzc);
+    const real *coords = (const real *)w.coords;
+    const ProbDev pio = get_prob_d(io, w.prob);
+    const real *Vp = (const real *)pio.Vp;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    real acc[W][4];
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc[k][i] = real(0);
+    // The quad's points are slot + 64 k, k < KP (items hold at most 64 KP
+    // points; the four lanes of a quad share their points).  The reads are
+    // issued in three waves so that many are in flight at once: the
+    // permutation entries and coordinates of all KP points, then the RHS rows
+    // of four points at a time, each batch loaded before the previous one's
+    // products.
+    constexpr int KP = kSpreadChunk / 64;
+    int pj[KP];
+    real uj[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int p = slot + 64 * k;
+        const bool act = p < it.count;
+        pj[k] = act ? w.perm[it.start + p] : -1;
+        uj[k] = act ? coords[it.start + p] : real(0);
+    }
+    auto load_rows = [&](int k0, real (&v)[4][4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (pj[k0 + k] >= 0)
+                load4(Vp + (int64_t)pj[k0 + k] * pio.ldvp + r0 + 4 * rq, v[k]);
+            else
+                v[k][0] = v[k][1] = v[k][2] = v[k][3] = real(0);
+        }
+    };
+    real va[4][4], vb[4][4];
+    load_rows(0, va);
+#pragma unroll
+    for (int k0 = 0; k0 < KP; k0 += 4) {
+        if (k0 + 4 < KP && slot + 64 * (k0 + 4) < it.count)
+            load_rows(k0 + 4, (k0 & 4) ? va : vb);
+        real (&v)[4][4] = (k0 & 4) ? vb : va;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (slot + 64 * (k0 + k) >= it.count)
+                break;
+            real wq[WQ], wv[W];
+#pragma unroll
+            for (int q = 0; q < WQ; ++q)
+                wq[q] = kb_psi_d(uj[k0 + k] - (real)(bx + rq * WQ + q), mm, kb, ie);
+            quad_gather<W>(wq, wv);
+#pragma unroll
+            for (int o = 0; o < W; ++o)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[o][i] += wv[o] * v[k][i];
+        }
+    }
+    // sum the 16 point slots of the wave (lanes rq, rq + 4, ...), then the waves
+#pragma unroll
+    for (int o = 0; o < W; ++o)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            real a = acc[o][i];
+#pragma unroll
+            for (int s = 4; s < 64; s <<= 1)
+                a += __shfl_xor(a, s, 64);
+            acc[o][i] = a;
+        }
+    if (lane < 4)
+#pragma unroll
+        for (int o = 0; o < W; ++o)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                red[wave][o][4 * rq + i] = acc[o][i];
+    __syncthreads();
+    if (t < W * 16) {
+        const int o = t >> 4, rr = t & 15, r = r0 + rr;
+        if (r < R) {
+            const real g = red[0][o][rr] + red[1][o][rr] + red[2][o][rr] + red[3][o][rr];
+            real *G = (real *)w.G;
+            gadd(&G[((int64_t)(r >> 1) * w.szG + bx + o) * 2 + (r & 1)], g);
+        }
+    }
+}
+
+// Interp: one block per dense item (<= kDenseChunk points) and 16 RHS, both
+// outputs.  The item's W cells x 16 RHS of each output grid are staged in LDS;
+// one lane per point (all 16 RHS of the point in the lane), so the point's
+// coordinate and permutation entry are read once and its row is written with
+// four 16-byte stores per output.  (Four lanes per point, each with four
+// RHS, measured 0.84 against 0.81 ms on fifteen 1e6-point windows: the
+// scattered 64-byte row writes bound both.)
+template <typename real, int W>
+__global__ __launch_bounds__(kBlock) void k_interp_dense1(const WinDev *__restrict__ wins,
+                                                           const Chunk *__restrict__ items, int R, int nout)
+{
+    __shared__ __align__(16) real hs[2][W][16];
+    const Chunk it = items[blockIdx.x];
+    const WinDev &w = wins[it.win];
+    const int r0 = blockIdx.y * 16;
+    const int nr = min(16, R - r0);
+    const int t = threadIdx.x;
+    int bx, by, bz, nzc;
+    unpack_cell(it.tile, bx, by, bz, nzc);
+    const real *H = (const real *)w.H;
+    for (int e = t; e < nout * W * 8; e += kBlock) {
+        const int pi = e & 7, c = (e >> 3) % W, o = e / (8 * W);
+        const int ra = 2 * pi;
+        real re = real(0), im = real(0);
+        if (ra < nr) {
+            const int64_t off = ((int64_t)(o * w.npair_cap + (r0 >> 1) + pi) * w.szH + bx + c) * 2;
+            re = H[off];
+            im = H[off + 1];
+        }
+        hs[o][c][ra] = re;
+        hs[o][c][ra + 1] = ra + 1 < nr ? im : real(0);
+    }
+    __syncthreads();
+    if (t >= it.count)
+        return;
+    const real *coords = (const real *)w.coords;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    const int j = it.start + t;
+    const real u = coords[j];
+    const int64_t orig = w.perm[j];
+    real acc[2][16] = {};
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const real wc = kb_psi_d(u - (real)(bx + c), mm, kb, ie);
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            if (o >= nout)
+                break;
+#pragma unroll
+            for (int i = 0; i < 16; i += 4) {
+                real h[4];
+                load4(&hs[o][c][i], h);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[o][i + q] += wc * h[q];
+            }
+        }
+    }
+    const bool vec = (w.Rcap & 3) == 0 && nr == 16;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        if (o >= nout)
+            break;
+        real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+        if (vec) {
+#pragma unroll
+            for (int i = 0; i < 16; i += 4) {
+                real v4[4] = {acc[o][i], acc[o][i + 1], acc[o][i + 2], acc[o][i + 3]};
+                store4(dst + i, v4);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < nr)
+                    dst[i] = acc[o][i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -382,6 +631,16 @@ static void interp_dense_w(Engine &E, int R, int nout, hipStream_t st)
 template <typename real, int D>
 static void spread_dense_d(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
+    if (D == 1) {
+        const dim3 grid(E.ndense_sp[1][wi], (R + 15) / 16);
+        if (wi == 0)
+            hipLaunchKernelGGL((k_spread_dense1<real, 8>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[1][wi], io,
+                               R);
+        else
+            hipLaunchKernelGGL((k_spread_dense1<real, 12>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense_sp[1][wi],
+                               io, R);
+        return;
+    }
     if (wi == 0)
         spread_dense_w<real, D, 8>(E, R, io, st);
     else
@@ -391,6 +650,16 @@ static void spread_dense_d(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 template <typename real, int D>
 static void interp_dense_d(Engine &E, int wi, int R, int nout, hipStream_t st)
 {
+    if (D == 1) {
+        const dim3 grid(E.ndense[1][wi], (R + 15) / 16);
+        if (wi == 0)
+            hipLaunchKernelGGL((k_interp_dense1<real, 8>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[1][wi], R,
+                               nout);
+        else
+            hipLaunchKernelGGL((k_interp_dense1<real, 12>), grid, dim3(kBlock), 0, st, E.d_wins, E.d_dense[1][wi], R,
+                               nout);
+        return;
+    }
     if (wi == 0)
         interp_dense_w<real, D, 8>(E, R, nout, st);
     else

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
     const real *coords = (const real *)w.coords;
     const int W = w.W, m = w.m;
     const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
-    double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0;
+    real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0;
 
     for (int base = wave * 4; base < ch.count; base += 16) {
         const int p = base + grp;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
 #pragma unroll
             for (int i = 0; i < RB; ++i)
                 if (i == g && i < nr)
-                    dst[(int64_t)orig * w.Rcap + i] = (double)acc[i];
+                    dst[(int64_t)orig * w.Rcap + i] = acc[i];
         }
         wave_sync();
     }
@@ -665,6 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
 // needed; the 16-RHS tiles of k_combine would leave most lanes idle here.
 constexpr int kCombineRowsMaxR = 4;
 
+template <typename real>
 __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
 {
     const ProbDev p = get_prob(io, blockIdx.y);
@@ -675,20 +676,20 @@ __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restric
         double y[kCombineRowsMaxR] = {};
         for (int k = 0; k < nwin; ++k) {
             const WinDev &w = wins[p.wbeg + k];
-            const double *src = w.Yw + i * w.Rcap;
-            const double *dsrc = w.Yw + ((int64_t)w.N + i) * w.Rcap;
+            const real *src = (const real *)w.Yw + i * w.Rcap;
+            const real *dsrc = (const real *)w.Yw + ((int64_t)w.N + i) * w.Rcap;
             const int64_t blk = (int64_t)k * p.ldy * R;  // window k's block of dY/dl, dY/dsigma
 #pragma unroll
             for (int r = 0; r < kCombineRowsMaxR; ++r) {
                 if (r >= R)
                     break;
-                const double v = src[r];
+                const double v = (double)src[r];
                 const int64_t at = blk + iy + (int64_t)r * p.ldy;
                 y[r] += w.sig2 * v;
                 if (want_ds)
                     p.dYs[at] = w.dsig * v;
                 if (want_dl)
-                    p.dYl[at] = w.der_scale * dsrc[r];
+                    p.dYl[at] = w.der_scale * (double)dsrc[r];
             }
         }
         if (want_y)
@@ -699,6 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restric
     }
 }
 
+template <typename real>
 __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
 {
     // Tiles of 64 points x 16 RHS: the window products (point-major) are read
@@ -724,7 +726,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                 for (int q = 0; q < 4; ++q) {
                     const int e = t + kBlock * q, pl = e >> 4, rr = e & 15;
                     const int64_t ip = i0 + pl;
-                    v[q] = (ip < p.N && rr < nr) ? w.Yw[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr] : 0.0;
+                    v[q] = (ip < p.N && rr < nr) ? (double)((const real *)w.Yw)[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr]
+                                                  : 0.0;
                 }
             };
             double y[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1346,7 +1349,7 @@ WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
         ys += w.nf ? 2 * w.N : 0;
     }
     L.grid_bytes = std::max<int64_t>(total * (int64_t)cs, 256);
-    L.y_bytes = std::max<int64_t>(ytotal * (int64_t)sizeof(double), 256);
+    L.y_bytes = std::max<int64_t>(ytotal * (int64_t)real_size(E.precision), 256);
     L.nys_bytes = ys * (int64_t)sizeof(double);
     int64_t packN = 0;
     for (const Plan *pl : E.plans)
@@ -1363,7 +1366,7 @@ WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
 // Point the engine's descriptors and problem records at workspace buffers of
 // layout L (grids, per-window products, close-pair sums, RHS staging, dense
 // spread blocks).  Host-side only: the descriptors still need an upload.
-void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *nys, void *vpack, void *scr0,
+void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, void *yw, double *nys, void *vpack, void *scr0,
                     void *scr1)
 {
     const size_t cs = 2 * real_size(E.precision);
@@ -1386,8 +1389,8 @@ void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *
         E.probs[p].ldvp = L.vpack_ld;
         off += E.probs[p].N * L.vpack_ld;
     }
-    char *p = (char *)ws;
-    double *yp = yw, *q = nys;
+    char *p = (char *)ws, *yp = (char *)yw;
+    double *q = nys;
     for (WinDev &w : E.wdev) {
         auto take = [&](int64_t n) {
             void *r = p;
@@ -1405,7 +1408,7 @@ void engine_bind_ws(Engine &E, const WsLayout &L, void *ws, double *yw, double *
         w.npair_cap = L.cap;
         w.Rcap = L.rcap;
         w.Yw = yp;
-        yp += 2 * L.rcap * w.N;
+        yp += 2 * L.rcap * w.N * (int64_t)real_size(E.precision);
         w.nf_ys = w.nf ? q : nullptr;
         q += w.nf ? 2 * w.N : 0;
     }
@@ -1436,7 +1439,8 @@ addk_status engine_ensure_workspace(Engine &E, int R)
     E.d_near_ys = nullptr;
     E.vpack = E.scratch[0] = E.scratch[1] = nullptr;
     void *ws = nullptr, *vp = nullptr, *scr[2] = {nullptr, nullptr};
-    double *yw = nullptr, *nys = nullptr;
+    void *yw = nullptr;
+    double *nys = nullptr;
     auto release = [&]() {
         free_dev(ws);
         free_dev(yw);
@@ -1730,10 +1734,16 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
     StageTimer t(E, PS_COMBINE, st);
     if (R <= kCombineRowsMaxR) {
         const int bx1 = (int)std::min<int64_t>((maxN + kBlock - 1) / kBlock, 16384);
-        hipLaunchKernelGGL(k_combine_rows, dim3(bx1, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+        if (E.precision == ADDK_FP32)
+            hipLaunchKernelGGL(k_combine_rows<float>, dim3(bx1, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+        else
+            hipLaunchKernelGGL(k_combine_rows<double>, dim3(bx1, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
     } else {
         const int bx = (int)std::min<int64_t>((maxN + 63) / 64, 16384);
-        hipLaunchKernelGGL(k_combine, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+        if (E.precision == ADDK_FP32)
+            hipLaunchKernelGGL(k_combine<float>, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
+        else
+            hipLaunchKernelGGL(k_combine<double>, dim3(bx, ny), dim3(kBlock), 0, st, E.d_wins, io, R, mode);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

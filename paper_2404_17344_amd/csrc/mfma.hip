@@ -237,14 +237,14 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        float *dst = (float *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int p = (wave + 4 * g) * 16 + 4 * q + i;
                 if (p < it.count)
-                    dst[(int64_t)w.perm[it.start + p] * w.Rcap] = (double)acc[o][g][i];
+                    dst[(int64_t)w.perm[it.start + p] * w.Rcap] = acc[o][g][i];
             }
     }
 }
@@ -331,7 +331,7 @@ __device__ __forceinline__ void interp_dense_item_z1(const WinDev &w, const Chun
                 for (int s = 8; s > 0; s >>= 1)
                     v += __shfl_xor(v, s, 16);
                 if (act && mrow == 0)
-                    w.Yw[((int64_t)o * w.N + w.perm[it.start + p]) * w.Rcap] = (double)v;
+                    ((float *)w.Yw)[((int64_t)o * w.N + w.perm[it.start + p]) * w.Rcap] = v;
             }
         }
     }
@@ -964,14 +964,14 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        double *dst = w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        float *dst = (float *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
                 if (p < ch.count)
-                    dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = (double)acc[o][g][i];
+                    dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = acc[o][g][i];
             }
     }
 }

@@ -266,11 +266,11 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
     const int64_t orig = w.perm[i];
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        double *dst = w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+        real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
 #pragma unroll
         for (int r = 0; r < RT; ++r)
             if (r0 + r < R)
-                dst[r] += (double)acc[o][r];
+                dst[r] += acc[o][r];
     }
 }
 
@@ -459,6 +459,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
 
 // Yw[o][perm[j]][0] += ys[o][j], then ys[o][j] = 0, for the near-field windows
 // (blockIdx.y = window).
+template <typename real>
 __global__ void k_near_scatter(const WinDev *__restrict__ wins, int nout)
 {
     const WinDev &w = wins[blockIdx.y];
@@ -470,7 +471,7 @@ __global__ void k_near_scatter(const WinDev *__restrict__ wins, int nout)
     const int64_t oj = w.perm[j];
     for (int o = 0; o < nout; ++o) {
         double *src = w.nf_ys + o * w.N + j;
-        w.Yw[(o * w.N + oj) * w.Rcap] += *src;
+        ((real *)w.Yw)[(o * w.N + oj) * w.Rcap] += (real)*src;
         *src = 0.0;
     }
 }
@@ -566,8 +567,8 @@ void launch_near_sym(Engine &E, int nout, IoArgs io, hipStream_t st)
     if (E.nnear[3])
         launch_near_sym_d<real, 3>(E, nout, io, st);
     if (nmax > 0)
-        hipLaunchKernelGGL(k_near_scatter, dim3((unsigned)((nmax + 255) / 256), (unsigned)E.wdev.size()), dim3(256), 0,
-                           st, E.d_wins, nout);
+        hipLaunchKernelGGL(k_near_scatter<real>, dim3((unsigned)((nmax + 255) / 256), (unsigned)E.wdev.size()),
+                           dim3(256), 0, st, E.d_wins, nout);
 }
 
 }  // namespace

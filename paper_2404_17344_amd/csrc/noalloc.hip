@@ -60,8 +60,8 @@ int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
 // The engine's own workspace binding, put back after the call.
 struct SavedWs {
     std::vector<WinDev> wdev;
-    void *ws, *vpack, *scr[2];
-    double *yw, *nys;
+    void *ws, *vpack, *scr[2], *yw;
+    double *nys;
     int64_t ws_bytes, yw_bytes, vpack_bytes, vpack_ld, scap[2], rcap;
     int npair_cap;
     bool dirty;
@@ -150,8 +150,8 @@ extern "C" addk_status addk_matvec_noalloc(addk_plan plan, int32_t R, const doub
         return s;
     char *b = (char *)base;
     const SavedWs saved(E);
-    engine_bind_ws(E, L, b, (double *)(b + off_y), L.nys_bytes > 0 ? (double *)(b + off_n) : nullptr, b + off_v,
-                   b + off_s0, b + off_s1);
+    engine_bind_ws(E, L, b, b + off_y, L.nys_bytes > 0 ? (double *)(b + off_n) : nullptr, b + off_v, b + off_s0,
+                   b + off_s1);
     hipStream_t st = (hipStream_t)stream;
     s = engine_upload(E);  // synchronous: the previous user of the array has finished
     if (s == ADDK_OK && L.nys_bytes > 0) {
