@@ -75,8 +75,8 @@ typedef enum {
 #define ADDK_NO_ACCURACY_CHECK 4u /* do not refuse windows with eta < 1                       */
 #define ADDK_TILE_KERNELS_ONLY 8u /* route every point through the tile kernels (no dense-cell
                                      kernels); same results up to rounding, for comparison     */
-#define ADDK_VECTOR_ALU_ONLY 16u  /* FP32 plans: run the dense-cell kernels on the vector ALUs
-                                     instead of the matrix cores; for comparison              */
+#define ADDK_VECTOR_ALU_ONLY 16u  /* run the dense-cell kernels on the vector ALUs instead of
+                                     the matrix cores; for comparison                         */
 #define ADDK_NEAR_FIELD 32u       /* Matern kernels only: near-field corrected products (below) */
 
 /*
@@ -273,9 +273,11 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
                                     void *stream);
 
 /*
- * Kernel-variant knobs (FP32 plans): which stages run on the matrix cores
- * (v_mfma_f32_16x16x4f32) instead of the vector ALUs.  Both variants compute
- * the same products; they differ in speed and in FP32 summation order.
+ * Kernel-variant knobs: which stages run on the matrix cores
+ * (v_mfma_f32_16x16x4f32; FP64 plans: v_mfma_f64_16x16x4f64 for the dense
+ * interpolation with R >= 2, the other stages stay on the vector ALUs)
+ * instead of the vector ALUs.  Both variants compute the same products; they
+ * differ in speed and in summation order.
  */
 #define ADDK_KNOB_SPREAD_MFMA 1u       /* dense-cell spreading (d = 3)      */
 #define ADDK_KNOB_INTERP_DENSE_MFMA 2u /* dense-cell interpolation (d = 3)  */
@@ -324,7 +326,7 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
  * with K V and dK/dl V) or on this batch (graph replays), `reps` timed runs
  * each after one warm-up, keeps the fastest combination and returns it in
  * *knobs (may be NULL).  Temporary inputs are allocated and freed inside.
- * Synchronous.  FP64 plans have nothing to tune (knobs = 0).
+ * Synchronous.  FP64 plans tune the dense interpolation knob only.
  * Errors: INVALID_ARG, OOM, HIP.
  */
 addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs,

@@ -175,8 +175,16 @@ static addk_status time_runs(Fn fn, int reps, hipStream_t st, double *ms)
 // that the engine has work for (others are left on, they have no effect).
 static std::vector<uint32_t> knob_candidates(const Engine &E)
 {
-    if (E.precision != ADDK_FP32 || E.no_mfma)
+    if (E.no_mfma)
         return {0u};
+    if (E.precision != ADDK_FP32) {  // FP64: only the dense interp has a matrix-core variant
+        bool dense = false;
+        for (int wi = 0; wi < 2; ++wi)
+            dense = dense || E.ndense[3][wi] > 0;
+        if (!dense)
+            return {0u};
+        return {0u, (uint32_t)ADDK_KNOB_INTERP_DENSE_MFMA};
+    }
     bool dense = false, tile = false;
     for (int wi = 0; wi < 2; ++wi)
         dense = dense || E.ndense[3][wi] > 0;

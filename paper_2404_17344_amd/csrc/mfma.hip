@@ -23,6 +23,35 @@
 namespace addk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core types per precision: one 16 x 16 x 4 product per instruction,
+// v_mfma_f32_16x16x4f32 (FP32) or v_mfma_f64_16x16x4f64 (FP64).  Both take
+// A[l % 16][l / 16] and B[l / 16][l % 16] from lane l; the FP32 product
+// returns D[4 (l / 16) + i][l % 16] in register i, the FP64 one
+// D[4 i + l / 16][l % 16] (out_row).
+template <typename real>
+struct MfmaT;
+template <>
+struct MfmaT<float> {
+    typedef f4 v4;
+    typedef float2 v2;
+};
+template <>
+struct MfmaT<double> {
+    typedef d4 v4;
+    typedef double2 v2;
+};
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename real>
+__device__ __forceinline__ constexpr int out_row(int q, int i)
+{
+    return sizeof(real) == 4 ? 4 * q + i : 4 * i + q;
+}
 
 // psi(z) = m sinh(b s) / (sinh(b m) s), s = sqrt(m^2 - z^2), evaluated as
 //   m e^{-b z^2 / (s + m)} (1 - e^{-2 b s}) / ((1 - e^{-2 b m}) s),
@@ -39,6 +68,17 @@ __device__ __forceinline__ float kb_psi_f(float z, float m, float b, float inv_e
     const float e2 = __builtin_amdgcn_exp2f(-2.f * bl * s);
     return m * e1 * (1.f - e2) * inv_e2bm * __builtin_amdgcn_rcpf(s);
 }
+
+// FP64: the same stable form with IEEE sqrt and exp.
+__device__ __forceinline__ double kb_psi_m(double z, double m, double b, double inv_e2bm)
+{
+    const double z2 = z * z;
+    double s2 = m * m - z2;
+    s2 = s2 > 1e-24 ? s2 : 1e-24;
+    const double s = sqrt(s2);
+    return m * exp(-b * z2 / (s + m)) * (1.0 - exp(-2.0 * b * s)) * inv_e2bm / s;
+}
+__device__ __forceinline__ float kb_psi_m(float z, float m, float b, float inv_e2bm) { return kb_psi_f(z, m, b, inv_e2bm); }
 
 // Dense item anchor: base cell (bx, by, bz) and the number of cells in z
 // (1, or 2 for two z-adjacent dense cells sharing one item).
@@ -62,23 +102,23 @@ __device__ __forceinline__ ProbDev get_prob_m(const IoArgs &io, int p) { return 
 template <int NO>
 constexpr int acc_rows() { return NO == 1 ? 2 : NO; }
 
-template <int SW, int NT, int SX, int NG, int NO>
-__device__ __forceinline__ void slab_products(f4 (&acc)[acc_rows<NO>()][NG], const float (&wxq)[NG][NT], const float *wyl,
-                                              const float (&wz)[NG], const bool (&live)[NG], const float (*sl)[16],
-                                              int ny, int q, int mrow)
+template <typename real, int SW, int NT, int SX, int NG, int NO>
+__device__ __forceinline__ void slab_products(typename MfmaT<real>::v4 (&acc)[acc_rows<NO>()][NG],
+                                              const real (&wxq)[NG][NT], const real *wyl, const real (&wz)[NG],
+                                              const bool (&live)[NG], const real (*sl)[16], int ny, int q, int mrow)
 {
     constexpr int C = SW * SX;  // cells of one output's slab
 #pragma unroll
     for (int oy = 0; oy < SW; ++oy) {
         if (oy >= ny)
             break;
-        float wyz[NG];
+        real wyz[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             wyz[g] = wyl[(g * SW + oy) * 16 + mrow] * wz[g];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            float b[NO];
+            real b[NO];
 #pragma unroll
             for (int o = 0; o < NO; ++o)
                 b[o] = sl[o * C + oy * SX + 4 * t + q][mrow];
@@ -86,11 +126,11 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[acc_rows<NO>()][NG], con
             for (int g = 0; g < NG; ++g) {
                 if (!live[g])  // wave-uniform: no point of the group reaches this slab
                     continue;
-                const float a = wyz[g] * wxq[g][t];
+                const real a = wyz[g] * wxq[g][t];
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
                     const int ai = NO == 1 ? (oy & 1) : o;
-                    acc[ai][g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[o], acc[ai][g], 0, 0, 0);
+                    acc[ai][g] = mfma4(a, b[o], acc[ai][g]);
                 }
             }
         }
@@ -104,26 +144,27 @@ __device__ __forceinline__ void slab_products(f4 (&acc)[acc_rows<NO>()][NG], con
 // of the wave's NG point groups.  Cells outside the window's grid box read as
 // zero.  Every thread of the block calls this with the same nz, so the
 // barriers inside match.
-template <int SW, int SX, int NT, int NG, int NO, int NB = 2>
-__device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
+template <typename real, int SW, int SX, int NT, int NG, int NO, int NB = 2>
+__device__ __forceinline__ void stream_slabs(const WinDev &w, real (*slab)[NO][SW * SX][16], int r0, int nr, int x0,
                                              int y0, int z0, int sx, int sy, int nz,
-                                             f4 (&acc)[acc_rows<NO>()][NG],
-                                             const float (&wxq)[NG][NT], const float *wyl,
-                                             const float (&uzr)[NG], const int (&lbz)[NG], bool zmask)
+                                             typename MfmaT<real>::v4 (&acc)[acc_rows<NO>()][NG],
+                                             const real (&wxq)[NG][NT], const real *wyl,
+                                             const real (&uzr)[NG], const int (&lbz)[NG], bool zmask)
 {
+    typedef typename MfmaT<real>::v2 v2;
     constexpr int C = SW * SX;
     constexpr int SL = (8 * C + kBlock - 1) / kBlock;  // complex values per thread per slab and output
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, mrow = lane & 15;
-    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-    const float *H = (const float *)w.H;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    const real *H = (const real *)w.H;
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     const int p0 = r0 >> 1;
     const int np = (nr + 1) >> 1;
     // Thread element idx covers RHS pair idx % 8 of cell idx / 8: the LDS
     // stores are then consecutive 8-byte words (no bank conflicts), and the
     // global loads read 64-byte runs of 8 cells in each pair's grid.
-    float2 pre[NO][SL];
+    v2 pre[NO][SL];
     auto load = [&](int oz) {
         const int gz = z0 + oz;
 #pragma unroll
@@ -134,11 +175,11 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
                 const int pi = idx & 7, c = idx >> 3;
                 const int ox = c % SX, oy = c / SX;
                 const int gx = x0 + ox, gy = y0 + oy;
-                float2 v = {0.f, 0.f};
+                v2 v = {real(0), real(0)};
                 if (idx < 8 * C && pi < np && ox < sx && oy < sy && gx < ex && gy < ey && gz < ez) {
                     const int64_t off =
                         ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
-                    v = *(const float2 *)(H + off);
+                    v = *(const v2 *)(H + off);
                 }
                 pre[o][k] = v;
             }
@@ -151,8 +192,7 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
                 const int idx = threadIdx.x + k * kBlock;
                 if (idx < 8 * C) {
                     const int pi = idx & 7, c = idx >> 3;
-                    *(float2 *)&slab[buf][o][c][2 * pi] =
-                        float2{pre[o][k].x, (2 * pi + 1 < nr) ? pre[o][k].y : 0.f};
+                    *(v2 *)&slab[buf][o][c][2 * pi] = v2{pre[o][k].x, (2 * pi + 1 < nr) ? pre[o][k].y : real(0)};
                 }
             }
     };
@@ -162,16 +202,17 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
     for (int oz = 0; oz < nz; ++oz) {
         if (oz + 1 < nz)
             load(oz + 1);  // in flight during this slab's products
-        float wz[NG];
+        real wz[NG];
         bool live[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             // lbz: the point's first z slab in the box (far away for inactive lanes)
             const bool in = (unsigned)(oz - lbz[g]) < (unsigned)w.W;
             live[g] = __builtin_amdgcn_readfirstlane(__any(in)) != 0;
-            wz[g] = (!zmask || in) ? kb_psi_f(uzr[g] - (float)(z0 + oz), mm, kb, ie) : 0.f;
+            wz[g] = (!zmask || in) ? kb_psi_m(uzr[g] - (real)(z0 + oz), mm, kb, ie) : real(0);
         }
-        slab_products<SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, live, &slab[NB == 2 ? oz & 1 : 0][0][0], sy, q, mrow);
+        slab_products<real, SW, NT, SX, NG, NO>(acc, wxq, wyl, wz, live, &slab[NB == 2 ? oz & 1 : 0][0][0], sy, q,
+                                                mrow);
         if (oz + 1 < nz) {
             if (NB == 1)
                 __syncthreads();  // every wave is done with the buffer
@@ -183,52 +224,55 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, float (*slab)[NO][
 
 // One dense item: every wave takes NG of the item's 16-point groups (group
 // wave + 4 g); groups past the item's end carry zero weights.
-template <int W, int NO, int NG>
+template <typename real, int W, int NO, int NG>
 __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &it, int r0, int nr,
-                                                  float (*slab)[NO][W * W][16], float *wy_lds)
+                                                  real (*slab)[NO][W * W][16], real *wy_lds)
 {
+    typedef typename MfmaT<real>::v4 v4;
     constexpr int NT = W / 4;  // K steps per x row
     int bx, by, bz, nzc;
     unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
-    const float *coords = (const float *)w.coords;
-    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    const real *coords = (const real *)w.coords;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     // x weights stay in registers (lane q holds taps 4t + q); the y weights of
     // the wave's points go to its LDS area [g][oy][16 points], each lane
     // computing the taps 4t + q of its point
-    float *wyl = wy_lds + wave * (4 * W * 16);
-    float wxq[NG][NT], uz[NG];
+    real *wyl = wy_lds + wave * (4 * W * 16);
+    real wxq[NG][NT], uz[NG];
     int lbz[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int p = (wave + 4 * g) * 16 + mrow;
         const bool act = p < it.count;
         const int j = it.start + (act ? p : 0);
-        const float ux = coords[j], uy = coords[w.N + j];
+        const real ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
         lbz[g] = act ? (int)floorf(uz[g]) - w.m + 1 - bz : (1 << 20);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            wxq[g][t] = act ? kb_psi_f(ux - (float)(bx + 4 * t + q), mm, kb, ie) : 0.f;
-            wyl[(g * W + 4 * t + q) * 16 + mrow] = kb_psi_f(uy - (float)(by + 4 * t + q), mm, kb, ie);
+            wxq[g][t] = act ? kb_psi_m(ux - (real)(bx + 4 * t + q), mm, kb, ie) : real(0);
+            wyl[(g * W + 4 * t + q) * 16 + mrow] = kb_psi_m(uy - (real)(by + 4 * t + q), mm, kb, ie);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     constexpr int NA = acc_rows<NO>();
-    f4 acc[NA][NG];
+    v4 acc[NA][NG];
 #pragma unroll
     for (int o = 0; o < NA; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
+            acc[o][g] = v4{real(0), real(0), real(0), real(0)};
     // With two z cells, one of the 2m + 1 slabs lies just outside each point's
-    // window; the window there evaluates to ~2 m b e^{-bm} (< 1e-10), so no mask
-    // is applied in this FP32 kernel; a group whose points all lie in one of
-    // the cells skips its outside slab altogether.
-    stream_slabs<W, W, NT, NG, NO, 1>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz, false);
+    // window, where the window formula does not vanish (~2.5e-7 at m = 4,
+    // 3e-11 at m = 6), so the z weights are masked to the point's own 2m
+    // slabs; a group whose points all lie in one of the cells skips its
+    // outside slab altogether.
+    stream_slabs<real, W, W, NT, NG, NO, 1>(w, slab, r0, nr, bx, by, bz, W, W, W + nzc - 1, acc, wxq, wyl, uz, lbz,
+                                            true);
     if (NO == 1)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
@@ -237,12 +281,12 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        float *dst = (float *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = (wave + 4 * g) * 16 + 4 * q + i;
+                const int p = (wave + 4 * g) * 16 + out_row<real>(q, i);
                 if (p < it.count)
                     dst[(int64_t)w.perm[it.start + p] * w.Rcap] = acc[o][g][i];
             }
@@ -376,15 +420,16 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma_z1(const WinDev *__restr
 // outputs at once.  The number of groups per wave is uniform in the block, so
 // the dispatch below is a uniform branch and every wave runs the same slab
 // loop (and barriers).
-template <int W, int NO>
-__global__ __launch_bounds__(kBlock, 5) void k_interp_mfma(const WinDev *__restrict__ wins,
-                                                          const Chunk *__restrict__ items, int R)
+template <typename real, int W, int NO>
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 5 : 2) void k_interp_mfma(const WinDev *__restrict__ wins,
+                                                                                  const Chunk *__restrict__ items,
+                                                                                  int R)
 {
     // one slab buffer (31 KB of LDS with the y weights at 2m = 12, two outputs)
     // and at most 96 registers (a few spills at the slab barriers): five blocks
-    // per CU
-    __shared__ __align__(16) float slab[1][NO][W * W][16];
-    __shared__ __align__(16) float wy_lds[4 * 4 * W * 16];
+    // per CU in FP32; in FP64 the 61 KB of LDS allow two
+    __shared__ __align__(16) real slab[1][NO][W * W][16];
+    __shared__ __align__(16) real wy_lds[4 * 4 * W * 16];
     const Chunk it = items[blockIdx.x];
     const WinDev &w = wins[it.win];
     const int r0 = blockIdx.y * 16;
@@ -393,10 +438,10 @@ __global__ __launch_bounds__(kBlock, 5) void k_interp_mfma(const WinDev *__restr
     const int nr = min(16, R - r0);
     const int ng = (((it.count + 15) >> 4) + 3) >> 2;
     switch (ng) {
-    case 1: interp_dense_item<W, NO, 1>(w, it, r0, nr, slab, wy_lds); break;
-    case 2: interp_dense_item<W, NO, 2>(w, it, r0, nr, slab, wy_lds); break;
-    case 3: interp_dense_item<W, NO, 3>(w, it, r0, nr, slab, wy_lds); break;
-    default: interp_dense_item<W, NO, 4>(w, it, r0, nr, slab, wy_lds); break;
+    case 1: interp_dense_item<real, W, NO, 1>(w, it, r0, nr, slab, wy_lds); break;
+    case 2: interp_dense_item<real, W, NO, 2>(w, it, r0, nr, slab, wy_lds); break;
+    case 3: interp_dense_item<real, W, NO, 3>(w, it, r0, nr, slab, wy_lds); break;
+    default: interp_dense_item<real, W, NO, 4>(w, it, r0, nr, slab, wy_lds); break;
     }
 }
 
@@ -954,8 +999,8 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz, lbz,
-                                       true);
+    stream_slabs<float, SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz,
+                                              lbz, true);
     if (NO == 1)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
@@ -1017,10 +1062,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_interp_tile_mfma(const WinDev *__
 
 bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
 {
-    if (E.precision != ADDK_FP32 || !E.ndense[3][wi])
+    if (!E.ndense[3][wi])
         return false;
     dim3 grid(E.ndense[3][wi], (R + 15) / 16);
     const Chunk *items = E.d_dense[3][wi];
+    if (E.precision == ADDK_FP64) {  // 16 RHS columns only (no one-RHS form)
+        if (R == 1)
+            return false;
+        if (wi == 0 && nout == 1)
+            hipLaunchKernelGGL((k_interp_mfma<double, 8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        else if (wi == 0)
+            hipLaunchKernelGGL((k_interp_mfma<double, 8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        else if (nout == 1)
+            hipLaunchKernelGGL((k_interp_mfma<double, 12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        else
+            hipLaunchKernelGGL((k_interp_mfma<double, 12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        return true;
+    }
     if (R == 1) {  // the z-slabs as columns
         if (wi == 0 && nout == 1)
             hipLaunchKernelGGL((k_interp_mfma_z1<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items);
@@ -1033,13 +1091,13 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
         return true;
     }
     if (wi == 0 && nout == 1)
-        hipLaunchKernelGGL((k_interp_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        hipLaunchKernelGGL((k_interp_mfma<float, 8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     else if (wi == 0)
-        hipLaunchKernelGGL((k_interp_mfma<8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        hipLaunchKernelGGL((k_interp_mfma<float, 8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     else if (nout == 1)
-        hipLaunchKernelGGL((k_interp_mfma<12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        hipLaunchKernelGGL((k_interp_mfma<float, 12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     else
-        hipLaunchKernelGGL((k_interp_mfma<12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
+        hipLaunchKernelGGL((k_interp_mfma<float, 12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, R);
     return true;
 }
 

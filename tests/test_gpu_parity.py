@@ -221,6 +221,35 @@ def test_matrix_core_kernels_match_vector_kernels(A, m, R):
 
 
 @pytest.mark.parametrize("m", [4, 6])
+@pytest.mark.parametrize("R", [8, 16, 21])
+def test_fp64_matrix_core_interp(A, m, R):
+    """FP64 dense-cell interpolation on the matrix cores (v_mfma_f64_16x16x4f64)
+    against the vector-ALU kernel (same FP64 products, other summation order)
+    and the direct sum, for K V alone and with the derivative products."""
+    rng = np.random.default_rng(112)
+    X = np.concatenate([rng.normal(0, 0.02, size=(30000, 3)), rng.uniform(-0.25, 0.25, size=(700, 3))])
+    V = rng.standard_normal((X.shape[0], R))
+    _say("fp64 mfma interp m=%d R=%d" % (m, R))
+    mk = lambda **kw: A.Plan(X, [[0, 1, 2]], [0.1], [1.0], n=32, m=m, precision="fp64", **kw)  # noqa: E731
+    pm, pv = mk(), mk(matrix_cores=False)
+    assert pm.query()["dense_points"] > 20000
+    Vc = torch.from_numpy(V).cuda()
+    Ym, dlm, _ = pm.dmatvec(Vc)
+    Yv, dlv, _ = pv.dmatvec(Vc)
+    Yk = pm.matvec(Vc)
+    assert relerr(Ym.cpu().numpy(), Yv.cpu().numpy()) < 1e-12
+    assert relerr(dlm[0].cpu().numpy(), dlv[0].cpu().numpy()) < 1e-12
+    assert relerr(Yk.cpu().numpy(), Yv.cpu().numpy()) < 1e-12
+    rows = np.arange(0, X.shape[0], 61)
+    Yo, dlo, _ = oracle_direct(X, [[0, 1, 2]], WL.GAUSSIAN, [0.1], [1.0], V, rows=rows, want_derivs=True)
+    # m = 4 is window-limited: on this tight cluster its element-wise error
+    # reaches 1.5e-6 of max |y| (both FP64 kernels alike)
+    tol = 1e-10 if m == 6 else 5e-6
+    assert relerr(Ym.cpu().numpy()[rows], Yo) < tol
+    assert relerr(dlm[0].cpu().numpy()[rows], dlo[0]) < tol
+
+
+@pytest.mark.parametrize("m", [4, 6])
 def test_dense_kernels_all_dims(A, m):
     """Clustered points in d = 1, 2, 3 windows so that every dense kernel runs."""
     rng = np.random.default_rng(110)
