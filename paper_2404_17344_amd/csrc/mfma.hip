@@ -449,28 +449,35 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 5 : 2) void k_interp_mf
 // Dense spread: one block per spread item (one or two dense cells) and 16 RHS;
 // the item's (2m)^2 x (2m + 1) block is written to its scratch slot and summed
 // into the grid by k_gather_blocks.
-// Z1 (one RHS): the 2m + 1 z-slabs take the N dimension instead of the RHS,
-// D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
+// Z1 (one RHS, FP32): the 2m + 1 z-slabs take the N dimension instead of the
+// RHS, D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
 // B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block, and the
 // flush writes the block with one value per tap (the gather's one-RHS layout).
-template <int W, bool Z1>
+// MS: the x-y taps' M tiles (16 taps each) are split over MS blocks
+// (blockIdx.z), each owning MTB consecutive tiles of every slab; FP64 uses
+// MS = 2 so that the accumulators (twice the registers of FP32) stay in the
+// register file, at the price of evaluating each point's window values twice.
+template <typename real, int W, bool Z1, int MS>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                        IoArgs io, int R, float *__restrict__ scratch)
+                                                        IoArgs io, int R, real *__restrict__ scratch)
 {
+    typedef typename MfmaT<real>::v4 v4;
     constexpr int WW = W * W;
     constexpr int MT = WW / 16;        // M tiles (16 taps) per z-slab
+    constexpr int MTB = (MT + MS - 1) / MS;  // M tiles of this block
     constexpr int SPW = W / 4;         // z-slabs per wave: slabs wave + 4 s, s < SPW (the first 2m)
-    constexpr int XT = (MT + 3) / 4;   // M tiles per wave of slab 2m (two-cell items only)
-    constexpr int PB = 32;             // points per round (8 K steps)
-    constexpr int FL = WW * 17;        // per-wave flush tile [tap][16 RHS + 1 pad]
+    constexpr int XT = (MTB + 3) / 4;  // M tiles per wave of slab 2m (two-cell items only)
+    constexpr int PB = sizeof(real) == 4 ? 32 : 16;  // points per round (PB / 4 K steps)
+    constexpr int KV = PB * 16 / kBlock;             // RHS values staged per thread and round
+    constexpr int FL = MTB * 16 * 17;  // per-wave flush tile [tap][16 RHS + 1 pad]
     constexpr int PS = 3 * W + 1;     // window values per point: x [W], y [W], z [W + 1] (item slabs)
     struct Round {
-        float pxy[PB][WW];
-        float pw[PB][PS];
-        float pv[PB][16];
+        real pxy[PB][WW];
+        real pw[PB][PS];
+        real pv[PB][16];
     };
     constexpr int RB_BYTES = 2 * (int)sizeof(Round);
-    constexpr int FL_BYTES = 4 * FL * (int)sizeof(float);
+    constexpr int FL_BYTES = 4 * FL * (int)sizeof(real);
     __shared__ __align__(16) unsigned char lds[RB_BYTES > FL_BYTES ? RB_BYTES : FL_BYTES];
     Round *rd = (Round *)lds;
 
@@ -479,25 +486,29 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     const int r0 = blockIdx.y * 16;
     if (r0 >= R)
         return;
+    const int mt0 = MS > 1 ? (int)blockIdx.z * MTB : 0;  // first M tile of this block
     int bx, by, bz, nzc;
     unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int NS = W + nzc - 1;  // z-slabs of the item's block
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: slab branches are scalar
     const int q = lane >> 4, mrow = lane & 15;
-    const float *coords = (const float *)w.coords;
+    const real *coords = (const real *)w.coords;
     const ProbDev pio = get_prob_m(io, w.prob);
-    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     const int t = threadIdx.x;
 
     // prefetch registers: the coordinates behind this thread's window values
     // (entry e = p * PS + o of the round's table, o < W: x, o < 2W: y, else z;
-    // e = t + k * kBlock) and two RHS values; all threads then share the
+    // e = t + k * kBlock) and KV RHS values; all threads then share the
     // window evaluations
     constexpr int NWE = PB * PS;
     constexpr int KW = (NWE + kBlock - 1) / kBlock;
-    float pcs[KW];
-    float pvv[2] = {0.f, 0.f};
+    real pcs[KW];
+    real pvv[KV];
+#pragma unroll
+    for (int k = 0; k < KV; ++k)
+        pvv[k] = real(0);
     auto load = [&](int p0) {
         const int np = min(PB, it.count - p0);
 #pragma unroll
@@ -505,21 +516,22 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             const int e = t + k * kBlock;
             const int p = e / PS, o = e - p * PS;
             const int dd = o < W ? 0 : (o < 2 * W ? 1 : 2);
-            pcs[k] = (e < NWE && p < np) ? coords[dd * w.N + it.start + p0 + p] : 0.f;
+            pcs[k] = (e < NWE && p < np) ? coords[dd * w.N + it.start + p0 + p] : real(0);
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < KV; ++k) {
             const int e = t + k * kBlock;  // e < PB * 16
             const int p = e >> 4, i = e & 15;
             const int r = r0 + i;
-            pvv[k] = (p < np && r < R) ? ((const float *)pio.Vp)[(int64_t)w.perm[it.start + p0 + p] * pio.ldvp + r] : 0.f;
+            pvv[k] = (p < np && r < R) ? ((const real *)pio.Vp)[(int64_t)w.perm[it.start + p0 + p] * pio.ldvp + r]
+                                       : real(0);
         }
     };
     // Straight-line code (selects, no branches) so that the compiler can
     // interleave it with the matrix ops of the current round.
     auto store_raw = [&](Round &d, int p0) {
         const int np = min(PB, it.count - p0);
-        float *pw = &d.pw[0][0];
+        real *pw = &d.pw[0][0];
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
@@ -527,15 +539,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             // x and y: tap o of the item's block; z: slab oz of the item, inside the
             // point's own window only
             const int oz = o - 2 * W;
-            const int dz = (int)floorf(pcs[k]) - w.m + 1 - bz;
-            const float c = o < W ? (float)(bx + o) : (o < 2 * W ? (float)(by + o - W) : (float)(bz + oz));
+            const int dz = (int)floor(pcs[k]) - w.m + 1 - bz;
+            const real c = o < W ? (real)(bx + o) : (o < 2 * W ? (real)(by + o - W) : (real)(bz + oz));
             const bool live = p < np && (o < 2 * W || (unsigned)(oz - dz) < (unsigned)W);
-            const float v = kb_psi_f(pcs[k] - c, mm, kb, ie);
+            const real v = kb_psi_m(pcs[k] - c, mm, kb, ie);
             if (KW * kBlock == NWE || e < NWE)
-                pw[e] = live ? v : 0.f;
+                pw[e] = live ? v : real(0);
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < KV; ++k) {
             const int e = t + k * kBlock;
             d.pv[e >> 4][e & 15] = pvv[k];
         }
@@ -548,21 +560,22 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     };
 
     // wave `wave` owns slabs wave + 4 s of the first 2m and, for two-cell
-    // items, the M tiles wave + 4 j of slab 2m (Z1: the M tiles wave + 4 j of
-    // every slab, accz)
+    // items, the M tiles mt0 + wave + 4 j of slab 2m (Z1: the M tiles wave + 4 j
+    // of every slab, accz)
     constexpr int JT = (MT + 3) / 4;
-    f4 acc[Z1 ? 1 : SPW][Z1 ? 1 : MT], accx[XT], accz[JT];
+    v4 acc[Z1 ? 1 : SPW][Z1 ? 1 : MTB], accx[XT], accz[Z1 ? JT : 1];
+    const v4 zero4 = v4{real(0), real(0), real(0), real(0)};
 #pragma unroll
     for (int s = 0; s < (Z1 ? 1 : SPW); ++s)
 #pragma unroll
-        for (int mt = 0; mt < (Z1 ? 1 : MT); ++mt)
-            acc[s][mt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < (Z1 ? 1 : MTB); ++mt)
+            acc[s][mt] = zero4;
 #pragma unroll
     for (int j = 0; j < XT; ++j)
-        accx[j] = f4{0.f, 0.f, 0.f, 0.f};
+        accx[j] = zero4;
 #pragma unroll
-    for (int j = 0; j < JT; ++j)
-        accz[j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < (Z1 ? JT : 1); ++j)
+        accz[j] = zero4;
 
     // Z1 forms the x-y products of its few matrix ops on the fly (no products
     // phase): lane mrow's tap of M tile wave + 4 j is (x, y) = (zx[j], zy[j] - W)
@@ -599,13 +612,12 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int ks = 0; ks < PB / 4; ++ks) {
                 const int pk = 4 * ks + q;
                 // B[point][slab mrow] = v wz(slab); zero past the item's 2m + 1 slabs
-                const float b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][2 * W + min(mrow, W)] : 0.f;
+                const real b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][2 * W + min(mrow, W)] : real(0);
 #pragma unroll
                 for (int j = 0; j < JT; ++j) {
                     const int mt = wave + 4 * j;
                     if (mt < MT)
-                        accz[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(cr.pw[pk][zx[j]] * cr.pw[pk][zy[j]], b,
-                                                                         accz[j], 0, 0, 0);
+                        accz[j] = mfma4(cr.pw[pk][zx[j]] * cr.pw[pk][zy[j]], b, accz[j]);
                 }
             }
         } else {
@@ -614,16 +626,16 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         // The next step's operands are read from LDS before this step's
         // matrix ops issue, so the reads overlap them.
         struct Ops {
-            float a[MT], ax[XT], v, wz[SPW + 1];
+            real a[MTB], ax[XT], v, wz[SPW + 1];
         };
         auto fetch = [&](int ks, Ops &o) {
             const int pk = 4 * ks + q;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                o.a[mt] = cr.pxy[pk][mt * 16 + mrow];
+            for (int mt = 0; mt < MTB; ++mt)
+                o.a[mt] = cr.pxy[pk][min(mt0 + mt, MT - 1) * 16 + mrow];
 #pragma unroll
             for (int j = 0; j < XT; ++j)
-                o.ax[j] = cr.pxy[pk][min(wave + 4 * j, MT - 1) * 16 + mrow];
+                o.ax[j] = cr.pxy[pk][min(mt0 + wave + 4 * j, MT - 1) * 16 + mrow];
             o.v = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s)
@@ -641,15 +653,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             // values), so the A operand is the plain x-y weight product
 #pragma unroll
             for (int s = 0; s < SPW; ++s) {
-                const float b = o.v * o.wz[s];
+                const real b = o.v * o.wz[s];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    acc[s][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[mt], b, acc[s][mt], 0, 0, 0);
+                for (int mt = 0; mt < MTB; ++mt)
+                    acc[s][mt] = mfma4(o.a[mt], b, acc[s][mt]);
             }
-            const float bx = o.v * o.wz[SPW];
+            const real bx2 = o.v * o.wz[SPW];
 #pragma unroll
             for (int j = 0; j < XT; ++j)
-                accx[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.ax[j], bx, accx[j], 0, 0, 0);
+                accx[j] = mfma4(o.ax[j], bx2, accx[j]);
         }
         }
         if (!Z1 && more) {
@@ -663,54 +675,56 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // write the item's block [oz][oy][ox][16 RHS] to its scratch slot (plain
     // stores; the blocks of all items are summed by k_gather_blocks), each
     // slab (or M tile of slab 2m) through a per-wave LDS transpose
-    float *fl = (float *)lds + wave * FL;
+    real *fl = (real *)lds + wave * FL;
     if constexpr (Z1) {
         // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow; one RHS per tap
-        float *dz = scratch + (int64_t)blockIdx.x * ((W + 1) * WW);
+        real *dz = scratch + (int64_t)blockIdx.x * ((W + 1) * WW);
 #pragma unroll
         for (int j = 0; j < JT; ++j) {
             const int mt = wave + 4 * j;
             if (mt < MT && mrow < NS)
-                *(f4 *)(dz + mrow * WW + mt * 16 + 4 * q) = accz[j];
+                *(v4 *)(dz + mrow * WW + mt * 16 + 4 * q) = accz[j];
         }
         return;
     }
-    float *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
+    real *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
     auto wsync = []() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
+    constexpr int NTAP = MTB * 16;                       // taps of this block's M tiles
+    const int ntap = min(NTAP, WW - mt0 * 16);           // (the last block's may be fewer)
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int oz = wave + 4 * s;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                fl[(mt * 16 + 4 * q + i) * 17 + mrow] = acc[s][mt][i];
+                fl[(mt * 16 + out_row<real>(q, i)) * 17 + mrow] = acc[s][mt][i];
         wsync();
-        float *ds = dst + (int64_t)oz * WW * 16;
-        for (int idx = lane; idx < WW * 4; idx += 64) {
+        real *ds = dst + ((int64_t)oz * WW + mt0 * 16) * 16;
+        for (int idx = lane; idx < ntap * 4; idx += 64) {
             const int tap = idx >> 2, r4 = (idx & 3) * 4;
-            const float *src = fl + tap * 17 + r4;
-            *(f4 *)(ds + tap * 16 + r4) = f4{src[0], src[1], src[2], src[3]};
+            const real *src = fl + tap * 17 + r4;
+            *(v4 *)(ds + tap * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
         }
         wsync();
     }
     if (NS > W) {
 #pragma unroll
         for (int j = 0; j < XT; ++j) {
-            const int mt = wave + 4 * j;
-            if (mt >= MT)
+            const int mt = mt0 + wave + 4 * j;
+            if (wave + 4 * j >= MTB || mt >= MT)
                 break;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                fl[(4 * q + i) * 17 + mrow] = accx[j][i];
+                fl[out_row<real>(q, i) * 17 + mrow] = accx[j][i];
             wsync();
             const int tap = lane >> 2, r4 = (lane & 3) * 4;
-            const float *src = fl + tap * 17 + r4;
-            *(f4 *)(dst + ((int64_t)W * WW + mt * 16 + tap) * 16 + r4) = f4{src[0], src[1], src[2], src[3]};
+            const real *src = fl + tap * 17 + r4;
+            *(v4 *)(dst + ((int64_t)W * WW + mt * 16 + tap) * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
             wsync();
         }
     }
@@ -1103,19 +1117,36 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st)
 
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
-    if (E.precision != ADDK_FP32 || !E.ndense_sp[3][wi] || !E.scratch[wi])
+    if (!E.ndense_sp[3][wi] || !E.scratch[wi])
         return false;
+    const Chunk *items = E.d_dense_sp[3][wi];
+    if (E.precision == ADDK_FP64) {  // 16 RHS columns, the M tiles split over two blocks
+        if (R == 1)
+            return false;
+        double *scratch = (double *)E.scratch[wi];
+        dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16, 2);
+        if (wi == 0)
+            hipLaunchKernelGGL((k_spread_mfma<double, 8, false, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
+                               scratch);
+        else
+            hipLaunchKernelGGL((k_spread_mfma<double, 12, false, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, io,
+                               R, scratch);
+        return true;
+    }
     float *scratch = (float *)E.scratch[wi];
     dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16);
-    const Chunk *items = E.d_dense_sp[3][wi];
     if (wi == 0 && R == 1)
-        hipLaunchKernelGGL((k_spread_mfma<8, true>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+        hipLaunchKernelGGL((k_spread_mfma<float, 8, true, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
+                           scratch);
     else if (wi == 0)
-        hipLaunchKernelGGL((k_spread_mfma<8, false>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+        hipLaunchKernelGGL((k_spread_mfma<float, 8, false, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
+                           scratch);
     else if (R == 1)
-        hipLaunchKernelGGL((k_spread_mfma<12, true>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+        hipLaunchKernelGGL((k_spread_mfma<float, 12, true, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
+                           scratch);
     else
-        hipLaunchKernelGGL((k_spread_mfma<12, false>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+        hipLaunchKernelGGL((k_spread_mfma<float, 12, false, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
+                           scratch);
     return true;
 }
 
