@@ -455,8 +455,9 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 5 : 2) void k_interp_mf
 // flush writes the block with one value per tap (the gather's one-RHS layout).
 // MS: the x-y taps' M tiles (16 taps each) are split over MS blocks
 // (blockIdx.z), each owning MTB consecutive tiles of every slab; FP64 uses
-// MS = 2 so that the accumulators (twice the registers of FP32) stay in the
-// register file, at the price of evaluating each point's window values twice.
+// MS = 2 or 3 so that the accumulators (twice the registers of FP32) stay in
+// the register file, at the price of evaluating each point's window values
+// MS times.
 template <typename real, int W, bool Z1, int MS>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
                                                         IoArgs io, int R, real *__restrict__ scratch)
@@ -1120,17 +1121,19 @@ bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
     if (!E.ndense_sp[3][wi] || !E.scratch[wi])
         return false;
     const Chunk *items = E.d_dense_sp[3][wi];
-    if (E.precision == ADDK_FP64) {  // 16 RHS columns, the M tiles split over two blocks
+    if (E.precision == ADDK_FP64) {  // 16 RHS columns, the M tiles split over blocks
         if (R == 1)
             return false;
         double *scratch = (double *)E.scratch[wi];
-        dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16, 2);
+        // 2m = 8: 4 M tiles over two blocks; 2m = 12: 9 over three (measured on
+        // the large workload: 14.4 ms with two blocks, 11.0 with three, 15.7
+        // with five)
         if (wi == 0)
-            hipLaunchKernelGGL((k_spread_mfma<double, 8, false, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
-                               scratch);
+            hipLaunchKernelGGL((k_spread_mfma<double, 8, false, 2>), dim3(E.ndense_sp[3][wi], (R + 15) / 16, 2),
+                               dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
         else
-            hipLaunchKernelGGL((k_spread_mfma<double, 12, false, 2>), grid, dim3(kBlock), 0, st, E.d_wins, items, io,
-                               R, scratch);
+            hipLaunchKernelGGL((k_spread_mfma<double, 12, false, 3>), dim3(E.ndense_sp[3][wi], (R + 15) / 16, 3),
+                               dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
         return true;
     }
     float *scratch = (float *)E.scratch[wi];
