@@ -83,6 +83,7 @@ struct WinDev {
     double nf_hl;        // (data units per grid unit) / l: r / l = sqrt(d2) * nf_hl
     double nf_a[kNearQ + 1], nf_ad[kNearQ + 1];  // even polynomials in (r / eps) of kernel and derivative kernel
     const int32_t *tile_off;  // tile t's points are [tile_off[t], tile_off[t + 1]) of the sorted order
+    const int2 *sp_rng;       // d = 3: {first, count} of tile t's sparsely populated cells' points (sources)
     double *nf_ys;            // [2][N] close-pair sums by sorted position (zero between calls)
 };
 
@@ -191,6 +192,10 @@ struct Engine {
     uint32_t knobs = ADDK_KNOB_ALL_MFMA;  // matrix-core variant per stage (ADDK_KNOB_*)
     bool tuned = false;            // knobs chosen by measurement: no R threshold
     int2 *d_dmap[2] = {nullptr, nullptr};        // base-cell maps of all windows (per 2m = 8, 12)
+    int2 *d_sprng = nullptr;                     // sparse point ranges per tile, all d = 3 windows (WinDev::sp_rng)
+    LineGroup *d_sptiles[2] = {nullptr, nullptr};  // output tiles of the sparse spread (per 2m = 8, 12)
+    int nsptiles[2] = {0, 0};
+    bool sparse_gather = false;  // d = 3 sparse spread by output tiles (k_spread_sparse_mfma)
     LineGroup *d_gtiles[2] = {nullptr, nullptr};  // output tiles of the dense block gather
     int ngtiles[2] = {0, 0};
     void *scratch[2] = {nullptr, nullptr};        // per-item dense spread blocks (engine precision, d = 3)
@@ -289,6 +294,7 @@ bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
 void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st);
 bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st);
+void launch_spread_sparse_mfma(Engine &E, int R, IoArgs io, hipStream_t st);
 
 // nearfield.hip (ADDK_NEAR_FIELD)
 void launch_near(Engine &E, int R, int nout, IoArgs io, hipStream_t st);

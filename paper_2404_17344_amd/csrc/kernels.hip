@@ -1059,6 +1059,7 @@ void engine_free(Engine &E)
     for (int wi = 0; wi < 2; ++wi) {
         free_dev(E.d_dmap[wi]);
         free_dev(E.d_gtiles[wi]);
+        free_dev(E.d_sptiles[wi]);
         free_dev(E.scratch[wi]);
     }
     free_dev(E.vpack);
@@ -1072,6 +1073,8 @@ void engine_free(Engine &E)
     E.d_near_part = nullptr;
     free_dev(E.d_near_ys);
     E.d_near_ys = nullptr;
+    free_dev(E.d_sprng);
+    E.d_sprng = nullptr;
     E.near_part_cap = 0;
     for (const ProfRec &r : E.recs) {
         (void)hipEventDestroy(r.a);
@@ -1303,6 +1306,84 @@ addk_status engine_build_device(Engine &E, int precision)
         for (size_t w = 0; w < E.wdev.size(); ++w)
             if (moff[w] >= 0)
                 E.wdev[w].dmap = E.d_dmap[wi] + moff[w];
+    }
+    // Sparse spread of d = 3 windows by output tiles (4^3 grid cells each):
+    // per window, the range of every point tile's sparse points and the list
+    // of output tiles that such points reach.  Used when every d = 3 window
+    // with sparse points has 4^3-cell point tiles and 2m in {8, 12}.
+    {
+        free_dev(E.d_sprng);
+        E.d_sprng = nullptr;
+        for (int wi = 0; wi < 2; ++wi) {
+            free_dev(E.d_sptiles[wi]);
+            E.d_sptiles[wi] = nullptr;
+            E.nsptiles[wi] = 0;
+        }
+        for (WinDev &d : E.wdev)
+            d.sp_rng = nullptr;
+        bool ok = true;
+        int64_t ntot = 0;
+        std::vector<int64_t> roff(E.wdev.size(), -1);
+        for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
+            const WinDev &d = E.wdev[wi];
+            const WinHost &h = E.plans[E.wplan[wi]]->wins[E.wlocal[wi]];
+            if (d.d != 3 || h.chunks.empty())
+                continue;
+            if (d.tb[0] != 4 || d.tb[1] != 4 || d.tb[2] != 4 || (d.W != 8 && d.W != 12))
+                ok = false;
+            roff[wi] = ntot;
+            ntot += (int64_t)d.ntile[0] * d.ntile[1] * d.ntile[2];
+        }
+        E.sparse_gather = ok && ntot > 0;
+        if (E.sparse_gather) {
+            std::vector<int2> rng(ntot, make_int2(0, 0));
+            std::vector<LineGroup> lists[2];
+            for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
+                if (roff[wi] < 0)
+                    continue;
+                const WinDev &d = E.wdev[wi];
+                const WinHost &h = E.plans[E.wplan[wi]]->wins[E.wlocal[wi]];
+                int2 *r = rng.data() + roff[wi];
+                for (const Chunk &c : h.chunks) {  // the sources' sparse chunks, consecutive per tile
+                    if (r[c.tile].y == 0)
+                        r[c.tile].x = c.start;
+                    r[c.tile].y += c.count;
+                }
+                const int ot[3] = {(d.ext[0] + 3) / 4, (d.ext[1] + 3) / 4, (d.ext[2] + 3) / 4};
+                const int reach = (d.W + 2) / 4;  // a point tile reaches output tiles tp .. tp + reach
+                std::vector<char> mark((size_t)ot[0] * ot[1] * ot[2], 0);
+                for (int tz = 0; tz < d.ntile[2]; ++tz)
+                    for (int ty = 0; ty < d.ntile[1]; ++ty)
+                        for (int tx = 0; tx < d.ntile[0]; ++tx) {
+                            if (r[((int64_t)tz * d.ntile[1] + ty) * d.ntile[0] + tx].y == 0)
+                                continue;
+                            for (int oz = tz; oz <= std::min(ot[2] - 1, tz + reach); ++oz)
+                                for (int oy = ty; oy <= std::min(ot[1] - 1, ty + reach); ++oy)
+                                    for (int ox = tx; ox <= std::min(ot[0] - 1, tx + reach); ++ox)
+                                        mark[((size_t)oz * ot[1] + oy) * ot[0] + ox] = 1;
+                        }
+                for (size_t t = 0; t < mark.size(); ++t)
+                    if (mark[t])
+                        lists[d.W == 8 ? 0 : 1].push_back({(int)wi, (int)t});
+            }
+            hipError_t e = hipMalloc(&E.d_sprng, ntot * sizeof(int2));
+            if (e == hipSuccess)
+                e = hipMemcpy(E.d_sprng, rng.data(), ntot * sizeof(int2), hipMemcpyHostToDevice);
+            for (int wi = 0; wi < 2 && e == hipSuccess; ++wi) {
+                E.nsptiles[wi] = (int)lists[wi].size();
+                if (lists[wi].empty())
+                    continue;
+                e = hipMalloc(&E.d_sptiles[wi], lists[wi].size() * sizeof(LineGroup));
+                if (e == hipSuccess)
+                    e = hipMemcpy(E.d_sptiles[wi], lists[wi].data(), lists[wi].size() * sizeof(LineGroup),
+                                  hipMemcpyHostToDevice);
+            }
+            if (e != hipSuccess)
+                return hip_fail(e, "sparse spread lists");
+            for (size_t wi = 0; wi < E.wdev.size(); ++wi)
+                if (roff[wi] >= 0)
+                    E.wdev[wi].sp_rng = E.d_sprng + roff[wi];
+        }
     }
     for (int s = 0; s < ST_COUNT; ++s) {
         E.ngroups[s] = (int)gr[s].size();
@@ -1597,6 +1678,10 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         if (!E.nchunks[d])
             continue;
         StageTimer t(E, PS_SPREAD, st);
+        if (d == 3 && E.sparse_gather && !E.no_mfma) {
+            launch_spread_sparse_mfma(E, R, io, st);
+            continue;
+        }
         if (launch_spread_tile(E, d, R, io, st))
             continue;
         if (d == 1) launch_spread<real, 1>(E, R, io, st);

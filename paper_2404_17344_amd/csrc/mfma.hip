@@ -732,6 +732,151 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Sparse spread (d = 3, points of sparsely populated cells), by output tiles:
+// one block per 4 x 4 x 4 tile of grid cells and 16 RHS computes
+//   G[cell][r] = sum over the sparse points p whose window reaches the tile
+//                of wx(p, x) wy(p, y) wz(p, z) V[p][r]
+// as a matrix product D[16 cells of a z layer][16 RHS] += A[cells][4 points]
+// B[4 points][RHS] per wave (wave = z layer), with window values of zero for
+// cells outside a point's 2m taps.  The points come from the NT^3 point tiles
+// (4^3 base cells each) that can reach the tile, in rounds of 64.  Every grid
+// value is written once, by one lane: no atomics, and the sum order is fixed.
+// The grid holds the sum when the dense-cell blocks are added (the gather
+// reads it).
+template <typename real, int W>
+__global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__restrict__ wins,
+                                                               const LineGroup *__restrict__ tiles, IoArgs io, int R)
+{
+    typedef typename MfmaT<real>::v4 v4;
+    typedef typename MfmaT<real>::v2 v2;
+    constexpr int NT = (W + 2) / 4 + 1;  // point tiles per dimension that reach an output tile
+    constexpr int NT3 = NT * NT * NT;
+    constexpr int PB = 64;               // points per round (16 K steps)
+    __shared__ int pre[NT3 + 1];
+    __shared__ int2 rng[NT3];
+    __shared__ real pw[PB][3][4];        // window values at the tile's 4 cells per dimension
+    __shared__ __align__(16) real pv[PB][16];
+    const LineGroup g = tiles[blockIdx.x];
+    const WinDev &w = wins[g.win];
+    const int r0 = blockIdx.y * 16;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int q = lane >> 4, mrow = lane & 15;
+    const int otx = (w.ext[0] + 3) >> 2, oty = (w.ext[1] + 3) >> 2;
+    const int to[3] = {g.grp % otx, (g.grp / otx) % oty, g.grp / (otx * oty)};
+    if (t < NT3) {
+        const int tx = to[0] - (NT - 1) + t % NT, ty = to[1] - (NT - 1) + (t / NT) % NT,
+                  tz = to[2] - (NT - 1) + t / (NT * NT);
+        int2 r = make_int2(0, 0);
+        if (tx >= 0 && ty >= 0 && tz >= 0 && tx < w.ntile[0] && ty < w.ntile[1] && tz < w.ntile[2])
+            r = w.sp_rng[((int64_t)tz * w.ntile[1] + ty) * w.ntile[0] + tx];
+        rng[t] = r;
+    }
+    __syncthreads();
+    if (t == 0) {
+        pre[0] = 0;
+        for (int i = 0; i < NT3; ++i)
+            pre[i + 1] = pre[i] + rng[i].y;
+    }
+    __syncthreads();
+    const int total = pre[NT3];
+    const real *coords = (const real *)w.coords;
+    const ProbDev pio = get_prob_m(io, w.prob);
+    const real *Vp = (const real *)pio.Vp;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    // staging: thread (pi = t / 4, k = t % 4) loads RHS 4k .. 4k + 3 of point pi
+    // and, for k < 3, the point's window values along dimension k at the
+    // tile's four cells
+    const int pi = t >> 2, kq = t & 3;
+    v4 acc[2];
+    acc[0] = acc[1] = v4{real(0), real(0), real(0), real(0)};
+    for (int p0 = 0; p0 < total; p0 += PB) {
+        const int f = p0 + pi;
+        real v[4] = {real(0), real(0), real(0), real(0)};
+        real wk[4] = {real(0), real(0), real(0), real(0)};
+        if (f < total) {
+            int lo = 0, hi = NT3 - 1;  // last tile k with pre[k] <= f
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= f)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int j = rng[lo].x + (f - pre[lo]);
+            const int64_t orig = w.perm[j];
+            const real *vr = Vp + orig * pio.ldvp + r0 + 4 * kq;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                v[i] = vr[i];
+            if (kq < 3) {
+                const real u = coords[(int64_t)kq * w.N + j];
+                const int b = (int)floor(u) - w.m + 1;  // the point's first cell
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = 4 * to[kq] + i;
+                    wk[i] = (unsigned)(c - b) < (unsigned)W ? kb_psi_m(u - (real)c, mm, kb, ie) : real(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            pv[pi][4 * kq + i] = r0 + 4 * kq + i < R ? v[i] : real(0);
+            if (kq < 3)
+                pw[pi][kq][i] = wk[i];
+        }
+        __syncthreads();
+        const int np = min(PB, total - p0);
+#pragma unroll
+        for (int ks = 0; ks < PB / 4; ++ks) {
+            if (4 * ks >= np)
+                break;
+            const int pk = 4 * ks + q;
+            // A[cell mrow of layer `wave`][point pk], B[point pk][RHS mrow]
+            const real a = pw[pk][0][mrow & 3] * pw[pk][1][mrow >> 2] * pw[pk][2][wave];
+            acc[ks & 1] = mfma4(a, pv[pk][mrow], acc[ks & 1]);
+        }
+        __syncthreads();
+    }
+    const v4 sum = acc[0] + acc[1];
+    const int r = r0 + mrow;
+    if (r >= R)
+        return;
+    real *G = (real *)w.G;
+    const int z = 4 * to[2] + wave;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int cell = out_row<real>(q, i);
+        const int x = 4 * to[0] + (cell & 3), y = 4 * to[1] + (cell >> 2);
+        if (x < w.ext[0] && y < w.ext[1] && z < w.ext[2])
+            G[((int64_t)(r >> 1) * w.szG + ((int64_t)z * w.ext[1] + y) * w.ext[0] + x) * 2 + (r & 1)] = sum[i];
+    }
+}
+
+void launch_spread_sparse_mfma(Engine &E, int R, IoArgs io, hipStream_t st)
+{
+    for (int wi = 0; wi < 2; ++wi) {
+        if (!E.nsptiles[wi])
+            continue;
+        const dim3 grid(E.nsptiles[wi], (R + 15) / 16);
+        if (E.precision == ADDK_FP32) {
+            if (wi == 0)
+                hipLaunchKernelGGL((k_spread_sparse_mfma<float, 8>), grid, dim3(kBlock), 0, st, E.d_wins,
+                                   E.d_sptiles[wi], io, R);
+            else
+                hipLaunchKernelGGL((k_spread_sparse_mfma<float, 12>), grid, dim3(kBlock), 0, st, E.d_wins,
+                                   E.d_sptiles[wi], io, R);
+        } else {
+            if (wi == 0)
+                hipLaunchKernelGGL((k_spread_sparse_mfma<double, 8>), grid, dim3(kBlock), 0, st, E.d_wins,
+                                   E.d_sptiles[wi], io, R);
+            else
+                hipLaunchKernelGGL((k_spread_sparse_mfma<double, 12>), grid, dim3(kBlock), 0, st, E.d_wins,
+                                   E.d_sptiles[wi], io, R);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sum the per-item blocks into the spread grid.  A block owns a 4 x 4 x 4 tile
 // of grid cells and 16 RHS; it visits, in a fixed order, every base cell whose
 // (2m)^3 window block overlaps the tile and adds the overlapping part of each

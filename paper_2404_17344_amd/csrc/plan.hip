@@ -30,6 +30,8 @@
 #include <string>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "addk_internal.h"
 
 namespace addk {
@@ -333,16 +335,31 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
     }
 }
 
+// Place the points in their sorted positions.  (ks, js) are the (key, index)
+// pairs sorted by key with a stable radix sort, so the points of one key come
+// in increasing index order; the point at sorted rank idx goes to off[k] plus
+// its rank among its key's points, idx - kstart[k] (kstart: exclusive prefix
+// sum of the key counts in key order; off: the key's first position in the
+// plan's order).  The result does not depend on scheduling.
 template <typename real>
-__global__ void k_scatter(int64_t N, int d, const real *__restrict__ ucoord, const int32_t *__restrict__ key,
-                          int32_t *cursor, real *sorted, int32_t *perm)
+__global__ void k_place(int64_t N, int d, const real *__restrict__ ucoord, const uint32_t *__restrict__ ks,
+                        const int32_t *__restrict__ js, const int32_t *__restrict__ off,
+                        const int32_t *__restrict__ kstart, real *sorted, int32_t *perm)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
-        const int pos = atomicAdd(&cursor[key[j]], 1);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < N; idx += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = ks[idx];
+        const int32_t j = js[idx];
+        const int64_t pos = off[k] + (idx - kstart[k]);
         for (int dd = 0; dd < d; ++dd)
             sorted[dd * N + pos] = ucoord[dd * N + j];
-        perm[pos] = (int32_t)j;
+        perm[pos] = j;
     }
+}
+
+__global__ void k_iota(int32_t *a, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = (int32_t)i;
 }
 
 // Continuous Fourier transform of the kernel (der = 0) or of its derivative
@@ -999,22 +1016,59 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
         if (e != hipSuccess)
             return hip_fail(e, "near-field tile ranges");
     }
-    e = hipMemcpy(hist, offall.data(), nseg * nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
+    // stable sort of (key, index) pairs, then placement (deterministic)
+    std::vector<int32_t> kstart(nseg * nkeys, 0);
+    for (int64_t k = 1; k < nseg * nkeys; ++k)
+        kstart[k] = kstart[k - 1] + hall[k - 1];
+    int32_t *dkstart = nullptr, *js_in = nullptr, *js_out = nullptr;
+    uint32_t *ks_out = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int end_bit = 1;
+    while (end_bit < 32 && ((int64_t)1 << end_bit) < nseg * nkeys)
+        ++end_bit;
+    auto release = [&]() {
+        (void)hipFree(ucoord);
+        (void)hipFree(key);
+        (void)hipFree(hist);
+        (void)hipFree(bad);
+        (void)hipFree(dkstart);
+        (void)hipFree(js_in);
+        (void)hipFree(js_out);
+        (void)hipFree(ks_out);
+        (void)hipFree(tmp);
+    };
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (const uint32_t *)key, ks_out, js_in, js_out, (int)N, 0,
+                                           end_bit, st);
+    if (e == hipSuccess && ((e = hipMalloc(&dkstart, nseg * nkeys * sizeof(int32_t))) != hipSuccess ||
+                            (e = hipMalloc(&js_in, N * sizeof(int32_t))) != hipSuccess ||
+                            (e = hipMalloc(&js_out, N * sizeof(int32_t))) != hipSuccess ||
+                            (e = hipMalloc(&ks_out, N * sizeof(uint32_t))) != hipSuccess ||
+                            (e = hipMalloc(&tmp, std::max<size_t>(tmp_bytes, 16))) != hipSuccess)) {
+        release();
+        return fail(ADDK_ERR_OOM, "sort buffers allocation failed");
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(hist, offall.data(), nseg * nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(dkstart, kstart.data(), nseg * nkeys * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_iota, dim3(nb), dim3(256), 0, st, js_in, N);
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, (const uint32_t *)key, ks_out, js_in, js_out, (int)N, 0,
+                                               end_bit, st);
+    }
+    if (e == hipSuccess) {
+        if (pl.precision == ADDK_FP32)
+            hipLaunchKernelGGL(k_place<float>, dim3(nb), dim3(256), 0, st, N, w.d, (const float *)ucoord, ks_out,
+                               js_out, hist, dkstart, (float *)w.coords, w.perm);
+        else
+            hipLaunchKernelGGL(k_place<double>, dim3(nb), dim3(256), 0, st, N, w.d, (const double *)ucoord, ks_out,
+                               js_out, hist, dkstart, (double *)w.coords, w.perm);
+        e = hipStreamSynchronize(st);
+    }
+    release();
     if (e != hipSuccess)
-        return hip_fail(e, "hipMemcpy(offsets)");
-    if (pl.precision == ADDK_FP32)
-        hipLaunchKernelGGL(k_scatter<float>, dim3(nb), dim3(256), 0, st, N, w.d, (const float *)ucoord, key, hist,
-                           (float *)w.coords, w.perm);
-    else
-        hipLaunchKernelGGL(k_scatter<double>, dim3(nb), dim3(256), 0, st, N, w.d, (const double *)ucoord, key, hist,
-                           (double *)w.coords, w.perm);
-    e = hipStreamSynchronize(st);
-    (void)hipFree(ucoord);
-    (void)hipFree(key);
-    (void)hipFree(hist);
-    (void)hipFree(bad);
-    if (e != hipSuccess)
-        return hip_fail(e, "tile scatter");
+        return hip_fail(e, "tile sort");
     return ADDK_OK;
 }
 

@@ -47,8 +47,8 @@ def test_uneven_batch_full_size_graph_autotuned(A):
     knobs = B.autotune(reps=2)
     assert 0 <= knobs <= A.ADDK_KNOB_ALL_MFMA
     # Replays and eager runs agree to FP32 rounding (within the FP32 tolerance):
-    # the d = 1, 2 dense-cell and the sparse-tile spreads sum with atomics, so
-    # the FP32 summation order varies run to run.  A graph that reused stale
+    # the d = 1, 2 spreads sum with atomics, so the FP32 summation order of
+    # those windows varies run to run (d = 3 windows are bitwise reproducible).  A graph that reused stale
     # buffers would be off by O(1).
     B.launch()
     torch.cuda.synchronize()
