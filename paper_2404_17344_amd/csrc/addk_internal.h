@@ -178,6 +178,7 @@ struct Engine {
     int ndense[4][2] = {};
     Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)
     int ndense_sp[4][2] = {};
+    int ndense_sp2[2] = {};        // d = 3: the two-cell items, which lead each spread item list
     int fft_L = 16;                // lines per FFT block (halved when some window's grid exceeds 128)
     int nos_max = 16;              // largest oversampled grid edge of the engine's windows
     Chunk *d_near[4] = {};         // near-field target blocks per d (tile field = tile index)

@@ -1238,6 +1238,14 @@ addk_status engine_build_device(Engine &E, int precision)
                 return s;
         }
     }
+    // d = 3 spread items: two-cell items first (stable, so that the items of one
+    // anchor cell stay consecutive), each part spread by its own kernel variant
+    for (int wi = 0; wi < 2; ++wi) {
+        std::vector<Chunk> &v = dsp[3][wi];
+        auto two = [](const Chunk &c) { return ((c.tile >> 30) & 1) != 0; };
+        std::stable_partition(v.begin(), v.end(), two);
+        E.ndense_sp2[wi] = (int)std::count_if(v.begin(), v.end(), two);
+    }
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
             addk_status s = upload_items(dn[d][wi], E.d_dense[d][wi], E.ndense[d][wi]);
@@ -1338,6 +1346,7 @@ addk_status engine_build_device(Engine &E, int precision)
         if (E.sparse_gather) {
             std::vector<int2> rng(ntot, make_int2(0, 0));
             std::vector<LineGroup> lists[2];
+            std::vector<std::pair<int64_t, LineGroup>> work[2];
             for (size_t wi = 0; wi < E.wdev.size(); ++wi) {
                 if (roff[wi] < 0)
                     continue;
@@ -1351,20 +1360,33 @@ addk_status engine_build_device(Engine &E, int precision)
                 }
                 const int ot[3] = {(d.ext[0] + 3) / 4, (d.ext[1] + 3) / 4, (d.ext[2] + 3) / 4};
                 const int reach = (d.W + 2) / 4;  // a point tile reaches output tiles tp .. tp + reach
-                std::vector<char> mark((size_t)ot[0] * ot[1] * ot[2], 0);
+                std::vector<int64_t> load((size_t)ot[0] * ot[1] * ot[2], -1);  // points reaching a tile
                 for (int tz = 0; tz < d.ntile[2]; ++tz)
                     for (int ty = 0; ty < d.ntile[1]; ++ty)
                         for (int tx = 0; tx < d.ntile[0]; ++tx) {
-                            if (r[((int64_t)tz * d.ntile[1] + ty) * d.ntile[0] + tx].y == 0)
+                            const int cnt = r[((int64_t)tz * d.ntile[1] + ty) * d.ntile[0] + tx].y;
+                            if (cnt == 0)
                                 continue;
                             for (int oz = tz; oz <= std::min(ot[2] - 1, tz + reach); ++oz)
                                 for (int oy = ty; oy <= std::min(ot[1] - 1, ty + reach); ++oy)
-                                    for (int ox = tx; ox <= std::min(ot[0] - 1, tx + reach); ++ox)
-                                        mark[((size_t)oz * ot[1] + oy) * ot[0] + ox] = 1;
+                                    for (int ox = tx; ox <= std::min(ot[0] - 1, tx + reach); ++ox) {
+                                        int64_t &l = load[((size_t)oz * ot[1] + oy) * ot[0] + ox];
+                                        l = (l < 0 ? 0 : l) + cnt;
+                                    }
                         }
-                for (size_t t = 0; t < mark.size(); ++t)
-                    if (mark[t])
-                        lists[d.W == 8 ? 0 : 1].push_back({(int)wi, (int)t});
+                for (size_t t = 0; t < load.size(); ++t)
+                    if (load[t] >= 0)
+                        work[d.W == 8 ? 0 : 1].push_back({load[t], LineGroup{(int)wi, (int)t}});
+            }
+            // heaviest tiles first (the points per tile vary by two orders of
+            // magnitude near the dense core): the last blocks to start are short
+            for (int k = 0; k < 2; ++k) {
+                std::stable_sort(work[k].begin(), work[k].end(),
+                                 [](const std::pair<int64_t, LineGroup> &a, const std::pair<int64_t, LineGroup> &b) {
+                                     return a.first > b.first;
+                                 });
+                for (const auto &pw : work[k])
+                    lists[k].push_back(pw.second);
             }
             hipError_t e = hipMalloc(&E.d_sprng, ntot * sizeof(int2));
             if (e == hipSuccess)

@@ -449,23 +449,32 @@ __global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 5 : 2) void k_interp_mf
 // Dense spread: one block per spread item (one or two dense cells) and 16 RHS;
 // the item's (2m)^2 x (2m + 1) block is written to its scratch slot and summed
 // into the grid by k_gather_blocks.
+// The x-y taps of a z-slab are tiled as 4 x 4 squares: M tile (tx, ty) holds
+// the taps x = 4 tx + (row & 3), y = 4 ty + (row >> 2), so the A operand of
+// lane (q, mrow), wx(x) wy(y), is the product of one of 2m / 4 x weights and
+// one of 2m / 4 y weights of point 4 ks + q; both come straight from the
+// round's window table in LDS (no product table, one barrier per round).
 // Z1 (one RHS, FP32): the 2m + 1 z-slabs take the N dimension instead of the
 // RHS, D[16 taps][16 slabs] += A[taps][4 points] B[4 points][slabs] with
-// B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block, and the
-// flush writes the block with one value per tap (the gather's one-RHS layout).
-// MS: the x-y taps' M tiles (16 taps each) are split over MS blocks
-// (blockIdx.z), each owning MTB consecutive tiles of every slab; FP64 uses
-// MS = 2 or 3 so that the accumulators (twice the registers of FP32) stay in
-// the register file, at the price of evaluating each point's window values
-// MS times.
-template <typename real, int W, bool Z1, int MS>
+// B = v wz(slab); wave w owns the M tiles w + 4 j of the whole block (linear
+// tap order), and the flush writes the block with one value per tap (the
+// gather's one-RHS layout).
+// MS: the M tiles are split over MS blocks (blockIdx.z), each owning MTB
+// consecutive tiles (whole rows of squares) of every slab; FP64 uses MS = 2
+// or 3 so that the accumulators (twice the registers of FP32) stay in the
+// register file, at the price of evaluating each point's window values MS
+// times.
+template <typename real, int W, bool Z1, int MS, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict__ wins, const Chunk *__restrict__ items,
-                                                        IoArgs io, int R, real *__restrict__ scratch)
+                                                        int item0, IoArgs io, int R, real *__restrict__ scratch)
 {
     typedef typename MfmaT<real>::v4 v4;
     constexpr int WW = W * W;
+    constexpr int NX = W / 4;          // squares per row of taps
     constexpr int MT = WW / 16;        // M tiles (16 taps) per z-slab
     constexpr int MTB = (MT + MS - 1) / MS;  // M tiles of this block
+    static_assert(Z1 || MTB * MS == MT && MTB % NX == 0, "blocks own whole rows of squares");
+    constexpr int NYB = Z1 ? 1 : MTB / NX;  // rows of squares of this block
     constexpr int SPW = W / 4;         // z-slabs per wave: slabs wave + 4 s, s < SPW (the first 2m)
     constexpr int XT = (MTB + 3) / 4;  // M tiles per wave of slab 2m (two-cell items only)
     constexpr int PB = sizeof(real) == 4 ? 32 : 16;  // points per round (PB / 4 K steps)
@@ -473,7 +482,6 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     constexpr int FL = MTB * 16 * 17;  // per-wave flush tile [tap][16 RHS + 1 pad]
     constexpr int PS = 3 * W + 1;     // window values per point: x [W], y [W], z [W + 1] (item slabs)
     struct Round {
-        real pxy[PB][WW];
         real pw[PB][PS];
         real pv[PB][16];
     };
@@ -482,18 +490,21 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     __shared__ __align__(16) unsigned char lds[RB_BYTES > FL_BYTES ? RB_BYTES : FL_BYTES];
     Round *rd = (Round *)lds;
 
-    const Chunk it = items[blockIdx.x];
+    const int ii = item0 + (int)blockIdx.x;  // the item (and its scratch slot)
+    const Chunk it = items[ii];
     const WinDev &w = wins[it.win];
     const int r0 = blockIdx.y * 16;
     if (r0 >= R)
         return;
     const int mt0 = MS > 1 ? (int)blockIdx.z * MTB : 0;  // first M tile of this block
+    const int ty0 = mt0 / NX;                              // its first row of squares
     int bx, by, bz, nzc;
     unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int NS = W + nzc - 1;  // z-slabs of the item's block
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: slab branches are scalar
     const int q = lane >> 4, mrow = lane & 15;
+    const int xi = mrow & 3, yi = mrow >> 2;  // the lane's tap within a square
     const real *coords = (const real *)w.coords;
     const ProbDev pio = get_prob_m(io, w.prob);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
@@ -553,12 +564,6 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             d.pv[e >> 4][e & 15] = pvv[k];
         }
     };
-    auto products = [&](Round &d) {
-        for (int e = t; e < PB * WW; e += kBlock) {
-            const int p = e / WW, c = e - p * WW;
-            d.pxy[p][c] = d.pw[p][c % W] * d.pw[p][W + c / W];
-        }
-    };
 
     // wave `wave` owns slabs wave + 4 s of the first 2m and, for two-cell
     // items, the M tiles mt0 + wave + 4 j of slab 2m (Z1: the M tiles wave + 4 j
@@ -578,24 +583,27 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     for (int j = 0; j < (Z1 ? JT : 1); ++j)
         accz[j] = zero4;
 
-    // Z1 forms the x-y products of its few matrix ops on the fly (no products
-    // phase): lane mrow's tap of M tile wave + 4 j is (x, y) = (zx[j], zy[j] - W)
-    int zx[JT], zy[JT];
+    // Z1: lane mrow's tap of M tile wave + 4 j is (x, y) = (zx[j], zy[j] - W)
+    // (linear tap order).  Otherwise: the x and y window-table entries of the
+    // lane's A operand in the slab-2m tiles mt0 + wave + 4 j (squares).
+    int zx[Z1 ? JT : XT], zy[Z1 ? JT : XT];
 #pragma unroll
-    for (int j = 0; j < JT; ++j) {
-        const int c = min((wave + 4 * j) * 16 + mrow, WW - 1);
-        zx[j] = c % W;
-        zy[j] = W + c / W;
+    for (int j = 0; j < (Z1 ? JT : XT); ++j) {
+        if constexpr (Z1) {
+            const int c = min((wave + 4 * j) * 16 + mrow, WW - 1);
+            zx[j] = c % W;
+            zy[j] = W + c / W;
+        } else {
+            const int mt = min(mt0 + wave + 4 * j, MT - 1);
+            zx[j] = 4 * (mt % NX) + xi;
+            zy[j] = W + 4 * (mt / NX) + yi;
+        }
     }
     load(0);
     store_raw(rd[0], 0);
     if (PB < it.count)
         load(PB);  // the registers run one round ahead of the window values
     __syncthreads();
-    if constexpr (!Z1) {
-        products(rd[0]);
-        __syncthreads();
-    }
     int buf = 0;
     for (int p0 = 0; p0 < it.count; p0 += PB) {
         const bool more = p0 + PB < it.count;
@@ -622,26 +630,32 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 }
             }
         } else {
-        // Operands of one K step (four points): A = x-y weight products of the
-        // M tiles, and the B factors (RHS value, z weights of the wave's slabs).
-        // The next step's operands are read from LDS before this step's
-        // matrix ops issue, so the reads overlap them.
+        // Operands of one K step (four points): the lane's x weights (one per
+        // column of squares) and y weights (one per row of squares of this
+        // block), the slab-2m A values, and the B factors (RHS value, z
+        // weights of the wave's slabs).  The next step's operands are read
+        // from LDS before this step's matrix ops issue, so the reads overlap
+        // them.
         struct Ops {
-            real a[MTB], ax[XT], v, wz[SPW + 1];
+            real wx[NX], wy[NYB], ax[XT], v, wz[SPW + 1];
         };
         auto fetch = [&](int ks, Ops &o) {
             const int pk = 4 * ks + q;
+            const real *pw = cr.pw[pk];
 #pragma unroll
-            for (int mt = 0; mt < MTB; ++mt)
-                o.a[mt] = cr.pxy[pk][min(mt0 + mt, MT - 1) * 16 + mrow];
+            for (int i = 0; i < NX; ++i)
+                o.wx[i] = pw[4 * i + xi];
+#pragma unroll
+            for (int i = 0; i < NYB; ++i)
+                o.wy[i] = pw[W + 4 * (ty0 + i) + yi];
 #pragma unroll
             for (int j = 0; j < XT; ++j)
-                o.ax[j] = cr.pxy[pk][min(mt0 + wave + 4 * j, MT - 1) * 16 + mrow];
+                o.ax[j] = pw[zx[j]] * pw[zy[j]];
             o.v = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s)
-                o.wz[s] = cr.pw[pk][2 * W + wave + 4 * s];
-            o.wz[SPW] = cr.pw[pk][3 * W];  // slab 2m: zero for single-cell items
+                o.wz[s] = pw[2 * W + wave + 4 * s];
+            o.wz[SPW] = pw[3 * W];  // slab 2m: zero for single-cell items
         };
         Ops ops[2];
         fetch(0, ops[0]);
@@ -650,6 +664,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             const Ops &o = ops[ks & 1];
             if (ks + 1 < PB / 4)
                 fetch(ks + 1, ops[(ks + 1) & 1]);
+            real a[MTB];
+#pragma unroll
+            for (int mt = 0; mt < MTB; ++mt)
+                a[mt] = o.wx[mt % NX] * o.wy[mt / NX];
             // the point's z weight of the slab scales the B operand (its RHS
             // values), so the A operand is the plain x-y weight product
 #pragma unroll
@@ -657,17 +675,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 const real b = o.v * o.wz[s];
 #pragma unroll
                 for (int mt = 0; mt < MTB; ++mt)
-                    acc[s][mt] = mfma4(o.a[mt], b, acc[s][mt]);
+                    acc[s][mt] = mfma4(a[mt], b, acc[s][mt]);
             }
-            const real bx2 = o.v * o.wz[SPW];
+            if constexpr (TWO) {  // slab 2m: two-cell items only
+                const real bx2 = o.v * o.wz[SPW];
 #pragma unroll
-            for (int j = 0; j < XT; ++j)
-                accx[j] = mfma4(o.ax[j], bx2, accx[j]);
+                for (int j = 0; j < XT; ++j)
+                    accx[j] = mfma4(o.ax[j], bx2, accx[j]);
+            }
         }
-        }
-        if (!Z1 && more) {
-            __syncthreads();
-            products(rd[buf ^ 1]);
         }
         __syncthreads();
         buf ^= 1;
@@ -679,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     real *fl = (real *)lds + wave * FL;
     if constexpr (Z1) {
         // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow; one RHS per tap
-        real *dz = scratch + (int64_t)blockIdx.x * ((W + 1) * WW);
+        real *dz = scratch + (int64_t)ii * ((W + 1) * WW);
 #pragma unroll
         for (int j = 0; j < JT; ++j) {
             const int mt = wave + 4 * j;
@@ -688,25 +704,29 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         }
         return;
     }
-    real *dst = scratch + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
+    real *dst = scratch + ((int64_t)ii * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
     auto wsync = []() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    constexpr int NTAP = MTB * 16;                       // taps of this block's M tiles
-    const int ntap = min(NTAP, WW - mt0 * 16);           // (the last block's may be fewer)
+    // D row `row` of square (tx, ty) is tap (4 ty + (row >> 2)) W + 4 tx + (row & 3);
+    // the block's taps are the contiguous range from mt0 16 (whole rows of squares)
+    constexpr int NTAP = MTB * 16;
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
         const int oz = wave + 4 * s;
 #pragma unroll
         for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fl[(mt * 16 + out_row<real>(q, i)) * 17 + mrow] = acc[s][mt][i];
+            for (int i = 0; i < 4; ++i) {
+                const int row = out_row<real>(q, i);
+                const int tap = (4 * (mt / NX) + (row >> 2)) * W + 4 * (mt % NX) + (row & 3);
+                fl[tap * 17 + mrow] = acc[s][mt][i];
+            }
         wsync();
         real *ds = dst + ((int64_t)oz * WW + mt0 * 16) * 16;
-        for (int idx = lane; idx < ntap * 4; idx += 64) {
+        for (int idx = lane; idx < NTAP * 4; idx += 64) {
             const int tap = idx >> 2, r4 = (idx & 3) * 4;
             const real *src = fl + tap * 17 + r4;
             *(v4 *)(ds + tap * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
@@ -723,9 +743,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int i = 0; i < 4; ++i)
                 fl[out_row<real>(q, i) * 17 + mrow] = accx[j][i];
             wsync();
-            const int tap = lane >> 2, r4 = (lane & 3) * 4;
-            const real *src = fl + tap * 17 + r4;
-            *(v4 *)(dst + ((int64_t)W * WW + mt * 16 + tap) * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
+            const int row = lane >> 2, r4 = (lane & 3) * 4;
+            const int tap = (4 * (mt / NX) + (row >> 2)) * W + 4 * (mt % NX) + (row & 3);
+            const real *src = fl + row * 17 + r4;
+            *(v4 *)(dst + ((int64_t)W * WW + tap) * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
             wsync();
         }
     }
@@ -1265,36 +1286,38 @@ bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
 {
     if (!E.ndense_sp[3][wi] || !E.scratch[wi])
         return false;
+    if (E.precision == ADDK_FP64 && R == 1)  // FP64 takes 16 RHS columns
+        return false;
     const Chunk *items = E.d_dense_sp[3][wi];
-    if (E.precision == ADDK_FP64) {  // 16 RHS columns, the M tiles split over blocks
-        if (R == 1)
-            return false;
-        double *scratch = (double *)E.scratch[wi];
-        // 2m = 8: 4 M tiles over two blocks; 2m = 12: 9 over three (measured on
-        // the large workload: 14.4 ms with two blocks, 11.0 with three, 15.7
-        // with five)
+    const int n2 = E.ndense_sp2[wi], n = E.ndense_sp[3][wi];
+    const int ry = (R + 15) / 16;
+    // the two-cell items (2m + 1 slabs) lead the list, then the single-cell ones
+    auto run = [&](auto kern2, auto kern1, int ms, auto *scratch) {
+        if (n2)
+            hipLaunchKernelGGL(kern2, dim3(n2, ry, ms), dim3(kBlock), 0, st, E.d_wins, items, 0, io, R, scratch);
+        if (n > n2)
+            hipLaunchKernelGGL(kern1, dim3(n - n2, ry, ms), dim3(kBlock), 0, st, E.d_wins, items, n2, io, R, scratch);
+    };
+    if (E.precision == ADDK_FP64) {
+        // the M tiles split over blocks: 2m = 8: 4 over two; 2m = 12: 9 over three
+        // (measured on the large workload: 14.4 ms with two blocks, 11.0 with
+        // three, 15.7 with five)
+        double *sd = (double *)E.scratch[wi];
         if (wi == 0)
-            hipLaunchKernelGGL((k_spread_mfma<double, 8, false, 2>), dim3(E.ndense_sp[3][wi], (R + 15) / 16, 2),
-                               dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+            run(k_spread_mfma<double, 8, false, 2, true>, k_spread_mfma<double, 8, false, 2, false>, 2, sd);
         else
-            hipLaunchKernelGGL((k_spread_mfma<double, 12, false, 3>), dim3(E.ndense_sp[3][wi], (R + 15) / 16, 3),
-                               dim3(kBlock), 0, st, E.d_wins, items, io, R, scratch);
+            run(k_spread_mfma<double, 12, false, 3, true>, k_spread_mfma<double, 12, false, 3, false>, 3, sd);
         return true;
     }
-    float *scratch = (float *)E.scratch[wi];
-    dim3 grid(E.ndense_sp[3][wi], (R + 15) / 16);
+    float *sf = (float *)E.scratch[wi];
     if (wi == 0 && R == 1)
-        hipLaunchKernelGGL((k_spread_mfma<float, 8, true, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
-                           scratch);
+        run(k_spread_mfma<float, 8, true, 1, false>, k_spread_mfma<float, 8, true, 1, false>, 1, sf);
     else if (wi == 0)
-        hipLaunchKernelGGL((k_spread_mfma<float, 8, false, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
-                           scratch);
+        run(k_spread_mfma<float, 8, false, 1, true>, k_spread_mfma<float, 8, false, 1, false>, 1, sf);
     else if (R == 1)
-        hipLaunchKernelGGL((k_spread_mfma<float, 12, true, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
-                           scratch);
+        run(k_spread_mfma<float, 12, true, 1, false>, k_spread_mfma<float, 12, true, 1, false>, 1, sf);
     else
-        hipLaunchKernelGGL((k_spread_mfma<float, 12, false, 1>), grid, dim3(kBlock), 0, st, E.d_wins, items, io, R,
-                           scratch);
+        run(k_spread_mfma<float, 12, false, 1, true>, k_spread_mfma<float, 12, false, 1, false>, 1, sf);
     return true;
 }
 
