@@ -108,9 +108,14 @@ __device__ __forceinline__ void slab_products(typename MfmaT<real>::v4 (&acc)[ac
                                               const bool (&live)[NG], const real (*sl)[16], int ny, int q, int mrow)
 {
     constexpr int C = SW * SX;  // cells of one output's slab
+    // rows in pairs, so that the accumulator row of a one-output product
+    // (oy & 1) is known at compile time even where the row loop stays rolled
 #pragma unroll
-    for (int oy = 0; oy < SW; ++oy) {
-        if (oy >= ny)
+    for (int oy0 = 0; oy0 < SW; oy0 += 2)
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const int oy = oy0 + par;
+        if (oy >= SW || oy >= ny)
             break;
         real wyz[NG];
 #pragma unroll
@@ -129,7 +134,7 @@ __device__ __forceinline__ void slab_products(typename MfmaT<real>::v4 (&acc)[ac
                 const real a = wyz[g] * wxq[g][t];
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
-                    const int ai = NO == 1 ? (oy & 1) : o;
+                    const int ai = NO == 1 ? par : o;
                     acc[ai][g] = mfma4(a, b[o], acc[ai][g]);
                 }
             }
@@ -480,7 +485,9 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     constexpr int PB = sizeof(real) == 4 ? 32 : 16;  // points per round (PB / 4 K steps)
     constexpr int KV = PB * 16 / kBlock;             // RHS values staged per thread and round
     constexpr int FL = MTB * 16 * 17;  // per-wave flush tile [tap][16 RHS + 1 pad]
-    constexpr int PS = 3 * W + 1;     // window values per point: x [W], y [W], z [W + 1] (item slabs)
+    constexpr int NYV = Z1 ? W : 4 * NYB;  // y window values per point: the y taps of this block's squares
+    constexpr int ZO = W + NYV;            // offset of the z values
+    constexpr int PS = ZO + W + 1;         // window values per point: x [W], y [NYV], z [W + 1] (item slabs)
     struct Round {
         real pw[PB][PS];
         real pv[PB][16];
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
             const int p = e / PS, o = e - p * PS;
-            const int dd = o < W ? 0 : (o < 2 * W ? 1 : 2);
+            const int dd = o < W ? 0 : (o < ZO ? 1 : 2);
             pcs[k] = (e < NWE && p < np) ? coords[dd * w.N + it.start + p0 + p] : real(0);
         }
 #pragma unroll
@@ -550,10 +557,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             const int p = e / PS, o = e - p * PS;
             // x and y: tap o of the item's block; z: slab oz of the item, inside the
             // point's own window only
-            const int oz = o - 2 * W;
+            const int oz = o - ZO;
             const int dz = (int)floor(pcs[k]) - w.m + 1 - bz;
-            const real c = o < W ? (real)(bx + o) : (o < 2 * W ? (real)(by + o - W) : (real)(bz + oz));
-            const bool live = p < np && (o < 2 * W || (unsigned)(oz - dz) < (unsigned)W);
+            const real c = o < W ? (real)(bx + o) : (o < ZO ? (real)(by + 4 * ty0 + o - W) : (real)(bz + oz));
+            const bool live = p < np && (o < ZO || (unsigned)(oz - dz) < (unsigned)W);
             const real v = kb_psi_m(pcs[k] - c, mm, kb, ie);
             if (KW * kBlock == NWE || e < NWE)
                 pw[e] = live ? v : real(0);
@@ -596,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         } else {
             const int mt = min(mt0 + wave + 4 * j, MT - 1);
             zx[j] = 4 * (mt % NX) + xi;
-            zy[j] = W + 4 * (mt / NX) + yi;
+            zy[j] = W + 4 * (mt / NX - ty0) + yi;
         }
     }
     load(0);
@@ -621,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int ks = 0; ks < PB / 4; ++ks) {
                 const int pk = 4 * ks + q;
                 // B[point][slab mrow] = v wz(slab); zero past the item's 2m + 1 slabs
-                const real b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][2 * W + min(mrow, W)] : real(0);
+                const real b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][ZO + min(mrow, W)] : real(0);
 #pragma unroll
                 for (int j = 0; j < JT; ++j) {
                     const int mt = wave + 4 * j;
@@ -647,15 +654,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 o.wx[i] = pw[4 * i + xi];
 #pragma unroll
             for (int i = 0; i < NYB; ++i)
-                o.wy[i] = pw[W + 4 * (ty0 + i) + yi];
+                o.wy[i] = pw[W + 4 * i + yi];
 #pragma unroll
             for (int j = 0; j < XT; ++j)
                 o.ax[j] = pw[zx[j]] * pw[zy[j]];
             o.v = cr.pv[pk][mrow];
 #pragma unroll
             for (int s = 0; s < SPW; ++s)
-                o.wz[s] = pw[2 * W + wave + 4 * s];
-            o.wz[SPW] = pw[3 * W];  // slab 2m: zero for single-cell items
+                o.wz[s] = pw[ZO + wave + 4 * s];
+            o.wz[SPW] = pw[ZO + W];  // slab 2m: zero for single-cell items
         };
         Ops ops[2];
         fetch(0, ops[0]);
