@@ -281,7 +281,7 @@ def additive_main(args, A, WL, torch):
         # v_mfma_f64_16x16x4f64) unless the knobs turn them off; MI355X's dense FP32 and
         # FP64 matrix peaks equal its vector peaks (157.3 and 78.6 TFLOP/s)
         knob = {"spread_dense": 1, "interp_dense": 2, "interp": 4}.get(dom, 0)
-        on_mfma = bool(knob and (q["knobs"] & knob) and (not fp64 or (knob != 4 and R >= 2)))
+        on_mfma = bool(knob and (q["knobs"] & knob) and (not fp64 or R >= 2))
         roofline = {"bound": "mfma" if on_mfma else "alu", "kernel": dom, "achieved": round(achieved, 3),
                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": measured_traffic(dom, traffic_file) if full else None,

@@ -274,9 +274,8 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
 
 /*
  * Kernel-variant knobs: which stages run on the matrix cores
- * (v_mfma_f32_16x16x4f32; FP64 plans: v_mfma_f64_16x16x4f64 for the dense
- * spread and interpolation with R >= 2, the sparse-tile interpolation stays
- * on the vector ALUs) instead of the vector ALUs.  Both variants compute the same products; they
+ * (v_mfma_f32_16x16x4f32; FP64 plans: v_mfma_f64_16x16x4f64, with R >= 2)
+ * instead of the vector ALUs.  Both variants compute the same products; they
  * differ in speed and in summation order.
  */
 #define ADDK_KNOB_SPREAD_MFMA 1u       /* dense-cell spreading (d = 3)      */
@@ -326,7 +325,7 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
  * with K V and dK/dl V) or on this batch (graph replays), `reps` timed runs
  * each after one warm-up, keeps the fastest combination and returns it in
  * *knobs (may be NULL).  Temporary inputs are allocated and freed inside.
- * Synchronous.  FP64 plans tune the dense spread and interpolation knobs only.
+ * Synchronous.
  * Errors: INVALID_ARG, OOM, HIP.
  */
 addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs,

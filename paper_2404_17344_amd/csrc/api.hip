@@ -177,15 +177,6 @@ static std::vector<uint32_t> knob_candidates(const Engine &E)
 {
     if (E.no_mfma)
         return {0u};
-    if (E.precision != ADDK_FP32) {  // FP64: the dense spread and interp have matrix-core variants
-        bool dense = false;
-        for (int wi = 0; wi < 2; ++wi)
-            dense = dense || E.ndense[3][wi] > 0;
-        if (!dense)
-            return {0u};
-        return {0u, (uint32_t)ADDK_KNOB_SPREAD_MFMA, (uint32_t)ADDK_KNOB_INTERP_DENSE_MFMA,
-                (uint32_t)(ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA)};
-    }
     bool dense = false, tile = false;
     for (int wi = 0; wi < 2; ++wi)
         dense = dense || E.ndense[3][wi] > 0;

@@ -1790,13 +1790,13 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
 }
 
 // Matrix-core variant of a stage: off with ADDK_VECTOR_ALU_ONLY; FP64 engines
-// have it for the dense spread and interp with R >= 2 only; otherwise the knob decides,
-// and untuned engines also require the stage's fewest RHS (kMfmaMinR*).
+// have them with R >= 2 only; otherwise the knob decides, and untuned engines
+// also require the stage's fewest RHS (kMfmaMinR*).
 bool use_mfma(const Engine &E, uint32_t knob, int R)
 {
     if (E.no_mfma || !(E.knobs & knob))
         return false;
-    if (E.precision != ADDK_FP32 && (knob == ADDK_KNOB_INTERP_TILE_MFMA || R == 1))
+    if (E.precision != ADDK_FP32 && R == 1)
         return false;
     const int rmin = knob == ADDK_KNOB_SPREAD_MFMA       ? kMfmaMinRSpread
                      : knob == ADDK_KNOB_INTERP_TILE_MFMA ? kMfmaMinRInterpTile

@@ -1142,52 +1142,57 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
 // interp for the sparsely populated cells of one tile on the matrix cores: the
 // tile's sub-grid (tile + window halo, x padded to 16) plays the role of the
 // dense cell's window block; weights outside a point's support are zero.
-// One pass (<= 256 points) of a sparse tile chunk on the tile's sub-grid.
-template <int W, int NO, int NG>
+// One pass (<= 64 GMAX points) of a sparse tile chunk on the tile's sub-grid.
+template <typename real>
+constexpr int tile_gmax() { return sizeof(real) == 4 ? 4 : 2; }  // point groups per wave and pass
+
+template <typename real, int W, int NO, int NG>
 __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &ch, int pass, int r0, int nr, int x0,
-                                                 int y0, int z0, float (*slab)[NO][(3 + W) * 16][16], float *wy_lds)
+                                                 int y0, int z0, real (*slab)[NO][(3 + W) * 16][16], real *wy_lds)
 {
     constexpr int SX = 16, SY = 3 + W;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
-    const float *coords = (const float *)w.coords;
-    const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
-    float *wyl = wy_lds + wave * (4 * SY * 16);  // [g][oy][16 points]
-    float wxq[NG][4], uz[NG];
+    typedef typename MfmaT<real>::v4 v4;
+    const real *coords = (const real *)w.coords;
+    const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+    real *wyl = wy_lds + wave * (tile_gmax<real>() * SY * 16);  // [g][oy][16 points]
+    real wxq[NG][4], uz[NG];
     int lbz[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int p = pass + (wave + 4 * g) * 16 + mrow;
         const bool act = p < ch.count;
         const int j = ch.start + (act ? p : 0);
-        const float ux = coords[j], uy = coords[w.N + j];
+        const real ux = coords[j], uy = coords[w.N + j];
         uz[g] = coords[2 * w.N + j];
-        const int lx = (int)floorf(ux) - w.m + 1 - x0, ly = (int)floorf(uy) - w.m + 1 - y0;
-        lbz[g] = act ? (int)floorf(uz[g]) - w.m + 1 - z0 : (1 << 20);
+        const int lx = (int)floor(ux) - w.m + 1 - x0, ly = (int)floor(uy) - w.m + 1 - y0;
+        lbz[g] = act ? (int)floor(uz[g]) - w.m + 1 - z0 : (1 << 20);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int ox = 4 * t + q;
-            wxq[g][t] = (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_f(ux - (float)(x0 + ox), mm, kb, ie) : 0.f;
+            wxq[g][t] =
+                (act && (unsigned)(ox - lx) < (unsigned)W) ? kb_psi_m(ux - (real)(x0 + ox), mm, kb, ie) : real(0);
         }
 #pragma unroll
         for (int t = 0; t < (SY + 3) / 4; ++t) {
             const int oy = 4 * t + q;
             if (oy < SY)
                 wyl[(g * SY + oy) * 16 + mrow] =
-                    ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_f(uy - (float)(y0 + oy), mm, kb, ie) : 0.f;
+                    ((unsigned)(oy - ly) < (unsigned)W) ? kb_psi_m(uy - (real)(y0 + oy), mm, kb, ie) : real(0);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     constexpr int NA = acc_rows<NO>();
-    f4 acc[NA][NG];
+    v4 acc[NA][NG];
 #pragma unroll
     for (int o = 0; o < NA; ++o)
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            acc[o][g] = f4{0.f, 0.f, 0.f, 0.f};
-    stream_slabs<float, SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz,
+            acc[o][g] = v4{real(0), real(0), real(0), real(0)};
+    stream_slabs<real, SY, SX, 4, NG, NO, 1>(w, slab, r0, nr, x0, y0, z0, w.S[0], w.S[1], w.S[2], acc, wxq, wyl, uz,
                                               lbz, true);
     if (NO == 1)
 #pragma unroll
@@ -1197,12 +1202,12 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        float *dst = (float *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int p = pass + (wave + 4 * g) * 16 + 4 * q + i;
+                const int p = pass + (wave + 4 * g) * 16 + out_row<real>(q, i);
                 if (p < ch.count)
                     dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = acc[o][g][i];
             }
@@ -1212,14 +1217,17 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
 // Sparse-tile interp on the matrix cores: the points of a tile chunk (any base
 // cells of the tile) against the tile's (4 + 2m - 1)^3 sub-grid, taken as one
 // super-cell with x padded to 16; weights outside a point's support are zero.
-template <int W, int NO>
-__global__ __launch_bounds__(kBlock, 3) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
-                                                               const Chunk *__restrict__ chunks, int R)
+template <typename real, int W, int NO>
+__global__ __launch_bounds__(kBlock, sizeof(real) == 4 ? 3 : 2) void k_interp_tile_mfma(const WinDev *__restrict__ wins,
+                                                                                        const Chunk *__restrict__ chunks,
+                                                                                        int R)
 {
-    // one slab buffer (46 KB of LDS with the y weights at 2m = 12, two outputs)
-    // and at most 168 registers: three blocks per CU
-    __shared__ __align__(16) float slab[1][NO][(3 + W) * 16][16];
-    __shared__ __align__(16) float wy_lds[4 * 4 * (3 + W) * 16];
+    // one slab buffer (46 KB of LDS with the y weights at 2m = 12, two outputs,
+    // FP32) and at most 168 registers: three blocks per CU; FP64 takes passes
+    // of 128 points (76 KB): two
+    constexpr int GMAX = tile_gmax<real>();
+    __shared__ __align__(16) real slab[1][NO][(3 + W) * 16][16];
+    __shared__ __align__(16) real wy_lds[4 * GMAX * (3 + W) * 16];
     const Chunk ch = chunks[blockIdx.x];
     const WinDev &w = wins[ch.win];
     const int r0 = blockIdx.y * 16;
@@ -1232,14 +1240,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_interp_tile_mfma(const WinDev *__
     const int ty = tl % w.ntile[1];
     const int tz = tl / w.ntile[1];
     const int x0 = tx * w.tb[0], y0 = ty * w.tb[1], z0 = tz * w.tb[2];
-    for (int pass = 0; pass < ch.count; pass += 256) {
-        const int npass = min(256, ch.count - pass);
+    for (int pass = 0; pass < ch.count; pass += 64 * GMAX) {
+        const int npass = min(64 * GMAX, ch.count - pass);
         const int ng = (((npass + 15) >> 4) + 3) >> 2;
         switch (ng) {
-        case 1: interp_tile_pass<W, NO, 1>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
-        case 2: interp_tile_pass<W, NO, 2>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
-        case 3: interp_tile_pass<W, NO, 3>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
-        default: interp_tile_pass<W, NO, 4>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        case 1: interp_tile_pass<real, W, NO, 1>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        case 2: interp_tile_pass<real, W, NO, 2>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        case 3: interp_tile_pass<real, W, NO, GMAX < 3 ? GMAX : 3>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
+        default: interp_tile_pass<real, W, NO, GMAX>(w, ch, pass, r0, nr, x0, y0, z0, slab, wy_lds); break;
         }
         __syncthreads();  // the next pass overwrites the slab buffers
     }
@@ -1365,18 +1373,20 @@ namespace addk {
 bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st)
 {
     const int W = E.tile_w[3];
-    if (E.precision != ADDK_FP32 || !E.nchunks_i[3] || (W != 8 && W != 12))
+    if (!E.nchunks_i[3] || (W != 8 && W != 12))
         return false;
     dim3 grid(E.nchunks_i[3], (R + 15) / 16);
     const Chunk *ch = E.d_chunks_i[3];
-    if (W == 8 && nout == 1)
-        hipLaunchKernelGGL((k_interp_tile_mfma<8, 1>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
-    else if (W == 8)
-        hipLaunchKernelGGL((k_interp_tile_mfma<8, 2>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
-    else if (nout == 1)
-        hipLaunchKernelGGL((k_interp_tile_mfma<12, 1>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
+    auto go = [&](auto k81, auto k82, auto k121, auto k122) {
+        auto k = W == 8 ? (nout == 1 ? k81 : k82) : (nout == 1 ? k121 : k122);
+        hipLaunchKernelGGL(k, grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
+    };
+    if (E.precision == ADDK_FP32)
+        go(k_interp_tile_mfma<float, 8, 1>, k_interp_tile_mfma<float, 8, 2>, k_interp_tile_mfma<float, 12, 1>,
+           k_interp_tile_mfma<float, 12, 2>);
     else
-        hipLaunchKernelGGL((k_interp_tile_mfma<12, 2>), grid, dim3(kBlock), 0, st, E.d_wins, ch, R);
+        go(k_interp_tile_mfma<double, 8, 1>, k_interp_tile_mfma<double, 8, 2>, k_interp_tile_mfma<double, 12, 1>,
+           k_interp_tile_mfma<double, 12, 2>);
     return true;
 }
 

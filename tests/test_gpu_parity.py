@@ -223,9 +223,10 @@ def test_matrix_core_kernels_match_vector_kernels(A, m, R):
 @pytest.mark.parametrize("m", [4, 6])
 @pytest.mark.parametrize("R", [8, 16, 21])
 def test_fp64_matrix_core_interp(A, m, R):
-    """FP64 dense-cell interpolation on the matrix cores (v_mfma_f64_16x16x4f64)
-    against the vector-ALU kernel (same FP64 products, other summation order)
-    and the direct sum, for K V alone and with the derivative products."""
+    """FP64 dense-cell and sparse-tile interpolation (the 700 uniform points) on
+    the matrix cores (v_mfma_f64_16x16x4f64) against the vector-ALU kernels
+    (same FP64 products, other summation order) and the direct sum, for K V
+    alone and with the derivative products."""
     rng = np.random.default_rng(112)
     X = np.concatenate([rng.normal(0, 0.02, size=(30000, 3)), rng.uniform(-0.25, 0.25, size=(700, 3))])
     V = rng.standard_normal((X.shape[0], R))
