@@ -282,6 +282,12 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
 #define ADDK_KNOB_INTERP_DENSE_MFMA 2u /* dense-cell interpolation (d = 3)  */
 #define ADDK_KNOB_INTERP_TILE_MFMA 4u  /* sparse-tile interpolation (d = 3) */
 #define ADDK_KNOB_ALL_MFMA 7u
+/* Work shape of the matrix-core dense spread (FP32, R >= 2): its taps' M tiles
+ * split over 3 (2m = 12) or 2 (2m = 8) blocks per item, each evaluating the
+ * window values again, for fewer accumulators and more blocks per CU.  FP64
+ * always splits.  Same products, other block shape. */
+#define ADDK_KNOB_SPREAD_SPLIT 8u
+#define ADDK_KNOB_ALL 15u
 
 /* Plan facts.  Arrays are host memory with room for P entries (any may be NULL). */
 typedef struct {
@@ -330,6 +336,25 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
  */
 addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs,
                                void *stream);
+/* Set the plan's knobs directly (ADDK_KNOB_* mask, <= ADDK_KNOB_ALL), as if
+ * chosen by addk_plan_autotune (no RHS thresholds, the tuning cache is not
+ * consulted); e.g. to reuse a choice measured before.  Knobs a stage cannot
+ * use are ignored.  Errors: INVALID_ARG. */
+addk_status addk_plan_set_knobs(addk_plan plan, uint32_t knobs);
+/*
+ * Tuning cache.  addk_plan_autotune also records its choice under the plan's
+ * shape: (device, the set of window dimensions, the largest oversampled grid
+ * edge, m, R, the power of two at or below the largest window's point count,
+ * precision, nout).  A plan that was not tuned itself runs its products with
+ * the recorded knobs of its shape (R and nout of the call), if there are any;
+ * otherwise with its own.  Process-wide, thread-safe, never evicted.
+ *  addk_tune_cache_lookup: *found = 1 and *knobs (may be NULL) the recorded
+ *  knobs of the plan's shape at (R, nout in {1, 2}), else *found = 0.
+ *  addk_tune_cache_clear: forget every entry.
+ * Errors: INVALID_ARG.
+ */
+addk_status addk_tune_cache_lookup(addk_plan plan, int32_t R, int32_t nout, uint32_t *knobs, int32_t *found);
+addk_status addk_tune_cache_clear(void);
 addk_status addk_batch_autotune(addk_batch batch, int32_t reps, uint32_t *knobs, void *stream);
 
 /* Y[p] = K_p V[p] for all p: replays the captured graph on the stream. */

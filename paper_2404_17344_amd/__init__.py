@@ -18,10 +18,16 @@ import numpy as np
 from . import _lib
 from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, ADDK_MATERN32, AddkError,  # noqa: F401
                    ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK, ADDK_KNOB_SPREAD_MFMA,
-                   ADDK_KNOB_INTERP_DENSE_MFMA, ADDK_KNOB_INTERP_TILE_MFMA, ADDK_KNOB_ALL_MFMA)
+                   ADDK_KNOB_INTERP_DENSE_MFMA, ADDK_KNOB_INTERP_TILE_MFMA, ADDK_KNOB_ALL_MFMA,
+                   ADDK_KNOB_SPREAD_SPLIT, ADDK_KNOB_ALL)
 
 __all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "choose_n", "choose_n_for",
-           "KernelMatvec"]
+           "KernelMatvec", "tune_cache_clear"]
+
+
+def tune_cache_clear():
+    """Forget the knobs recorded by every autotune of the process (addk_tune_cache_clear)."""
+    _lib.check(_lib.load().addk_tune_cache_clear(), "addk_tune_cache_clear")
 
 _KERNELS = {"gaussian": ADDK_GAUSSIAN, "matern12": ADDK_MATERN12, "matern32": ADDK_MATERN32,
             ADDK_GAUSSIAN: ADDK_GAUSSIAN, ADDK_MATERN12: ADDK_MATERN12, ADDK_MATERN32: ADDK_MATERN32}
@@ -238,6 +244,17 @@ class Plan:
         _lib.check(self._lib.addk_plan_autotune(self._h, int(R), int(nout), int(reps), ctypes.byref(k),
                                                 _stream(stream)), "addk_plan_autotune")
         return k.value
+
+    def set_knobs(self, knobs: int):
+        """Run with these ADDK_KNOB_* (as if tuned; addk_plan_set_knobs)."""
+        _lib.check(self._lib.addk_plan_set_knobs(self._h, int(knobs)), "addk_plan_set_knobs")
+
+    def cached_knobs(self, R: int, nout: int = 1):
+        """The knobs the tuning cache holds for this plan's shape at (R, nout), or None."""
+        k, found = ctypes.c_uint32(), ctypes.c_int32()
+        _lib.check(self._lib.addk_tune_cache_lookup(self._h, int(R), int(nout), ctypes.byref(k), ctypes.byref(found)),
+                   "addk_tune_cache_lookup")
+        return k.value if found.value else None
 
     def update_params(self, ell, sigma, stream=None):
         ell_a = np.ascontiguousarray(np.broadcast_to(np.asarray(ell, dtype=np.float64), (self.P,)))

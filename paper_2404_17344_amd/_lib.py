@@ -37,6 +37,8 @@ ADDK_KNOB_SPREAD_MFMA = 1
 ADDK_KNOB_INTERP_DENSE_MFMA = 2
 ADDK_KNOB_INTERP_TILE_MFMA = 4
 ADDK_KNOB_ALL_MFMA = 7
+ADDK_KNOB_SPREAD_SPLIT = 8
+ADDK_KNOB_ALL = 15
 
 
 class AddkPlanInfo(ctypes.Structure):
@@ -79,6 +81,9 @@ _SIGS = {
     "addk_batch_launch": [_vp, _vp],
     "addk_plan_autotune": [_vp, _i32, _i32, _i32, ctypes.POINTER(_u32), _vp],
     "addk_batch_autotune": [_vp, _i32, ctypes.POINTER(_u32), _vp],
+    "addk_tune_cache_lookup": [_vp, _i32, _i32, ctypes.POINTER(_u32), _pi32],
+    "addk_plan_set_knobs": [_vp, _u32],
+    "addk_tune_cache_clear": [],
     "addk_batch_run_eager": [_vp, _vp],
     "addk_batch_destroy": [_vp],
     "addk_plan_profile": [_vp, _i32],

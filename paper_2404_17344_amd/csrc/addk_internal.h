@@ -293,6 +293,12 @@ bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st);
 // mfma.hip (FP32 matrix-core variants of the dense-cell kernels, d = 3)
 bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
+// Knobs chosen by measurement, by problem shape (device, window dimensions,
+// largest oversampled grid, m, R, point-count bucket, precision, outputs),
+// shared by the plans of the process.
+bool tune_cache_get(const Engine &E, int R, int nout, uint32_t *knobs);
+void tune_cache_put(const Engine &E, int R, int nout, uint32_t knobs);
+void tune_cache_clear();
 void launch_gather_blocks(Engine &E, int wi, int R, hipStream_t st);
 bool launch_interp_tile_mfma(Engine &E, int R, int nout, hipStream_t st);
 void launch_spread_sparse_mfma(Engine &E, int R, IoArgs io, hipStream_t st);

@@ -173,20 +173,26 @@ static addk_status time_runs(Fn fn, int reps, hipStream_t st, double *ms)
 
 // Candidate knob sets of an engine: every subset of the matrix-core stages
 // that the engine has work for (others are left on, they have no effect).
-static std::vector<uint32_t> knob_candidates(const Engine &E)
+static std::vector<uint32_t> knob_candidates(const Engine &E, int R)
 {
     if (E.no_mfma)
         return {0u};
-    bool dense = false, tile = false;
-    for (int wi = 0; wi < 2; ++wi)
+    bool dense = false, dense_sp = false, tile = false;
+    for (int wi = 0; wi < 2; ++wi) {
         dense = dense || E.ndense[3][wi] > 0;
+        dense_sp = dense_sp || E.ndense_sp[3][wi] > 0;
+    }
     tile = E.nchunks_i[3] > 0 && (E.tile_w[3] == 8 || E.tile_w[3] == 12);
+    // the split spread shape: FP32 matrix-core spread with 16 RHS columns
+    const bool split = E.precision == ADDK_FP32 && dense_sp && R >= 2;
     std::vector<uint32_t> out;
-    for (uint32_t k = 0; k <= ADDK_KNOB_ALL_MFMA; ++k) {
+    for (uint32_t k = 0; k <= ADDK_KNOB_ALL; ++k) {
         if (!dense && (k & (ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA)) !=
                           (ADDK_KNOB_SPREAD_MFMA | ADDK_KNOB_INTERP_DENSE_MFMA))
             continue;
         if (!tile && !(k & ADDK_KNOB_INTERP_TILE_MFMA))
+            continue;
+        if ((k & ADDK_KNOB_SPREAD_SPLIT) && !(split && (k & ADDK_KNOB_SPREAD_MFMA)))
             continue;
         out.push_back(k);
     }
@@ -532,7 +538,7 @@ addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t 
     Plan &pl = *(Plan *)plan;
     Engine &E = pl.eng;
     hipStream_t st = (hipStream_t)stream;
-    const std::vector<uint32_t> cand = knob_candidates(E);
+    const std::vector<uint32_t> cand = knob_candidates(E, R);
     if (cand.size() <= 1 || pl.N == 0) {
         E.knobs = cand.empty() ? 0u : cand[0];
         E.tuned = true;
@@ -580,8 +586,36 @@ addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t 
     }
     E.knobs = best_k;
     E.tuned = true;
+    tune_cache_put(E, R, nout, best_k);
     if (knobs)
         *knobs = best_k;
+    return ADDK_OK;
+}
+
+addk_status addk_plan_set_knobs(addk_plan plan, uint32_t knobs)
+{
+    if (!plan || knobs > ADDK_KNOB_ALL)
+        return fail2(ADDK_ERR_INVALID_ARG, "set knobs: plan and knobs <= ADDK_KNOB_ALL required");
+    Engine &E = ((Plan *)plan)->eng;
+    E.knobs = knobs;
+    E.tuned = true;
+    return ADDK_OK;
+}
+
+addk_status addk_tune_cache_lookup(addk_plan plan, int32_t R, int32_t nout, uint32_t *knobs, int32_t *found)
+{
+    if (!plan || !found || R < 1 || nout < 1 || nout > 2)
+        return fail2(ADDK_ERR_INVALID_ARG, "tune cache lookup: plan, found, R >= 1 and nout in {1, 2} required");
+    uint32_t k = 0;
+    *found = tune_cache_get(((Plan *)plan)->eng, R, nout, &k) ? 1 : 0;
+    if (knobs)
+        *knobs = k;
+    return ADDK_OK;
+}
+
+addk_status addk_tune_cache_clear(void)
+{
+    tune_cache_clear();
     return ADDK_OK;
 }
 
@@ -599,7 +633,7 @@ addk_status addk_batch_autotune(addk_batch batch, int32_t reps, uint32_t *knobs,
         if (s0 != ADDK_OK)
             return s0;
     }
-    const std::vector<uint32_t> cand = knob_candidates(E);
+    const std::vector<uint32_t> cand = knob_candidates(E, b.R);
     const uint32_t saved = E.knobs;
     const bool saved_tuned = E.tuned;
     double best = INFINITY;

@@ -25,6 +25,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "addk_internal.h"
 
@@ -1813,7 +1816,66 @@ addk_status engine_run(Engine &E, int R, int nout, bool vmodes_only, bool store_
     return engine_run_bound(E, R, nout, vmodes_only, store_gmodes, io, st);
 }
 
-// engine_run on the workspace already bound and uploaded (room for R RHS).
+// Tuning cache (see addk_internal.h).
+namespace {
+struct TuneKey {
+    int dev, dmask, nos, m, R, nbucket, precision, nout;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(dev, dmask, nos, m, R, nbucket, precision, nout) <
+               std::tie(o.dev, o.dmask, o.nos, o.m, o.R, o.nbucket, o.precision, o.nout);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, uint32_t> g_tune;
+
+TuneKey tune_key(const Engine &E, int R, int nout)
+{
+    TuneKey k{};
+    (void)hipGetDevice(&k.dev);
+    int64_t n = 0;
+    for (const WinDev &w : E.wdev) {
+        k.dmask |= 1 << w.d;
+        k.nos = std::max(k.nos, w.nos);
+        k.m = std::max(k.m, w.m);
+        n = std::max(n, w.N);
+    }
+    while ((int64_t(1) << (k.nbucket + 1)) <= n)  // the power of two at or below N
+        ++k.nbucket;
+    k.R = R;
+    k.precision = E.precision;
+    k.nout = nout;
+    return k;
+}
+}  // namespace
+
+bool tune_cache_get(const Engine &E, int R, int nout, uint32_t *knobs)
+{
+    const TuneKey k = tune_key(E, R, nout);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end())
+        return false;
+    *knobs = it->second;
+    return true;
+}
+
+void tune_cache_put(const Engine &E, int R, int nout, uint32_t knobs)
+{
+    const TuneKey k = tune_key(E, R, nout);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[k] = knobs;
+}
+
+void tune_cache_clear()
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.clear();
+}
+
+// engine_run on the workspace already bound and uploaded (room for R RHS).  A
+// plan's engine that was not tuned itself runs with the knobs the tuning cache
+// holds for its shape, if any.
 addk_status engine_run_bound(Engine &E, int R, int nout, bool vmodes_only, bool store_gmodes, IoArgs io,
                              hipStream_t st)
 {
@@ -1823,9 +1885,18 @@ addk_status engine_run_bound(Engine &E, int R, int nout, bool vmodes_only, bool 
         io.single.Vp = E.vpack;
         io.single.ldvp = E.vpack_ld;
     }
-    if (E.precision == ADDK_FP32)
-        return run_t<float>(E, R, no, modes_sel, !vmodes_only, io, st);
-    return run_t<double>(E, R, no, modes_sel, !vmodes_only, io, st);
+    const uint32_t knobs0 = E.knobs;
+    const bool tuned0 = E.tuned;
+    uint32_t kc = 0;
+    if (!E.tuned && !io.table && tune_cache_get(E, R, nout, &kc)) {
+        E.knobs = kc;
+        E.tuned = true;
+    }
+    const addk_status s = E.precision == ADDK_FP32 ? run_t<float>(E, R, no, modes_sel, !vmodes_only, io, st)
+                                                   : run_t<double>(E, R, no, modes_sel, !vmodes_only, io, st);
+    E.knobs = knobs0;
+    E.tuned = tuned0;
+    return s;
 }
 
 addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st)

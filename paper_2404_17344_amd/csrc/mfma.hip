@@ -1325,12 +1325,17 @@ bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st)
         return true;
     }
     float *sf = (float *)E.scratch[wi];
+    const bool split = (E.knobs & ADDK_KNOB_SPREAD_SPLIT) != 0;
     if (wi == 0 && R == 1)
         run(k_spread_mfma<float, 8, true, 1, false>, k_spread_mfma<float, 8, true, 1, false>, 1, sf);
+    else if (wi == 0 && split)
+        run(k_spread_mfma<float, 8, false, 2, true>, k_spread_mfma<float, 8, false, 2, false>, 2, sf);
     else if (wi == 0)
         run(k_spread_mfma<float, 8, false, 1, true>, k_spread_mfma<float, 8, false, 1, false>, 1, sf);
     else if (R == 1)
         run(k_spread_mfma<float, 12, true, 1, false>, k_spread_mfma<float, 12, true, 1, false>, 1, sf);
+    else if (split)
+        run(k_spread_mfma<float, 12, false, 3, true>, k_spread_mfma<float, 12, false, 3, false>, 3, sf);
     else
         run(k_spread_mfma<float, 12, false, 1, true>, k_spread_mfma<float, 12, false, 1, false>, 1, sf);
     return true;

@@ -1501,7 +1501,7 @@ addk_status addk_plan_query(addk_plan plan, addk_plan_info *info, double *torus_
         for (const WinHost &w : pl.wins)
             info->dense_points += w.ndense_pts;
         info->tile_points = pl.nsrc * pl.P - info->dense_points;
-        info->knobs = (pl.precision == ADDK_FP32 && !pl.eng.no_mfma) ? pl.eng.knobs : 0u;
+        info->knobs = pl.eng.no_mfma ? 0u : pl.eng.knobs;
         info->tuned = pl.eng.tuned ? 1 : 0;
         info->n_sources = pl.nsrc;
         info->n_targets = pl.rect ? pl.N - pl.nsrc : pl.N;
