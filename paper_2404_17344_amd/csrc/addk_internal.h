@@ -36,6 +36,7 @@ constexpr int kChunk = 1024;     // maximal points per spread/interp work item
 constexpr int kMaxW = 16;        // maximal taps per dimension (m <= 8)
 constexpr int kMaxNos = 256;     // maximal oversampled grid per dimension
 constexpr int kLdsBudget = 64 * 1024;
+constexpr int kCombineDepth = 1;  // window-sum blocks whose loads are in flight ahead of the current one (1 to 6 measured alike)
 constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
 constexpr int kDenseChunk = 256; // maximal points per dense interp item
 constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item (one window block each;

@@ -706,11 +706,13 @@ __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restric
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ wins, IoArgs io, int R, int mode)
 {
+    typedef real v4r __attribute__((ext_vector_type(4)));
     // Tiles of 64 points x 16 RHS: the window products (point-major) are read
     // row by row into LDS and written out column by column, so that both the
     // reads and the writes of the caller's column-major matrices are coalesced.
-    // The (window, output) blocks of a tile are software pipelined: the next
-    // block's loads are in flight while the current one goes through LDS.
+    // The (window, output) blocks of a tile are software pipelined: the loads
+    // of the next kCombineDepth blocks are in flight while the current one goes
+    // through LDS.
     __shared__ double tile[64][17];
     const ProbDev p = get_prob(io, blockIdx.y);
     const int t = threadIdx.x, il = t & 63, rq = t >> 6;
@@ -722,33 +724,37 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
         const int64_t iy = i - p.yoff;  // output row
         for (int r0 = 0; r0 < R; r0 += 16) {
             const int nr = min(16, R - r0);
-            auto load = [&](int k, double (&v)[4]) {
+            // thread t loads RHS 4 (t % 4) .. + 3 of point t / 4 of the tile (rows
+            // padded to a multiple of 4: one 4-vector)
+            const int pl = t >> 2, r4 = (t & 3) * 4;
+            auto load = [&](int k, v4r &v) {
                 const WinDev &w = wins[p.wbeg + k / nout];
                 const int o = k % nout;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int e = t + kBlock * q, pl = e >> 4, rr = e & 15;
-                    const int64_t ip = i0 + pl;
-                    v[q] = (ip < p.N && rr < nr) ? (double)((const real *)w.Yw)[((int64_t)o * w.N + ip) * w.Rcap + r0 + rr]
-                                                  : 0.0;
-                }
+                const int64_t ip = i0 + pl;
+                v = ip < p.N && r4 < nr ? *(const v4r *)((const real *)w.Yw + ((int64_t)o * w.N + ip) * w.Rcap + r0 + r4)
+                                        : v4r{real(0), real(0), real(0), real(0)};
             };
+            constexpr int DEP = kCombineDepth;
             double y[4] = {0.0, 0.0, 0.0, 0.0};
-            double cur[4], nxt[4] = {0.0, 0.0, 0.0, 0.0};
-            if (nblk > 0)
-                load(0, cur);
+            v4r ring[DEP + 1];
+#pragma unroll
+            for (int k = 0; k < DEP; ++k)
+                if (k < nblk)
+                    load(k, ring[k]);
+            // ring[0] holds block k; ring[1 ..] the next ones (shifted down each step)
             for (int k = 0; k < nblk; ++k) {
-                if (k + 1 < nblk)
-                    load(k + 1, nxt);
+                if (k + DEP < nblk)
+                    load(k + DEP, ring[DEP]);
                 const int wi = p.wbeg + k / nout, o = k % nout;
                 const WinDev &w = wins[wi];
                 const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
                 __syncthreads();
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int e = t + kBlock * q;
-                    tile[e >> 4][e & 15] = cur[q];
-                }
+                for (int q = 0; q < 4; ++q)  // columns past nr are zero (masked rows of the 4-vector)
+                    tile[pl][r4 + q] = r4 + q < nr ? (double)ring[0][q] : 0.0;
+#pragma unroll
+                for (int j = 0; j < DEP; ++j)
+                    ring[j] = ring[j + 1];
                 __syncthreads();
                 if (own) {
 #pragma unroll
@@ -767,9 +773,6 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                         }
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    cur[q] = nxt[q];
             }
             if ((mode & 1) && p.Y && own)
 #pragma unroll
@@ -1438,7 +1441,9 @@ WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
 {
     WsLayout L;
     L.cap = cap;
-    L.rcap = rcap;
+    // more than four RHS: rows of the per-window products padded to a multiple
+    // of four, so that the window sum reads them as 4-vectors
+    L.rcap = rcap > kCombineRowsMaxR ? (rcap + 3) / 4 * 4 : rcap;
     const size_t cs = 2 * real_size(E.precision);
     int64_t total = 0, ytotal = 0, ys = 0;
     for (WinDev &w : E.wdev) {
@@ -1451,7 +1456,7 @@ WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
         w.szA4 = w.d == 3 ? n1 * ey * ez : 0;
         w.szM = w.d == 3 ? n1 * n1 * n1 : (w.d == 2 ? n1 * n1 : n1);
         total += (int64_t)cap * (w.szG + w.szA1 + w.szA2 + 2 * (w.szA3 + w.szA4 + w.szH) + 2 * w.szM);
-        ytotal += 2 * rcap * w.N;
+        ytotal += 2 * L.rcap * w.N;  // rows of the (padded) row length
         ys += w.nf ? 2 * w.N : 0;
     }
     L.grid_bytes = std::max<int64_t>(total * (int64_t)cs, 256);
@@ -1460,11 +1465,11 @@ WsLayout engine_ws_layout(Engine &E, int cap, int64_t rcap)
     int64_t packN = 0;
     for (const Plan *pl : E.plans)
         packN += pl->N;
-    L.vpack_ld = (rcap + 15) / 16 * 16;
+    L.vpack_ld = (L.rcap + 15) / 16 * 16;
     L.vpack_bytes = std::max<int64_t>(packN * L.vpack_ld * (int64_t)real_size(E.precision), 256);
     for (int wi = 0; wi < 2; ++wi) {
         const int W = wi == 0 ? 8 : 12;
-        L.scratch_elems[wi] = (int64_t)E.ndense_sp[3][wi] * ((rcap + 15) / 16) * (W + 1) * W * W * 16;
+        L.scratch_elems[wi] = (int64_t)E.ndense_sp[3][wi] * ((L.rcap + 15) / 16) * (W + 1) * W * W * 16;
     }
     return L;
 }
