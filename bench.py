@@ -165,14 +165,18 @@ def stage_hbm(stages, q, d, R, P, N, rs, nout, traffic_file):
       spread (tile or dense-cell):  pairs x (d coordinates + R RHS values) x rs
       interp (tile or dense-cell):  pairs x (d + nout x R) x rs (coordinates read,
                                     per-window products written in the engine's precision)
-      combine:                      nout P N R x rs read + (1 + P) N R x 8 written (FP64)
+      combine:                      nout P N R x rs read + (1 + P) N R x 8 written (FP64);
+                                    all-d = 1 plans, whose window sum also interpolates
+                                    (no per-window products): P N x rs coordinates read
+                                    + (1 + P) N R x 8 written
     with rs the engine's real size and pairs the point-window pairs each kernel
     handles.  "measured" is the counter-based traffic where a summary exists."""
     pairs = {"spread": q["tile_points"], "spread_dense": q["dense_points"], "interp": q["tile_points"],
              "interp_dense": q["dense_points"]}
     alg = {k: pairs[k] * (d + R) * rs for k in ("spread", "spread_dense")}
     alg.update({k: pairs[k] * (d + nout * R) * rs for k in ("interp", "interp_dense")})
-    alg["combine"] = nout * P * N * R * rs + (1 + P) * N * R * 8
+    fused = d == 1 and stages.get("interp", (0, 0))[1] == 0 and stages.get("interp_dense", (0, 0))[1] == 0
+    alg["combine"] = (P * N * rs if fused else nout * P * N * R * rs) + (1 + P) * N * R * 8
     out = {}
     for k, b in alg.items():
         if stages.get(k, (0, 0))[1] == 0:

@@ -66,6 +66,7 @@ struct WinDev {
     double sig2, der_scale, dsig;  // sigma^2, sigma^2 * (2/l or 1/l), 2 sigma
     const void *coords;
     const int32_t *perm;
+    const void *ucoords;  // d = 1: the grid coordinates in the caller's point order (else nullptr)
     const void *Bk;
     const void *Bd;
     void *G, *A1, *A2, *A3, *A4, *H, *Gm, *Vm;  // workspace (complex interleaved)
@@ -129,6 +130,7 @@ struct WinHost {
     int64_t ntiles;
     void *coords = nullptr;
     int32_t *perm = nullptr;
+    void *ucoords = nullptr;  // d = 1 windows of square plans: coordinates in the caller's order
     void *Bk = nullptr, *Bd = nullptr;
     double *Bk64 = nullptr, *Bd64 = nullptr;
     std::vector<Chunk> chunks;  // sparse tile chunks; win field is filled by the engine
@@ -180,6 +182,8 @@ struct Engine {
     Chunk *d_dense_sp[4][2] = {};  // dense cell runs for spreading (larger items, one block each)
     int ndense_sp[4][2] = {};
     int ndense_sp2[2] = {};        // d = 3: the two-cell items, which lead each spread item list
+    bool fused_d1 = false;         // every window d = 1 (single problem): interp and window sum fused
+    int fused_no = 0;              // outputs of the fused interp the next engine_combine owes (0: none)
     int fft_L = 16;                // lines per FFT block (halved when some window's grid exceeds 128)
     int nos_max = 16;              // largest oversampled grid edge of the engine's windows
     Chunk *d_near[4] = {};         // near-field target blocks per d (tile field = tile index)
@@ -294,6 +298,8 @@ bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st);
 // mfma.hip (FP32 matrix-core variants of the dense-cell kernels, d = 3)
 bool launch_interp_mfma(Engine &E, int wi, int R, int nout, hipStream_t st);
 bool launch_spread_mfma(Engine &E, int wi, int R, IoArgs io, hipStream_t st);
+void launch_interp_combine_d1(Engine &E, int R, int nout, int mode, IoArgs io, hipStream_t st);
+int64_t interp_combine_d1_lds(const Engine &E, int nout);
 // Knobs chosen by measurement, by problem shape (device, window dimensions,
 // largest oversampled grid, m, R, point-count bucket, precision, outputs),
 // shared by the plans of the process.

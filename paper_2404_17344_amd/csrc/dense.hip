@@ -884,4 +884,132 @@ bool launch_spread_tile(Engine &E, int D, int R, IoArgs io, hipStream_t st)
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// d = 1 windows only: interpolation and window sum in one pass over the points
+// in the caller's order.  A block takes kBlock consecutive points (one per
+// thread) and 16 RHS.  For each window in turn it stages the window's grid box
+// of the NO output grids in LDS ([o][cell][16 RHS]), evaluates the point's 2m
+// window values at its own coordinate, forms the NO interpolated products in
+// registers (taps in order, as the sorted-order kernels do), adds sigma_w^2
+// times the kernel product to the FP64 sum and writes the window's scaled
+// derivative (and sigma) outputs with coalesced column stores; the sum is
+// written after the last window.  No per-window product buffer is written or
+// read back.
+template <typename real, int W, int NO>
+__global__ __launch_bounds__(kBlock) void k_interp_combine_d1(const WinDev *__restrict__ wins, int nw, int ecap,
+                                                              ProbDev p, int R, int mode)
+{
+    extern __shared__ __align__(16) unsigned char d1_lds[];
+    real *hs = (real *)d1_lds;  // [NO][ecap][16]
+    const int t = threadIdx.x;
+    const int r0 = blockIdx.y * 16;
+    const int nr = min(16, R - r0);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + t;
+    const bool own = i < p.N;
+    const int64_t iy = i - p.yoff;
+    double y[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        y[r] = 0.0;
+    for (int wi = 0; wi < nw; ++wi) {
+        const WinDev &w = wins[wi];
+        const int ext = w.ext[0];
+        const real *H = (const real *)w.H;
+        __syncthreads();  // every thread is done with the previous window's grids
+        for (int e = t; e < NO * ext * 8; e += kBlock) {
+            const int pi = e & 7, c = (e >> 3) % ext, o = e / (8 * ext);
+            const int ra = 2 * pi;
+            real re = real(0), im = real(0);
+            if (ra < nr) {
+                const int64_t off = ((int64_t)(o * w.npair_cap + (r0 >> 1) + pi) * w.szH + c) * 2;
+                re = H[off];
+                im = H[off + 1];
+            }
+            real *dst = hs + ((int64_t)o * ecap + c) * 16 + ra;
+            dst[0] = re;
+            dst[1] = ra + 1 < nr ? im : real(0);
+        }
+        __syncthreads();
+        if (!own)
+            continue;
+        const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
+        const real u = ((const real *)w.ucoords)[i];
+        const int b = (int)floor(u) - w.m + 1;  // the point's first cell of the box
+        real acc[NO][16];
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[o][r] = real(0);
+        // taps two at a time (full unrolling would hoist every tap's LDS reads)
+#pragma unroll 2
+        for (int c = 0; c < W; ++c) {
+            const real wc = kb_psi_d(u - (real)(b + c), mm, kb, ie);
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+#pragma unroll
+                for (int r = 0; r < 16; r += 4) {
+                    real h[4];
+                    load4(hs + ((int64_t)o * ecap + b + c) * 16 + r, h);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[o][r + q] += wc * h[q];
+                }
+        }
+        const int64_t blk = (int64_t)(wi - p.wbeg) * p.ldy * R;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            y[r] += w.sig2 * (double)acc[0][r];  // columns past nr hold zeros
+            if (r < nr) {
+                const int64_t at = iy + (int64_t)(r0 + r) * p.ldy;
+                if ((mode & 2) && p.dYs)
+                    p.dYs[blk + at] = w.dsig * (double)acc[0][r];
+                if (NO == 2 && (mode & 4) && p.dYl)
+                    p.dYl[blk + at] = w.der_scale * (double)acc[NO - 1][r];
+            }
+        }
+    }
+    if (own && (mode & 1) && p.Y)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (r < nr)
+                p.Y[iy + (int64_t)(r0 + r) * p.ldy] = y[r];
+}
+
+// LDS bytes of the fused d = 1 kernel: NO grid boxes of the widest window
+int64_t interp_combine_d1_lds(const Engine &E, int nout)
+{
+    int ecap = 0;
+    for (const WinDev &w : E.wdev)
+        ecap = std::max(ecap, w.ext[0]);
+    return (int64_t)nout * ecap * 16 * (E.precision == ADDK_FP32 ? 4 : 8);
+}
+
+void launch_interp_combine_d1(Engine &E, int R, int nout, int mode, IoArgs io, hipStream_t st)
+{
+    int ecap = 0;
+    for (const WinDev &w : E.wdev)
+        ecap = std::max(ecap, w.ext[0]);
+    const ProbDev &p = io.single;
+    const dim3 grid((unsigned)((p.N + kBlock - 1) / kBlock), (R + 15) / 16);
+    const size_t lds = (size_t)interp_combine_d1_lds(E, nout);
+    const int nw = (int)E.wdev.size();
+    const bool w8 = E.wdev[0].W == 8;
+    auto go = [&](auto k8, auto k12) {
+        auto k = w8 ? k8 : k12;
+        hipLaunchKernelGGL(k, grid, dim3(kBlock), lds, st, E.d_wins, nw, ecap, p, R, mode);
+    };
+    if (E.precision == ADDK_FP32) {
+        if (nout == 2)
+            go(k_interp_combine_d1<float, 8, 2>, k_interp_combine_d1<float, 12, 2>);
+        else
+            go(k_interp_combine_d1<float, 8, 1>, k_interp_combine_d1<float, 12, 1>);
+    } else {
+        if (nout == 2)
+            go(k_interp_combine_d1<double, 8, 2>, k_interp_combine_d1<double, 12, 2>);
+        else
+            go(k_interp_combine_d1<double, 8, 1>, k_interp_combine_d1<double, 12, 1>);
+    }
+}
+
 }  // namespace addk

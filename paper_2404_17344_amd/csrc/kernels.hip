@@ -1432,6 +1432,15 @@ addk_status engine_build_device(Engine &E, int precision)
         if (e != hipSuccess)
             return hip_fail(e, "hipMalloc(descriptors)");
     }
+    // one square plan whose windows are all d = 1 (no near field, one window
+    // width): interpolation fused with the window sum, in the caller's order
+    E.fused_d1 = !E.wdev.empty() && E.plans.size() == 1 && !E.plans[0]->rect;
+    for (const WinDev &w : E.wdev)
+        if (w.d != 1 || !w.ucoords || w.nf || w.W != E.wdev[0].W)
+            E.fused_d1 = false;
+    if (E.fused_d1 && interp_combine_d1_lds(E, 2) > 64 * 1024)
+        E.fused_d1 = false;
+    E.fused_no = 0;
     return ADDK_OK;
 }
 
@@ -1691,6 +1700,7 @@ static void launch_fft(Engine &E, int st_id, int ny, FftCall call, hipStream_t s
 template <typename real>
 static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp, IoArgs io, hipStream_t st)
 {
+    E.fused_no = 0;
     const int npair = (R + 1) / 2;
     const int nw = (int)E.wdev.size();
     if (nw == 0)
@@ -1766,8 +1776,12 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
             launch_fft<real, 0, 1>(E, ST_INV0, npair * nout, fc, st);
         }
         if (interp) {
+            // all-d = 1 plans: the interpolation runs in the window sum (engine_combine)
+            const bool fuse = E.fused_d1 && !io.table;
+            if (fuse)
+                E.fused_no = nout;
             for (int d = 1; d <= 3; ++d) {
-                if (!E.nchunks_i[d])
+                if (!E.nchunks_i[d] || (fuse && d == 1))
                     continue;
                 StageTimer t(E, PS_INTERP, st);
                 if (d == 3 && use_mfma(E, ADDK_KNOB_INTERP_TILE_MFMA, R) && launch_interp_tile_mfma(E, R, nout, st))
@@ -1778,7 +1792,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
             }
             for (int d = 1; d <= 3; ++d)
                 for (int wi = 0; wi < 2; ++wi) {
-                    if (!E.ndense[d][wi])
+                    if (!E.ndense[d][wi] || (fuse && d == 1))
                         continue;
                     StageTimer t(E, PS_INTERP_DENSE, st);
                     if (d == 3 && use_mfma(E, ADDK_KNOB_INTERP_DENSE_MFMA, R) && launch_interp_mfma(E, wi, R, nout, st))
@@ -1917,6 +1931,13 @@ addk_status engine_combine(Engine &E, int R, int mode, IoArgs io, hipStream_t st
         return ADDK_OK;
     const int ny = io.table ? E.nprob : 1;
     StageTimer t(E, PS_COMBINE, st);
+    if (E.fused_no > 0 && !io.table) {  // the d = 1 interpolation the last run left to the sum
+        const int no = E.fused_no;
+        E.fused_no = 0;
+        launch_interp_combine_d1(E, R, no, mode, io, st);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? ADDK_OK : hip_fail(e, "fused interp and window sum launch");
+    }
     if (R <= kCombineRowsMaxR) {
         const int bx1 = (int)std::min<int64_t>((maxN + kBlock - 1) / kBlock, 16384);
         if (E.precision == ADDK_FP32)

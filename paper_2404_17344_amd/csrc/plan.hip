@@ -598,6 +598,8 @@ static hipError_t free_win_arrays(WinHost &w)
     };
     f(w.coords);
     f(w.perm);
+    f(w.ucoords);
+    w.ucoords = nullptr;
     if (w.Bk != (void *)w.Bk64)
         f(w.Bk);
     if (w.Bd != (void *)w.Bd64)
@@ -776,6 +778,7 @@ static void fill_windesc(const Plan &pl, const WinHost &w, int prob, WinDev &d)
     d.dsig = 2.0 * w.sigma;
     d.coords = w.coords;
     d.perm = w.perm;
+    d.ucoords = w.ucoords;
     d.Bk = w.Bk;
     d.Bd = w.Bd;
     fill_near(pl, w, d);
@@ -1065,6 +1068,14 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
             hipLaunchKernelGGL(k_place<double>, dim3(nb), dim3(256), 0, st, N, w.d, (const double *)ucoord, ks_out,
                                js_out, hist, dkstart, (double *)w.coords, w.perm);
         e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess && w.d == 1 && !pl.rect) {
+        // d = 1: the interpolation runs in the caller's point order, fused with
+        // the window sum; it keeps these coordinates
+        if (w.ucoords)
+            (void)hipFree(w.ucoords);
+        w.ucoords = ucoord;
+        ucoord = nullptr;
     }
     release();
     if (e != hipSuccess)
