@@ -303,8 +303,16 @@ __device__ __forceinline__ int base_cell_p(real u, int m)
 // grid coordinate relative to the box, rounded to the plan's precision; tile key
 template <typename real>
 __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, KeyArgs a, real *ucoord,
-                       int32_t *key, int32_t *hist, int32_t *bad)
+                       int32_t *key, int32_t *hist, int32_t *bad, int nhist_lds)
 {
+    // Few keys (d = 1 windows: a few hundred cells for 1e6 points): the counts
+    // gather in a block-private LDS histogram first, so that the global atomics
+    // are one per block and non-empty key, not one per point.
+    extern __shared__ int32_t lh[];
+    for (int k = threadIdx.x; k < nhist_lds; k += blockDim.x)
+        lh[k] = 0;
+    if (nhist_lds)
+        __syncthreads();
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
         int t[3] = {0, 0, 0}, b3[3] = {0, 0, 0};
         bool ok = true;
@@ -331,7 +339,16 @@ __global__ void k_keys(const double *__restrict__ X, int64_t ldx, int64_t N, Key
         const int c = (b3[0] - t[0] * a.tb[0]) + a.tb[0] * ((b3[1] - t[1] * a.tb[1]) + a.tb[1] * (b3[2] - t[2] * a.tb[2]));
         const int k = tl * a.cpt + c + (a.split && j >= a.nsrc ? a.nkeys : 0);
         key[j] = k;
-        atomicAdd(&hist[k], 1);
+        if (nhist_lds)
+            atomicAdd(&lh[k], 1);
+        else
+            atomicAdd(&hist[k], 1);
+    }
+    if (nhist_lds) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < nhist_lds; k += blockDim.x)
+            if (lh[k])
+                atomicAdd(&hist[k], lh[k]);
     }
 }
 
@@ -927,11 +944,13 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
             return hip_fail(e, "clear histogram");
     }
     const int nb = (int)std::min<int64_t>((N + 255) / 256, 4096);
+    const int nhl = nseg * nkeys <= 8192 ? (int)(nseg * nkeys) : 0;  // LDS histogram (32 KB at most)
     if (pl.precision == ADDK_FP32)
-        hipLaunchKernelGGL(k_keys<float>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (float *)ucoord, key, hist, bad);
+        hipLaunchKernelGGL(k_keys<float>, dim3(nb), dim3(256), nhl * sizeof(int32_t), st, dX, ldx, N, ka,
+                           (float *)ucoord, key, hist, bad, nhl);
     else
-        hipLaunchKernelGGL(k_keys<double>, dim3(nb), dim3(256), 0, st, dX, ldx, N, ka, (double *)ucoord, key, hist,
-                           bad);
+        hipLaunchKernelGGL(k_keys<double>, dim3(nb), dim3(256), nhl * sizeof(int32_t), st, dX, ldx, N, ka,
+                           (double *)ucoord, key, hist, bad, nhl);
     std::vector<int32_t> hall(nseg * nkeys);
     int32_t hbad = 0;
     e = hipMemcpyAsync(hall.data(), hist, nseg * nkeys * sizeof(int32_t), hipMemcpyDeviceToHost, st);
