@@ -484,7 +484,6 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     constexpr int XT = (MTB + 3) / 4;  // M tiles per wave of slab 2m (two-cell items only)
     constexpr int PB = sizeof(real) == 4 ? 32 : 16;  // points per round (PB / 4 K steps)
     constexpr int KV = PB * 16 / kBlock;             // RHS values staged per thread and round
-    constexpr int FL = MTB * 16 * 17;  // per-wave flush tile [tap][16 RHS + 1 pad]
     constexpr int NYV = Z1 ? W : 4 * NYB;  // y window values per point: the y taps of this block's squares
     constexpr int ZO = W + NYV;            // offset of the z values
     constexpr int PS = ZO + W + 1;         // window values per point: x [W], y [NYV], z [W + 1] (item slabs)
@@ -492,10 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         real pw[PB][PS];
         real pv[PB][16];
     };
-    constexpr int RB_BYTES = 2 * (int)sizeof(Round);
-    constexpr int FL_BYTES = 4 * FL * (int)sizeof(real);
-    __shared__ __align__(16) unsigned char lds[RB_BYTES > FL_BYTES ? RB_BYTES : FL_BYTES];
-    Round *rd = (Round *)lds;
+    __shared__ __align__(16) Round rd[2];
 
     const int ii = item0 + (int)blockIdx.x;  // the item (and its scratch slot)
     const Chunk it = items[ii];
@@ -697,9 +693,9 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     }
 
     // write the item's block [oz][oy][ox][16 RHS] to its scratch slot (plain
-    // stores; the blocks of all items are summed by k_gather_blocks), each
-    // slab (or M tile of slab 2m) through a per-wave LDS transpose
-    real *fl = (real *)lds + wave * FL;
+    // stores; the blocks of all items are summed by k_gather_blocks).  A lane
+    // holds 4 taps of one RHS per M tile; for one register the 16 lanes of a
+    // quarter-wave write the 16 RHS of one tap (64 contiguous bytes).
     if constexpr (Z1) {
         // lane (q, mrow) holds taps mt 16 + 4 q + i of slab mrow; one RHS per tap
         real *dz = scratch + (int64_t)ii * ((W + 1) * WW);
@@ -712,33 +708,19 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         return;
     }
     real *dst = scratch + ((int64_t)ii * gridDim.y + blockIdx.y) * ((W + 1) * WW * 16);
-    auto wsync = []() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
     // D row `row` of square (tx, ty) is tap (4 ty + (row >> 2)) W + 4 tx + (row & 3);
     // the block's taps are the contiguous range from mt0 16 (whole rows of squares)
-    constexpr int NTAP = MTB * 16;
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
-        const int oz = wave + 4 * s;
+        real *ds = dst + ((int64_t)(wave + 4 * s) * WW + mt0 * 16) * 16;
 #pragma unroll
         for (int mt = 0; mt < MTB; ++mt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = out_row<real>(q, i);
                 const int tap = (4 * (mt / NX) + (row >> 2)) * W + 4 * (mt % NX) + (row & 3);
-                fl[tap * 17 + mrow] = acc[s][mt][i];
+                ds[tap * 16 + mrow] = acc[s][mt][i];
             }
-        wsync();
-        real *ds = dst + ((int64_t)oz * WW + mt0 * 16) * 16;
-        for (int idx = lane; idx < NTAP * 4; idx += 64) {
-            const int tap = idx >> 2, r4 = (idx & 3) * 4;
-            const real *src = fl + tap * 17 + r4;
-            *(v4 *)(ds + tap * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
-        }
-        wsync();
     }
     if (NS > W) {
 #pragma unroll
@@ -747,14 +729,11 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             if (wave + 4 * j >= MTB || mt >= MT)
                 break;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fl[out_row<real>(q, i) * 17 + mrow] = accx[j][i];
-            wsync();
-            const int row = lane >> 2, r4 = (lane & 3) * 4;
-            const int tap = (4 * (mt / NX) + (row >> 2)) * W + 4 * (mt % NX) + (row & 3);
-            const real *src = fl + row * 17 + r4;
-            *(v4 *)(dst + ((int64_t)W * WW + tap) * 16 + r4) = v4{src[0], src[1], src[2], src[3]};
-            wsync();
+            for (int i = 0; i < 4; ++i) {
+                const int row = out_row<real>(q, i);
+                const int tap = (4 * (mt / NX) + (row >> 2)) * W + 4 * (mt % NX) + (row & 3);
+                dst[((int64_t)W * WW + tap) * 16 + mrow] = accx[j][i];
+            }
         }
     }
 }
