@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     constexpr int NYB = Z1 ? 1 : MTB / NX;  // rows of squares of this block
     constexpr int SPW = W / 4;         // z-slabs per wave: slabs wave + 4 s, s < SPW (the first 2m)
     constexpr int XT = (MTB + 3) / 4;  // M tiles per wave of slab 2m (two-cell items only)
-    constexpr int PB = sizeof(real) == 4 ? 32 : 16;  // points per round (PB / 4 K steps)
+    constexpr int PB = 32;             // points per round (PB / 4 K steps; FP64 measured 8.55 ms at 16, 8.15 at 32)
     constexpr int KV = PB * 16 / kBlock;             // RHS values staged per thread and round
     constexpr int NYV = Z1 ? W : 4 * NYB;  // y window values per point: the y taps of this block's squares
     constexpr int ZO = W + NYV;            // offset of the z values
