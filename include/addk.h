@@ -288,6 +288,14 @@ addk_status addk_plan_update_params(addk_plan plan, const double *ell, const dou
  * always splits.  Same products, other block shape. */
 #define ADDK_KNOB_SPREAD_SPLIT 8u
 #define ADDK_KNOB_ALL 15u
+/* Sparse d = 3 points spread per point tile into a register sub-grid that is
+ * added to the grid with atomic adds, instead of by output tiles that write
+ * every grid value once.  Faster where sparsely populated cells hold many of
+ * the points (each point is then read once, not by every output tile it
+ * reaches), but the sums' order depends on timing: the products are no longer
+ * bitwise reproducible.  Never chosen by the autotuner; set it with
+ * addk_plan_set_knobs. */
+#define ADDK_KNOB_SPARSE_ATOMIC 16u
 
 /* Plan facts.  Arrays are host memory with room for P entries (any may be NULL). */
 typedef struct {
@@ -336,7 +344,7 @@ addk_status addk_batch_create(addk_batch *out, int32_t nprob, const addk_plan *p
  */
 addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t reps, uint32_t *knobs,
                                void *stream);
-/* Set the plan's knobs directly (ADDK_KNOB_* mask, <= ADDK_KNOB_ALL), as if
+/* Set the plan's knobs directly (ADDK_KNOB_* mask, <= ADDK_KNOB_ALL | ADDK_KNOB_SPARSE_ATOMIC), as if
  * chosen by addk_plan_autotune (no RHS thresholds, the tuning cache is not
  * consulted); e.g. to reuse a choice measured before.  Knobs a stage cannot
  * use are ignored.  Errors: INVALID_ARG. */

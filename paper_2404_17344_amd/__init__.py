@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (ADDK_FP32, ADDK_FP64, ADDK_GAUSSIAN, ADDK_MATERN12, ADDK_MATERN32, AddkError,  # noqa: F401
                    ADDK_COEF_SAMPLED, ADDK_TORUS_PAPER, ADDK_NO_ACCURACY_CHECK, ADDK_KNOB_SPREAD_MFMA,
                    ADDK_KNOB_INTERP_DENSE_MFMA, ADDK_KNOB_INTERP_TILE_MFMA, ADDK_KNOB_ALL_MFMA,
-                   ADDK_KNOB_SPREAD_SPLIT, ADDK_KNOB_ALL)
+                   ADDK_KNOB_SPREAD_SPLIT, ADDK_KNOB_ALL, ADDK_KNOB_SPARSE_ATOMIC)
 
 __all__ = ["Plan", "Batch", "AddkError", "addk_matvec", "torus_period", "window_ft", "choose_n", "choose_n_for",
            "KernelMatvec", "tune_cache_clear"]

@@ -39,6 +39,7 @@ ADDK_KNOB_INTERP_TILE_MFMA = 4
 ADDK_KNOB_ALL_MFMA = 7
 ADDK_KNOB_SPREAD_SPLIT = 8
 ADDK_KNOB_ALL = 15
+ADDK_KNOB_SPARSE_ATOMIC = 16
 
 
 class AddkPlanInfo(ctypes.Structure):

@@ -594,8 +594,8 @@ addk_status addk_plan_autotune(addk_plan plan, int32_t R, int32_t nout, int32_t 
 
 addk_status addk_plan_set_knobs(addk_plan plan, uint32_t knobs)
 {
-    if (!plan || knobs > ADDK_KNOB_ALL)
-        return fail2(ADDK_ERR_INVALID_ARG, "set knobs: plan and knobs <= ADDK_KNOB_ALL required");
+    if (!plan || knobs > (ADDK_KNOB_ALL | ADDK_KNOB_SPARSE_ATOMIC))
+        return fail2(ADDK_ERR_INVALID_ARG, "set knobs: plan and knobs <= ADDK_KNOB_ALL | ADDK_KNOB_SPARSE_ATOMIC required");
     Engine &E = ((Plan *)plan)->eng;
     E.knobs = knobs;
     E.tuned = true;

@@ -1718,7 +1718,7 @@ static addk_status run_t(Engine &E, int R, int nout, int modes_sel, bool interp,
         if (!E.nchunks[d])
             continue;
         StageTimer t(E, PS_SPREAD, st);
-        if (d == 3 && E.sparse_gather && !E.no_mfma) {
+        if (d == 3 && E.sparse_gather && !E.no_mfma && !(E.knobs & ADDK_KNOB_SPARSE_ATOMIC)) {
             launch_spread_sparse_mfma(E, R, io, st);
             continue;
         }

@@ -291,7 +291,10 @@ __device__ __forceinline__ float uniform(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-template <typename real, int D, int NO>
+// KT: 1 every window Matern-1/2, 2 every window Matern-3/2 (the kernel's form is
+// then fixed at compile time: the close-pair loop is bound by instruction issue),
+// 0 mixed (chosen per window).
+template <typename real, int D, int NO, int KT>
 __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restrict__ wins,
                                                          const Chunk *__restrict__ chunks, IoArgs io)
 {
@@ -319,7 +322,8 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
         bmax[a] = uniform(wave_max(own ? (float)u[a] : -3.0e38f));
     }
     const real eps2 = (real)w.nf_eps2, ie2 = (real)w.nf_inv_eps2, hl = (real)w.nf_hl;
-    const bool m32 = w.nf == 2;  // Matern-3/2: (1 + a r) e^{-a r} and (a r)^2 e^{-a r}, with rl = a r
+    // Matern-3/2: (1 + a r) e^{-a r} and (a r)^2 e^{-a r}, with rl = a r
+    const bool m32 = KT == 0 ? w.nf == 2 : KT == 2;
     const float eg = sqrtf((float)w.nf_eps2) + 1e-3f;
     real pa[kNearQ + 1], pd[kNearQ + 1];
 #pragma unroll
@@ -544,14 +548,31 @@ void launch_near_all(Engine &E, int R, int nout, IoArgs io, const double *Vt, in
     }
 }
 
-template <typename real, int D>
-void launch_near_sym_d(Engine &E, int nout, IoArgs io, hipStream_t st)
+template <typename real, int D, int KT>
+void launch_near_sym_k(Engine &E, int nout, IoArgs io, hipStream_t st)
 {
     const dim3 grid(E.nnear[D]);
     if (nout > 1)
-        hipLaunchKernelGGL((k_near_sym<real, D, 2>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
+        hipLaunchKernelGGL((k_near_sym<real, D, 2, KT>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
     else
-        hipLaunchKernelGGL((k_near_sym<real, D, 1>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
+        hipLaunchKernelGGL((k_near_sym<real, D, 1, KT>), grid, dim3(kNearBlock), 0, st, E.d_wins, E.d_near[D], io);
+}
+
+template <typename real, int D>
+void launch_near_sym_d(Engine &E, int nout, IoArgs io, hipStream_t st)
+{
+    // the near-field windows' kernel form: all Matern-1/2 (1), all Matern-3/2 (2), or both (0)
+    bool m12 = false, m32 = false;
+    for (const WinDev &w : E.wdev) {
+        m12 = m12 || w.nf == 1;
+        m32 = m32 || w.nf == 2;
+    }
+    if (m12 && !m32)
+        launch_near_sym_k<real, D, 1>(E, nout, io, st);
+    else if (m32 && !m12)
+        launch_near_sym_k<real, D, 2>(E, nout, io, st);
+    else
+        launch_near_sym_k<real, D, 0>(E, nout, io, st);
 }
 
 template <typename real>

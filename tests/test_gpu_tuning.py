@@ -80,4 +80,24 @@ def test_set_knobs_rejects(A):
     p = WL.small_problem(300, 3, [[0, 1, 2]], seed=5, R=1, n=16, m=4)
     pl = A.Plan(p.X, p.windows, p.ell, p.sigma, n=16, m=4)
     with pytest.raises(A.AddkError):
-        pl.set_knobs(A.ADDK_KNOB_ALL + 1)
+        pl.set_knobs((A.ADDK_KNOB_ALL | A.ADDK_KNOB_SPARSE_ATOMIC) + 1)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 5e-6), ("fp64", 1e-12)])
+def test_sparse_atomic_spread_same_products(A, prec, tol):
+    """The atomic per-tile sparse spread (ADDK_KNOB_SPARSE_ATOMIC) against the
+    output-tile spread: the same sums in another order (FP32: the two orders
+    round apart by ~1.4e-6 of max |y|, both within the FP32 bound of the exact
+    product)."""
+    p = WL.additive_c2(N=30000, seed=21, R=5)
+    _say("sparse atomic %s" % prec)
+    mk = lambda: A.Plan(p.X, p.windows, p.ell, p.sigma, n=64, m=6, precision=prec)  # noqa: E731
+    p1, p2 = mk(), mk()
+    assert p1.query()["tile_points"] > 1000
+    p2.set_knobs(A.ADDK_KNOB_ALL_MFMA | A.ADDK_KNOB_SPARSE_ATOMIC)
+    V = cuda(p.V)
+    Y1, d1, _ = p1.dmatvec(V, want_dsigma=False)
+    Y2, d2, _ = p2.dmatvec(V, want_dsigma=False)
+    assert relerr(Y2.cpu().numpy(), Y1.cpu().numpy()) < tol
+    for w in range(p.P):
+        assert relerr(d2[w].cpu().numpy(), d1[w].cpu().numpy()) < tol
