@@ -118,6 +118,20 @@ struct LineGroup {
     int32_t win, grp;
 };
 
+// Device memory reached through a pointer held in a descriptor, as a pointer in
+// the global address space: its loads and stores then compile to global, not
+// flat, instructions.  A flat access counts on the LDS counter as well as on
+// the vector-memory counter, so a wave that waits for its LDS reads would also
+// wait for every HBM load it still has in flight.
+template <typename T> using gptr = T __attribute__((address_space(1))) *;
+template <typename T> __device__ __forceinline__ gptr<T> gbl(T *p) { return (gptr<T>)p; }
+__device__ __forceinline__ int2 ld_int2(gptr<const int2> p)
+{
+    typedef int n2i __attribute__((ext_vector_type(2)));
+    const n2i t = *(gptr<const n2i>)p;
+    return make_int2(t.x, t.y);
+}
+
 // Stage identifiers for the FFT passes (axis, mode).
 enum FftStage { ST_FWD0 = 0, ST_FWD1, ST_FUSED2, ST_FUSED1, ST_FUSED0, ST_INV1, ST_INV0, ST_COUNT };
 

@@ -61,8 +61,14 @@ __device__ __forceinline__ void unpack_cell(int packed, int &bx, int &by, int &b
 
 __device__ __forceinline__ ProbDev get_prob_d(const IoArgs &io, int p) { return io.table ? io.table[p] : io.single; }
 
-__device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gadd(gptr<float> p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(gptr<double> p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Cells of a dense item's window block: (2m)^d, with one more z layer for the
 // two-cell items of d = 3.  Shared by the interp kernel and its launcher.
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const
     int bx, by, bz, nzc;
     unpack_cell(it.tile, bx, by, bz, nzc);
     const int bb[3] = {bx, by, bz};
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob_d(io, w.prob);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
 
@@ -135,8 +141,8 @@ __global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const
         for (int e = t; e < np * RBB; e += blockDim.x) {
             const int p = e / RBB, i = e - p * RBB;
             const int r = r0 + i;
-            const int orig = w.perm[it.start + p0 + p];
-            pv[p][i] = r < R ? ((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
+            const int orig = gbl(w.perm)[it.start + p0 + p];
+            pv[p][i] = r < R ? gbl((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
         }
         __syncthreads();
         for (int p = 0; p < np; ++p) {
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(D == 3 ? W * W * 4 : 256) void k_spread_dense(const
         __syncthreads();
     }
 
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int ex = w.ext[0], ey = w.ext[1];
 #pragma unroll
     for (int k = 0; k < IN2; ++k) {
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
     unpack_cell(it.tile, bx, by, bz, nzc);
     const int ncell = D == 3 ? W * W * (W + nzc - 1) : NC;  // the item's block (z cells bz .. bz + W + nzc - 2)
 
-    const real *H = (const real *)w.H;
+    const gptr<const real> H = gbl((const real *)w.H);
     const int ex = w.ext[0], ey = w.ext[1];
     const int np = (nr + 1) >> 1;
     const int p0 = r0 >> 1;
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
     if (p >= it.count)
         return;
     const int j = it.start + p;
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     const real ux = coords[j];
     real wy[W], wz[W];
@@ -313,8 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense(const WinDev *__restric
             }
         }
     }
-    const int orig = w.perm[j];
-    real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+    const int orig = gbl(w.perm)[j];
+    const gptr<real> dst = gbl((real *)w.Yw) + ((int64_t)o * w.N + orig) * w.Rcap + r0;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
         if (i < nr)
@@ -388,6 +394,31 @@ __device__ __forceinline__ void store4(real *p, const real (&v)[4])
     }
 }
 
+// the same for device memory (global loads and stores)
+__device__ __forceinline__ void load4(gptr<const float> p, float (&v)[4])
+{
+    typedef float n4 __attribute__((ext_vector_type(4)));
+    const n4 t = *(gptr<const n4>)p;
+    v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+}
+__device__ __forceinline__ void load4(gptr<const double> p, double (&v)[4])
+{
+    typedef double n2 __attribute__((ext_vector_type(2)));
+    const n2 a = *(gptr<const n2>)p, b = *(gptr<const n2>)(p + 2);
+    v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+}
+__device__ __forceinline__ void store4(gptr<float> p, const float (&v)[4])
+{
+    typedef float n4 __attribute__((ext_vector_type(4)));
+    *(gptr<n4>)p = n4{v[0], v[1], v[2], v[3]};
+}
+__device__ __forceinline__ void store4(gptr<double> p, const double (&v)[4])
+{
+    typedef double n2 __attribute__((ext_vector_type(2)));
+    *(gptr<n2>)p = n2{v[0], v[1]};
+    *(gptr<n2>)(p + 2) = n2{v[2], v[3]};
+}
+
 // Spread: one block (256 threads) per dense item (<= kSpreadChunk points of one
 // base cell) and 16 RHS.  Thread (slot = t / 4, rq = t % 4) accumulates the
 // item's W x 4 block (taps x its RHS) over points slot, slot + 64, ...; the
@@ -405,9 +436,9 @@ __global__ __launch_bounds__(kBlock) void k_spread_dense1(const WinDev *__restri
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, rq = t & 3, slot = t >> 2;
     int bx, by, bz, nzc;
     unpack_cell(it.tile, bx, by, bz, nzc);
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob_d(io, w.prob);
-    const real *Vp = (const real *)pio.Vp;
+    const gptr<const real> Vp = gbl((const real *)pio.Vp);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     real acc[W][4];
 #pragma unroll
@@ -428,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_dense1(const WinDev *__restri
     for (int k = 0; k < KP; ++k) {
         const int p = slot + 64 * k;
         const bool act = p < it.count;
-        pj[k] = act ? w.perm[it.start + p] : -1;
+        pj[k] = act ? gbl(w.perm)[it.start + p] : -1;
         uj[k] = act ? coords[it.start + p] : real(0);
     }
     auto load_rows = [&](int k0, real (&v)[4][4]) {
@@ -485,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_dense1(const WinDev *__restri
         const int o = t >> 4, rr = t & 15, r = r0 + rr;
         if (r < R) {
             const real g = red[0][o][rr] + red[1][o][rr] + red[2][o][rr] + red[3][o][rr];
-            real *G = (real *)w.G;
+            const gptr<real> G = gbl((real *)w.G);
             gadd(&G[((int64_t)(r >> 1) * w.szG + bx + o) * 2 + (r & 1)], g);
         }
     }
@@ -510,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense1(const WinDev *__restri
     const int t = threadIdx.x;
     int bx, by, bz, nzc;
     unpack_cell(it.tile, bx, by, bz, nzc);
-    const real *H = (const real *)w.H;
+    const gptr<const real> H = gbl((const real *)w.H);
     for (int e = t; e < nout * W * 8; e += kBlock) {
         const int pi = e & 7, c = (e >> 3) % W, o = e / (8 * W);
         const int ra = 2 * pi;
@@ -526,11 +557,11 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense1(const WinDev *__restri
     __syncthreads();
     if (t >= it.count)
         return;
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     const int j = it.start + t;
     const real u = coords[j];
-    const int64_t orig = w.perm[j];
+    const int64_t orig = gbl(w.perm)[j];
     real acc[2][16] = {};
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -554,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_dense1(const WinDev *__restri
     for (int o = 0; o < 2; ++o) {
         if (o >= nout)
             break;
-        real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+        const gptr<real> dst = gbl((real *)w.Yw) + ((int64_t)o * w.N + orig) * w.Rcap + r0;
         if (vec) {
 #pragma unroll
             for (int i = 0; i < 16; i += 4) {
@@ -732,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_tile(const WinDev *__restrict
     const int ty = tl % w.ntile[1];
     const int tz = tl / w.ntile[1];
     const int o0[3] = {tx * w.tb[0], ty * w.tb[1], tz * w.tb[2]};
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob_d(io, w.prob);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     const int t = threadIdx.x;
@@ -776,8 +807,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_tile(const WinDev *__restrict
         for (int e = t; e < np * RT; e += kBlock) {
             const int p = e / RT, i = e - p * RT;
             const int r = r0 + i;
-            const int orig = w.perm[ch.start + p0 + p];
-            pv[p][i] = r < R ? ((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
+            const int orig = gbl(w.perm)[ch.start + p0 + p];
+            pv[p][i] = r < R ? gbl((const real *)pio.Vp)[orig * pio.ldvp + r] : real(0);
         }
         __syncthreads();
         for (int e = t; e < np * D * W; e += kBlock) {
@@ -823,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_tile(const WinDev *__restrict
         __syncthreads();
     }
 
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -914,7 +945,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_combine_d1(const WinDev *__re
     for (int wi = 0; wi < nw; ++wi) {
         const WinDev &w = wins[wi];
         const int ext = w.ext[0];
-        const real *H = (const real *)w.H;
+        const gptr<const real> H = gbl((const real *)w.H);
         __syncthreads();  // every thread is done with the previous window's grids
         for (int e = t; e < NO * ext * 8; e += kBlock) {
             const int pi = e & 7, c = (e >> 3) % ext, o = e / (8 * ext);
@@ -933,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_combine_d1(const WinDev *__re
         if (!own)
             continue;
         const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
-        const real u = ((const real *)w.ucoords)[i];
+        const real u = gbl((const real *)w.ucoords)[i];
         const int b = (int)floor(u) - w.m + 1;  // the point's first cell of the box
         real acc[NO][16];
 #pragma unroll

@@ -38,6 +38,21 @@ struct cpx {
     real x, y;
 };
 
+// a complex value in device memory (one 2-vector access)
+template <typename real>
+__device__ __forceinline__ cpx<real> ldc(gptr<const cpx<real>> p)
+{
+    typedef real n2 __attribute__((ext_vector_type(2)));
+    const n2 v = *(gptr<const n2>)p;
+    return {v.x, v.y};
+}
+template <typename real>
+__device__ __forceinline__ void stc(gptr<cpx<real>> p, cpx<real> v)
+{
+    typedef real n2 __attribute__((ext_vector_type(2)));
+    *(gptr<n2>)p = n2{v.x, v.y};
+}
+
 template <typename real>
 __device__ __forceinline__ cpx<real> cadd(cpx<real> a, cpx<real> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename real>
@@ -52,8 +67,14 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ void lds_add(float *p, float v) { __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ __forceinline__ void lds_add(double *p, double v) { __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
-__device__ __forceinline__ void gbl_add(float *p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void gbl_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gbl_add(gptr<float> p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gbl_add(gptr<double> p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Normalised Kaiser-Bessel window in grid units (psi(0) = 1):
 //   psi(z) = (m / sinh(b m)) sinh(b s) / s,  s = sqrt(m^2 - z^2),  |z| <= m,
@@ -87,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_v(IoArgs io, int R)
 {
     __shared__ double tile[16][65];
     const ProbDev p = get_prob(io, blockIdx.y);
-    real *vp = (real *)p.Vp;
+    const gptr<real> vp = gbl((real *)p.Vp);
     const int t = threadIdx.x, il = t & 63, rq = t >> 6;
     for (int64_t i0 = blockIdx.x * (int64_t)64; i0 < p.N; i0 += (int64_t)gridDim.x * 64) {
         for (int r0 = 0; r0 < p.ldvp; r0 += 16) {
@@ -96,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_v(IoArgs io, int R)
             for (int k = 0; k < 4; ++k) {
                 const int r = r0 + rq + 4 * k;
                 const int64_t i = i0 + il;
-                tile[rq + 4 * k][il] = (i < p.nsrc && r < R) ? p.V[i + (int64_t)r * p.ldv] : 0.0;
+                tile[rq + 4 * k][il] = (i < p.nsrc && r < R) ? gbl(p.V)[i + (int64_t)r * p.ldv] : 0.0;
             }
             __syncthreads();
 #pragma unroll
@@ -117,7 +138,7 @@ template <typename real>
 __global__ __launch_bounds__(kBlock) void k_zero_grids(const WinDev *__restrict__ wins, int npair)
 {
     const WinDev &w = wins[blockIdx.y];
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int64_t n = 2 * w.szG * (int64_t)npair;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         G[i] = real(0);
@@ -156,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(const WinDev *__restrict__ wi
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, g = lane & 15;
     real *mywv = wv + (wave * 4 + grp) * (D * kMaxW);
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob(io, w.prob);
     const int W = w.W, m = w.m;
     const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
@@ -179,10 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_spread(const WinDev *__restrict__ wi
             mywv[dd * kMaxW + o] = kb_psi(uu - (real)(b0 + o), mm, bb, ie);
         }
         real v[RB];
-        const int orig = w.perm[j];
+        const int orig = gbl(w.perm)[j];
 #pragma unroll
         for (int i = 0; i < RB; ++i)
-            v[i] = (act && i < nr) ? ((const real *)pio.Vp)[orig * pio.ldvp + r0 + i] : real(0);
+            v[i] = (act && i < nr) ? gbl((const real *)pio.Vp)[orig * pio.ldvp + r0 + i] : real(0);
         wave_sync();
         if (act) {
             const int lx = bc[0] - ox0;
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_spread(const WinDev *__restrict__ wi
     __syncthreads();
 
     // flush the sub-grid: RHS r goes to component r % 2 of complex grid r / 2
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     for (int idx = threadIdx.x; idx < nr * vol; idx += kBlock) {
         const int i = idx / vol, c = idx - i * vol;
@@ -269,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
     const int ox0 = tx * w.tb[0], oy0 = ty * w.tb[1], oz0 = tz * w.tb[2];
 
     // stage the sub-grid (both components of each complex grid at once)
-    const real *H = (const real *)w.H;
+    const gptr<const real> H = gbl((const real *)w.H);
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     const int np = (nr + 1) >> 1;
     const int p0 = r0 >> 1;
@@ -293,10 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, g = lane & 15;
     real *mywv = wv + (wave * 4 + grp) * (D * kMaxW);
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const int W = w.W, m = w.m;
     const real mm = (real)m, bb = (real)w.b, ie = (real)w.inv_e2bm;
-    real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0;
+    const gptr<real> dst = gbl((real *)w.Yw) + (int64_t)o * w.N * w.Rcap + r0;
 
     for (int base = wave * 4; base < ch.count; base += 16) {
         const int p = base + grp;
@@ -363,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(const WinDev *__restrict__ wi
                 acc[i] += __shfl_xor(acc[i], off, kGroup);
         }
         if (act) {
-            const int orig = w.perm[j];
+            const int orig = gbl(w.perm)[j];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
                 if (i == g && i < nr)
@@ -447,8 +468,8 @@ struct FftCall {
 // Array dims (x, y, z) of the stage's input and output and their pointers.
 template <typename real>
 struct StageArrays {
-    const cpx<real> *in;
-    cpx<real> *out;
+    gptr<const cpx<real>> in;
+    gptr<cpx<real>> out;
     int din[3], dout[3];
 };
 
@@ -459,38 +480,38 @@ __device__ __forceinline__ void select_arrays(const WinDev &w, int pair, int o, 
     const int64_t po = (int64_t)o * w.npair_cap + pair;
     auto set = [](int *dd, int a, int b, int c) { dd[0] = a; dd[1] = b; dd[2] = c; };
     if (MODE == 0 && AXIS == 0) {  // G -> A1
-        sa.in = (const cpx<real> *)w.G + pair * w.szG;
-        sa.out = (cpx<real> *)w.A1 + pair * w.szA1;
+        sa.in = gbl((const cpx<real> *)w.G) + pair * w.szG;
+        sa.out = gbl((cpx<real> *)w.A1) + pair * w.szA1;
         set(sa.din, ex, ey, ez);
         set(sa.dout, n1, ey, ez);
     } else if (MODE == 0 && AXIS == 1) {  // A1 -> A2
-        sa.in = (const cpx<real> *)w.A1 + pair * w.szA1;
-        sa.out = (cpx<real> *)w.A2 + pair * w.szA2;
+        sa.in = gbl((const cpx<real> *)w.A1) + pair * w.szA1;
+        sa.out = gbl((cpx<real> *)w.A2) + pair * w.szA2;
         set(sa.din, n1, ey, ez);
         set(sa.dout, n1, n1, ez);
     } else if (MODE == 2 && AXIS == 2) {  // A2 -> A3[o]
-        sa.in = (const cpx<real> *)w.A2 + pair * w.szA2;
-        sa.out = (cpx<real> *)w.A3 + po * w.szA3;
+        sa.in = gbl((const cpx<real> *)w.A2) + pair * w.szA2;
+        sa.out = gbl((cpx<real> *)w.A3) + po * w.szA3;
         set(sa.din, n1, n1, ez);
         set(sa.dout, n1, n1, ez);
     } else if (MODE == 2 && AXIS == 1) {  // d = 2: A1 -> A3[o]
-        sa.in = (const cpx<real> *)w.A1 + pair * w.szA1;
-        sa.out = (cpx<real> *)w.A3 + po * w.szA3;
+        sa.in = gbl((const cpx<real> *)w.A1) + pair * w.szA1;
+        sa.out = gbl((cpx<real> *)w.A3) + po * w.szA3;
         set(sa.din, n1, ey, 1);
         set(sa.dout, n1, ey, 1);
     } else if (MODE == 2 && AXIS == 0) {  // d = 1: G -> H[o]
-        sa.in = (const cpx<real> *)w.G + pair * w.szG;
-        sa.out = (cpx<real> *)w.H + po * w.szH;
+        sa.in = gbl((const cpx<real> *)w.G) + pair * w.szG;
+        sa.out = gbl((cpx<real> *)w.H) + po * w.szH;
         set(sa.din, ex, 1, 1);
         set(sa.dout, ex, 1, 1);
     } else if (MODE == 1 && AXIS == 1) {  // A3[o] -> A4[o]
-        sa.in = (const cpx<real> *)w.A3 + po * w.szA3;
-        sa.out = (cpx<real> *)w.A4 + po * w.szA4;
+        sa.in = gbl((const cpx<real> *)w.A3) + po * w.szA3;
+        sa.out = gbl((cpx<real> *)w.A4) + po * w.szA4;
         set(sa.din, n1, n1, ez);
         set(sa.dout, n1, ey, ez);
     } else {  // MODE 1, AXIS 0: d = 3 A4[o] -> H[o], d = 2 A3[o] -> H[o]
-        sa.in = w.d == 3 ? (const cpx<real> *)w.A4 + po * w.szA4 : (const cpx<real> *)w.A3 + po * w.szA3;
-        sa.out = (cpx<real> *)w.H + po * w.szH;
+        sa.in = w.d == 3 ? gbl((const cpx<real> *)w.A4) + po * w.szA4 : gbl((const cpx<real> *)w.A3) + po * w.szA3;
+        sa.out = gbl((cpx<real> *)w.H) + po * w.szH;
         set(sa.din, n1, ey, ez);
         set(sa.dout, ex, ey, ez);
     }
@@ -526,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     C *buf1 = buf0 + L * call.nos_lds;
     C *buf2 = buf1 + L * call.nos_lds;  // allocated for MODE 2 only
     for (int q = threadIdx.x; q < nos / 2; q += kBlock)
-        tw[q] = ((const C *)w.tw)[q];
+        tw[q] = ldc<real>(gbl((const C *)w.tw) + q);
 
     // lines of this group: coordinates (a, b) of the two non-transform axes
     const int *dims = sa.din;
@@ -570,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
         }
         if (l < nvalid) {
             const int p = MODE == 1 ? (q - half + nos) % nos : w.lo[AXIS] + q;
-            buf0[l * nos + p] = sa.in[addr(sa.din, l, q)];
+            buf0[l * nos + p] = ldc<real>(sa.in + addr(sa.din, l, q));
         }
     }
     __syncthreads();
@@ -590,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
             }
             if (l < nvalid) {
                 const int p = MODE == 0 ? (q - half + nos) % nos : w.lo[AXIS] + q;
-                sa.out[addr(sa.dout, l, q)] = res[l * nos + p];
+                stc<real>(sa.out + addr(sa.dout, l, q), res[l * nos + p]);
             }
         }
         return;
@@ -612,15 +633,15 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
     for (int a = 0; a < AXIS; ++a)
         stride_c *= n1;
     if (call.modes_sel) {
-        C *M = (C *)(call.modes_sel == 1 ? w.Vm : w.Gm) + (int64_t)pair * w.szM;
+        const gptr<C> M = gbl((C *)(call.modes_sel == 1 ? w.Vm : w.Gm)) + (int64_t)pair * w.szM;
         for (int t = threadIdx.x; t < L * n1; t += kBlock) {
             const int l = t % L, c = t / L;
             if (l < nvalid)
-                M[c * stride_c + lineoff(l)] = fw[l * nos + (c - half + nos) % nos];
+                stc<real>(M + c * stride_c + lineoff(l), fw[l * nos + (c - half + nos) % nos]);
         }
     }
     for (int oo = 0; oo < call.nout; ++oo) {
-        const real *B = (const real *)(oo == 0 ? w.Bk : w.Bd);
+        const gptr<const real> B = gbl((const real *)(oo == 0 ? w.Bk : w.Bd));
         for (int i = threadIdx.x; i < L * nos; i += kBlock)
             x0[i] = {real(0), real(0)};
         __syncthreads();
@@ -636,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
         __syncthreads();
         C *r2 = fft_lines<real>(x0, x1, tw, nos, L, real(1));
         __syncthreads();
-        C *out = sa.out + (int64_t)oo * w.npair_cap * w.szH * (AXIS == 0) +
+        const gptr<C> out = sa.out + (int64_t)oo * w.npair_cap * w.szH * (AXIS == 0) +
                  (int64_t)oo * w.npair_cap * w.szA3 * (AXIS != 0);
         for (int t = threadIdx.x; t < L * Lout; t += kBlock) {
             int l, q;
@@ -648,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(const WinDev *__restrict__ wins,
                 q = t / L;
             }
             if (l < nvalid)
-                out[addr(sa.dout, l, q)] = r2[l * nos + w.lo[AXIS] + q];
+                stc<real>(out + addr(sa.dout, l, q), r2[l * nos + w.lo[AXIS] + q]);
         }
         __syncthreads();
         if (r2 != x0) {  // keep x0/x1 roles for the next output
@@ -679,8 +700,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restric
         double y[kCombineRowsMaxR] = {};
         for (int k = 0; k < nwin; ++k) {
             const WinDev &w = wins[p.wbeg + k];
-            const real *src = (const real *)w.Yw + i * w.Rcap;
-            const real *dsrc = (const real *)w.Yw + ((int64_t)w.N + i) * w.Rcap;
+            const gptr<const real> src = gbl((const real *)w.Yw) + i * w.Rcap;
+            const gptr<const real> dsrc = gbl((const real *)w.Yw) + ((int64_t)w.N + i) * w.Rcap;
             const int64_t blk = (int64_t)k * p.ldy * R;  // window k's block of dY/dl, dY/dsigma
 #pragma unroll
             for (int r = 0; r < kCombineRowsMaxR; ++r) {
@@ -690,16 +711,16 @@ __global__ __launch_bounds__(kBlock) void k_combine_rows(const WinDev *__restric
                 const int64_t at = blk + iy + (int64_t)r * p.ldy;
                 y[r] += w.sig2 * v;
                 if (want_ds)
-                    p.dYs[at] = w.dsig * v;
+                    gbl(p.dYs)[at] = w.dsig * v;
                 if (want_dl)
-                    p.dYl[at] = w.der_scale * (double)dsrc[r];
+                    gbl(p.dYl)[at] = w.der_scale * (double)dsrc[r];
             }
         }
         if (want_y)
 #pragma unroll
             for (int r = 0; r < kCombineRowsMaxR; ++r)
                 if (r < R)
-                    p.Y[iy + (int64_t)r * p.ldy] = y[r];
+                    gbl(p.Y)[iy + (int64_t)r * p.ldy] = y[r];
     }
 }
 
@@ -731,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                 const WinDev &w = wins[p.wbeg + k / nout];
                 const int o = k % nout;
                 const int64_t ip = i0 + pl;
-                v = ip < p.N && r4 < nr ? *(const v4r *)((const real *)w.Yw + ((int64_t)o * w.N + ip) * w.Rcap + r0 + r4)
+                v = ip < p.N && r4 < nr ? *(gptr<const v4r>)(gbl((const real *)w.Yw) + ((int64_t)o * w.N + ip) * w.Rcap + r0 + r4)
                                         : v4r{real(0), real(0), real(0), real(0)};
             };
             constexpr int DEP = kCombineDepth;
@@ -767,9 +788,9 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
                         if (o == 0) {
                             y[q] += w.sig2 * v;
                             if ((mode & 2) && p.dYs)
-                                p.dYs[blk + at] = w.dsig * v;
+                                gbl(p.dYs)[blk + at] = w.dsig * v;
                         } else {
-                            p.dYl[blk + at] = w.der_scale * v;
+                            gbl(p.dYl)[blk + at] = w.der_scale * v;
                         }
                     }
                 }
@@ -778,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const WinDev *__restrict__ w
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     if (rq + 4 * q < nr)
-                        p.Y[iy + (int64_t)(r0 + rq + 4 * q) * p.ldy] = y[q];
+                        gbl(p.Y)[iy + (int64_t)(r0 + rq + 4 * q) * p.ldy] = y[q];
         }
     }
 }
@@ -793,14 +814,14 @@ __global__ __launch_bounds__(kBlock) void k_mode_dot(const WinDev *__restrict__ 
 {
     const WinDev &w = wins[win];
     const int64_t total = (int64_t)npair * w.szM;
-    const cpx<real> *Gm = (const cpx<real> *)w.Gm;
-    const cpx<real> *Vm = (const cpx<real> *)w.Vm;
-    const real *Bk = (const real *)w.Bk;
-    const real *Bd = (const real *)w.Bd;
+    const gptr<const cpx<real>> Gm = gbl((const cpx<real> *)w.Gm);
+    const gptr<const cpx<real>> Vm = gbl((const cpx<real> *)w.Vm);
+    const gptr<const real> Bk = gbl((const real *)w.Bk);
+    const gptr<const real> Bd = gbl((const real *)w.Bd);
     double sk = 0.0, sd = 0.0;
     for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
         const int64_t idx = e % w.szM;
-        const cpx<real> g = Gm[e], v = Vm[e];
+        const cpx<real> g = ldc<real>(Gm + e), v = ldc<real>(Vm + e);
         const double re = (double)g.x * (double)v.x + (double)g.y * (double)v.y;
         sk += (double)Bk[idx] * re;
         sd += (double)Bd[idx] * re;

@@ -162,7 +162,7 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, real (*slab)[NO][S
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, mrow = lane & 15;
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
-    const real *H = (const real *)w.H;
+    const gptr<const real> H = gbl((const real *)w.H);
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     const int p0 = r0 >> 1;
     const int np = (nr + 1) >> 1;
@@ -184,7 +184,9 @@ __device__ __forceinline__ void stream_slabs(const WinDev &w, real (*slab)[NO][S
                 if (idx < 8 * C && pi < np && ox < sx && oy < sy && gx < ex && gy < ey && gz < ez) {
                     const int64_t off =
                         ((int64_t)(o * w.npair_cap + p0 + pi) * w.szH + ((int64_t)gz * ey + gy) * ex + gx) * 2;
-                    v = *(const v2 *)(H + off);
+                    typedef real n2 __attribute__((ext_vector_type(2)));
+                    const n2 t2 = *(gptr<const n2>)(H + off);
+                    v = v2{t2.x, t2.y};
                 }
                 pre[o][k] = v;
             }
@@ -239,7 +241,7 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
     unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     // x weights stay in registers (lane q holds taps 4t + q); the y weights of
     // the wave's points go to its LDS area [g][oy][16 points], each lane
@@ -286,14 +288,14 @@ __device__ __forceinline__ void interp_dense_item(const WinDev &w, const Chunk &
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        const gptr<real> dst = gbl((real *)w.Yw) + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int p = (wave + 4 * g) * 16 + out_row<real>(q, i);
                 if (p < it.count)
-                    dst[(int64_t)w.perm[it.start + p] * w.Rcap] = acc[o][g][i];
+                    dst[(int64_t)gbl(w.perm)[it.start + p] * w.Rcap] = acc[o][g][i];
             }
     }
 }
@@ -314,7 +316,7 @@ __device__ __forceinline__ void interp_dense_item_z1(const WinDev &w, const Chun
     unpack_cell_m(it.tile, bx, by, bz, nzc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
-    const float *coords = (const float *)w.coords;
+    const gptr<const float> coords = gbl((const float *)w.coords);
     const float mm = (float)w.m, kb = (float)w.b, ie = (float)w.inv_e2bm;
     float *wyl = wy_lds + wave * (4 * W * 16);
     float wxq[NG][NT];
@@ -380,7 +382,7 @@ __device__ __forceinline__ void interp_dense_item_z1(const WinDev &w, const Chun
                 for (int s = 8; s > 0; s >>= 1)
                     v += __shfl_xor(v, s, 16);
                 if (act && mrow == 0)
-                    ((float *)w.Yw)[((int64_t)o * w.N + w.perm[it.start + p]) * w.Rcap] = v;
+                    gbl((float *)w.Yw)[((int64_t)o * w.N + gbl(w.perm)[it.start + p]) * w.Rcap] = v;
             }
         }
     }
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_interp_mfma_z1(const WinDev *__restr
     const int NS = W + nzc - 1;
     // stage RHS 0 (the real part of pair 0) of the item's block, zero outside
     // the grid box and past the item's slabs
-    const float *H = (const float *)w.H;
+    const gptr<const float> H = gbl((const float *)w.H);
     const int ex = w.ext[0], ey = w.ext[1], ez = w.ext[2];
     for (int e = threadIdx.x; e < NO * 16 * WW; e += kBlock) {
         const int o = e / (16 * WW), rem = e - o * (16 * WW), oz = rem / WW, tap = rem - oz * WW;
@@ -508,23 +510,36 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: slab branches are scalar
     const int q = lane >> 4, mrow = lane & 15;
     const int xi = mrow & 3, yi = mrow >> 2;  // the lane's tap within a square
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob_m(io, w.prob);
+    const gptr<const real> vp = gbl((const real *)pio.Vp);
+    const gptr<const int32_t> perm = gbl(w.perm);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     const int t = threadIdx.x;
 
     // prefetch registers: the coordinates behind this thread's window values
     // (entry e = p * PS + o of the round's table, o < W: x, o < 2W: y, else z;
     // e = t + k * kBlock) and KV RHS values; all threads then share the
-    // window evaluations
+    // window evaluations.  The RHS values are gathered through the point
+    // permutation, whose entries are loaded one round earlier still (pix), so
+    // that no load waits for another one issued just before it.
     constexpr int NWE = PB * PS;
     constexpr int KW = (NWE + kBlock - 1) / kBlock;
     real pcs[KW];
     real pvv[KV];
+    int pix[KV];
 #pragma unroll
     for (int k = 0; k < KV; ++k)
         pvv[k] = real(0);
-    auto load = [&](int p0) {
+    auto load_pix = [&](int p0) {
+        const int np = min(PB, it.count - p0);
+#pragma unroll
+        for (int k = 0; k < KV; ++k) {
+            const int p = (t + k * kBlock) >> 4;
+            pix[k] = p < np ? perm[it.start + p0 + p] : -1;
+        }
+    };
+    auto load = [&](int p0) {  // round p0's coordinates, and its RHS values through pix
         const int np = min(PB, it.count - p0);
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
@@ -535,11 +550,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         }
 #pragma unroll
         for (int k = 0; k < KV; ++k) {
-            const int e = t + k * kBlock;  // e < PB * 16
-            const int p = e >> 4, i = e & 15;
-            const int r = r0 + i;
-            pvv[k] = (p < np && r < R) ? ((const real *)pio.Vp)[(int64_t)w.perm[it.start + p0 + p] * pio.ldvp + r]
-                                       : real(0);
+            const int r = r0 + ((t + k * kBlock) & 15);
+            pvv[k] = (pix[k] >= 0 && r < R) ? vp[(int64_t)pix[k] * pio.ldvp + r] : real(0);
         }
     };
     // Straight-line code (selects, no branches) so that the compiler can
@@ -602,21 +614,30 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             zy[j] = W + 4 * (mt / NX - ty0) + yi;
         }
     }
+    load_pix(0);
     load(0);
-    store_raw(rd[0], 0);
     if (PB < it.count)
+        load_pix(PB);
+    store_raw(rd[0], 0);
+    if (PB < it.count) {
         load(PB);  // the registers run one round ahead of the window values
+        if (2 * PB < it.count)
+            load_pix(2 * PB);
+    }
     __syncthreads();
     int buf = 0;
     for (int p0 = 0; p0 < it.count; p0 += PB) {
         const bool more = p0 + PB < it.count;
         // the next round's window values go to the other buffer, which no wave
         // reads any more (every wave passed the last round's closing barrier);
-        // then the registers take the round after it
+        // then the registers take the round after it (and pix the one after that)
         if (more) {
             store_raw(rd[buf ^ 1], p0 + PB);
-            if (p0 + 2 * PB < it.count)
+            if (p0 + 2 * PB < it.count) {
                 load(p0 + 2 * PB);
+                if (p0 + 3 * PB < it.count)
+                    load_pix(p0 + 3 * PB);
+            }
         }
         Round &cr = rd[buf];
         if constexpr (Z1) {
@@ -775,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
                   tz = to[2] - (NT - 1) + t / (NT * NT);
         int2 r = make_int2(0, 0);
         if (tx >= 0 && ty >= 0 && tz >= 0 && tx < w.ntile[0] && ty < w.ntile[1] && tz < w.ntile[2])
-            r = w.sp_rng[((int64_t)tz * w.ntile[1] + ty) * w.ntile[0] + tx];
+            r = ld_int2(gbl(w.sp_rng) + ((int64_t)tz * w.ntile[1] + ty) * w.ntile[0] + tx);
         rng[t] = r;
     }
     __syncthreads();
@@ -786,9 +807,9 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
     }
     __syncthreads();
     const int total = pre[NT3];
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const ProbDev pio = get_prob_m(io, w.prob);
-    const real *Vp = (const real *)pio.Vp;
+    const gptr<const real> Vp = gbl((const real *)pio.Vp);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     // staging: thread (pi = t / 4, k = t % 4) loads RHS 4k .. 4k + 3 of point pi
     // and, for k < 3, the point's window values along dimension k at the
@@ -810,8 +831,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
                     hi = mid - 1;
             }
             const int j = rng[lo].x + (f - pre[lo]);
-            const int64_t orig = w.perm[j];
-            const real *vr = Vp + orig * pio.ldvp + r0 + 4 * kq;
+            const int64_t orig = gbl(w.perm)[j];
+            const gptr<const real> vr = Vp + orig * pio.ldvp + r0 + 4 * kq;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 v[i] = vr[i];
@@ -848,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
     const int r = r0 + mrow;
     if (r >= R)
         return;
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int z = 4 * to[2] + wave;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -929,7 +950,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = tx * 4 + (lane & 3), gy = ty * 4 + ((lane >> 2) & 3), gz = tz * 4 + (lane >> 4);
     const int nb0 = w.nbase[0], nb1 = w.nbase[1], nb2 = w.nbase[2];
-    const int2 *map = w.dmap;
+    const gptr<const int2> map = gbl(w.dmap);
     f4 acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -943,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
     // stage the base-cell map of the candidate region in LDS (coalesced rows)
     for (int idx = threadIdx.x; idx < nx * ny * nz; idx += kBlock) {
         const int dx = idx % nx, dy = (idx / nx) % ny, dz = idx / (nx * ny);
-        cand[idx] = map[((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx];
+        cand[idx] = ld_int2(map + ((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx);
     }
     __syncthreads();
     // Per row of candidate cells, the cells holding items (a ballot over the
@@ -960,7 +981,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
             while (live) {
                 int2 its[CB];
                 bool in[CB];
-                const f4 *src[CB];
+                gptr<const f4> src[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
                     const int dx = live ? __builtin_ctzll(live) : 0;
@@ -972,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
                     in[k] = valid && (unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
                             (unsigned)oz < (unsigned)(W + nzc - 1);
                     const int tap = in[k] ? (oz * W + oy) * W + ox : 0;
-                    src[k] = (const f4 *)(scratch + (((int64_t)its[k].x * nrb + rb) * ((W + 1) * WW) + tap) * 16);
+                    src[k] = (gptr<const f4>)(gbl(scratch) + (((int64_t)its[k].x * nrb + rb) * ((W + 1) * WW) + tap) * 16);
                 }
                 f4 v[CB][4];
 #pragma unroll
@@ -990,7 +1011,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
                     for (int i = 1; i < cnt; ++i) {
                         if (!in[k])
                             break;
-                        const f4 *s2 = src[k] + (int64_t)i * nrb * ((W + 1) * WW) * 4;
+                        const gptr<const f4> s2 = src[k] + (int64_t)i * nrb * ((W + 1) * WW) * 4;
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             acc[j] += s2[j];
@@ -1015,13 +1036,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks(const WinDev *__restri
             acc[i] += red[k][lane][i];
     if (gx >= ex || gy >= ey || gz >= ez)
         return;
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
     // all loads of the cell's 8 complex grid values first, then the stores
     r2 g[8];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-        g[p] = r0 + 2 * p < R ? *(const r2 *)(G + ((int64_t)((r0 >> 1) + p) * w.szG + c) * 2) : r2{real(0), real(0)};
+    for (int p = 0; p < 8; ++p) {
+        typedef real n2 __attribute__((ext_vector_type(2)));
+        const n2 t2 = r0 + 2 * p < R ? *(gptr<const n2>)(G + ((int64_t)((r0 >> 1) + p) * w.szG + c) * 2) : n2{real(0), real(0)};
+        g[p] = r2{t2.x, t2.y};
+    }
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
         const int r = r0 + 2 * p;
@@ -1050,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = tx * 4 + (lane & 3), gy = ty * 4 + ((lane >> 2) & 3), gz = tz * 4 + (lane >> 4);
     const int nb0 = w.nbase[0], nb1 = w.nbase[1], nb2 = w.nbase[2];
-    const int2 *map = w.dmap;
+    const gptr<const int2> map = gbl(w.dmap);
     real acc = real(0);
     const int z0 = max(0, tz * 4 - W), z1 = min(nb2 - 1, tz * 4 + 3);
     const int y0 = max(0, ty * 4 - (W - 1)), y1 = min(nb1 - 1, ty * 4 + 3);
@@ -1059,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
     const int nx = any ? x1 - x0 + 1 : 0, ny = any ? y1 - y0 + 1 : 0, nz = any ? z1 - z0 + 1 : 0;
     for (int idx = threadIdx.x; idx < nx * ny * nz; idx += kBlock) {
         const int dx = idx % nx, dy = (idx / nx) % ny, dz = idx / (nx * ny);
-        cand[idx] = map[((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx];
+        cand[idx] = ld_int2(map + ((int64_t)(z0 + dz) * nb1 + y0 + dy) * nb0 + x0 + dx);
     }
     __syncthreads();
     for (int dz = wave; dz < nz; dz += 4) {
@@ -1071,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
             while (live) {
                 int2 its[CB];
                 bool in[CB];
-                const real *src[CB];
+                gptr<const real> src[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
                     const int dx = live ? __builtin_ctzll(live) : 0;
@@ -1083,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
                     in[k] = valid && (unsigned)ox < (unsigned)W && (unsigned)oy < (unsigned)W &&
                             (unsigned)oz < (unsigned)(W + nzc - 1);
                     const int tap = in[k] ? (oz * W + oy) * W + ox : 0;
-                    src[k] = scratch + (int64_t)its[k].x * ((W + 1) * WW) + tap;
+                    src[k] = gbl(scratch) + (int64_t)its[k].x * ((W + 1) * WW) + tap;
                 }
                 real v[CB];
 #pragma unroll
@@ -1112,7 +1136,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_blocks_1(const WinDev *__rest
         acc += red[k][lane];
     if (gx >= ex || gy >= ey || gz >= ez)
         return;
-    real *G = (real *)w.G;
+    const gptr<real> G = gbl((real *)w.G);
     const int64_t c = ((int64_t)gz * ey + gy) * ex + gx;
     G[c * 2] += acc;
 }
@@ -1133,7 +1157,7 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, mrow = lane & 15;
     typedef typename MfmaT<real>::v4 v4;
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const real mm = (real)w.m, kb = (real)w.b, ie = (real)w.inv_e2bm;
     real *wyl = wy_lds + wave * (tile_gmax<real>() * SY * 16);  // [g][oy][16 points]
     real wxq[NG][4], uz[NG];
@@ -1181,14 +1205,14 @@ __device__ __forceinline__ void interp_tile_pass(const WinDev &w, const Chunk &c
         return;
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        real *dst = (real *)w.Yw + (int64_t)o * w.N * w.Rcap + r0 + mrow;
+        const gptr<real> dst = gbl((real *)w.Yw) + (int64_t)o * w.N * w.Rcap + r0 + mrow;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int p = pass + (wave + 4 * g) * 16 + out_row<real>(q, i);
                 if (p < ch.count)
-                    dst[(int64_t)w.perm[ch.start + p] * w.Rcap] = acc[o][g][i];
+                    dst[(int64_t)gbl(w.perm)[ch.start + p] * w.Rcap] = acc[o][g][i];
             }
     }
 }

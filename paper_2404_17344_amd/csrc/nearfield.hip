@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
     const int r0 = blockIdx.y * RT;
     const int t = threadIdx.x;
     const ProbDev pio = nf_prob(io, w.prob);
-    const real *coords = (const real *)w.coords;
+    const gptr<const real> coords = gbl((const real *)w.coords);
     const bool own = t < ch.count;
     const int64_t i = ch.start + (own ? t : 0);
     real u[D];
@@ -136,13 +136,13 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
     }
     real sk = real(0), sd = real(0);
     if (DOT && own) {
-        const int orig = w.perm[i];
+        const int orig = gbl(w.perm)[i];
 #pragma unroll
         for (int r = 0; r < RT; ++r)
             vt[r] = r0 + r < R ? (real)Vt[orig + (int64_t)(r0 + r) * ldvt] : real(0);
     }
-    const real *vp = (const real *)pio.Vp;
-    const int32_t *toff = w.tile_off;
+    const gptr<const real> vp = gbl((const real *)pio.Vp);
+    const gptr<const int32_t> toff = gbl(w.tile_off);
     if (!none) {
         for (int tz = t0[2]; tz <= t1[2]; ++tz) {
             for (int ty = t0[1]; ty <= t1[1]; ++ty) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
 #pragma unroll
                         for (int a = 0; a < D; ++a)
                             sc[t][a] = coords[(int64_t)a * w.N + j];
-                        const int64_t orig = w.perm[j];
+                        const int64_t orig = gbl(w.perm)[j];
                         if (RT == 1)
                             sc[t][3] = vp[orig * pio.ldvp + r0];
                         else
@@ -263,10 +263,10 @@ __global__ __launch_bounds__(kNearBlock) void k_near(const WinDev *__restrict__ 
     }
     if (!own)
         return;
-    const int64_t orig = w.perm[i];
+    const int64_t orig = gbl(w.perm)[i];
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-        real *dst = (real *)w.Yw + ((int64_t)o * w.N + orig) * w.Rcap + r0;
+        const gptr<real> dst = gbl((real *)w.Yw) + ((int64_t)o * w.N + orig) * w.Rcap + r0;
 #pragma unroll
         for (int r = 0; r < RT; ++r)
             if (r0 + r < R)
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
     const WinDev &w = wins[ch.win];
     const int t = threadIdx.x;
     const ProbDev pio = nf_prob(io, w.prob);
-    const real *coords = (const real *)w.coords;
-    const real *vp = (const real *)pio.Vp;
+    const gptr<const real> coords = gbl((const real *)w.coords);
+    const gptr<const real> vp = gbl((const real *)pio.Vp);
     const bool own = t < ch.count;
     const int64_t i = ch.start + (own ? t : 0);
     const int cs = ch.start, ce = ch.start + ch.count;
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
 #pragma unroll
     for (int a = 0; a < D; ++a)
         u[a] = coords[(int64_t)a * w.N + i];
-    const int64_t oi = w.perm[i];
+    const int64_t oi = gbl(w.perm)[i];
     const real vi = own ? vp[oi * pio.ldvp] : real(0);
     float bmin[3] = {0.f, 0.f, 0.f}, bmax[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
 #pragma unroll
     for (int o = 0; o < NO; ++o)
         acc[o] = real(0);
-    double *ys = w.nf_ys;
+    const gptr<double> ys = gbl(w.nf_ys);
     // the sources [b, e), at most 64 of them
     auto batch = [&](int b, int e, bool sym) {
         const int n = __builtin_amdgcn_readfirstlane(e - b);
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
 #pragma unroll
             for (int a = 0; a < D; ++a)
                 sc[t][a] = coords[(int64_t)a * w.N + j];
-            sc[t][3] = vp[(int64_t)w.perm[j] * pio.ldvp];
+            sc[t][3] = vp[(int64_t)gbl(w.perm)[j] * pio.ldvp];
 #pragma unroll
             for (int o = 0; o < NO; ++o)
                 sa[t][o] = 0.0;
@@ -414,12 +414,12 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
                 for (int o = 0; o < NO; ++o) {
                     const double c = sa[t][o];
                     if (c != 0.0)
-                        unsafeAtomicAdd(ys + o * w.N + b + t, c);
+                        __hip_atomic_fetch_add(ys + o * w.N + b + t, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
     };
-    const int32_t *toff = w.tile_off;
+    const gptr<const int32_t> toff = gbl(w.tile_off);
     if (!none) {
         for (int tz = t0[2]; tz <= t1[2]; ++tz) {
             for (int ty = t0[1]; ty <= t1[1]; ++ty) {
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near_sym(const WinDev *__restric
     if (own) {
 #pragma unroll
         for (int o = 0; o < NO; ++o)
-            unsafeAtomicAdd(ys + o * w.N + i, (double)acc[o]);
+            __hip_atomic_fetch_add(ys + o * w.N + i, (double)acc[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -472,10 +472,10 @@ __global__ void k_near_scatter(const WinDev *__restrict__ wins, int nout)
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= w.N)
         return;
-    const int64_t oj = w.perm[j];
+    const int64_t oj = gbl(w.perm)[j];
     for (int o = 0; o < nout; ++o) {
-        double *src = w.nf_ys + o * w.N + j;
-        ((real *)w.Yw)[(o * w.N + oj) * w.Rcap] += (real)*src;
+        const gptr<double> src = gbl(w.nf_ys) + o * w.N + j;
+        gbl((real *)w.Yw)[(o * w.N + oj) * w.Rcap] += (real)*src;
         *src = 0.0;
     }
 }
