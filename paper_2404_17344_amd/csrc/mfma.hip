@@ -614,6 +614,54 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             zy[j] = W + 4 * (mt / NX - ty0) + yi;
         }
     }
+    // Operands of one K step (four points): the lane's x weights (one per
+    // column of squares) and y weights (one per row of squares of this
+    // block), the slab-2m A values, and the B factors (RHS value, z weights of
+    // the wave's slabs).  In full rounds the next step's operands are read
+    // from LDS before this step's matrix ops issue, so the reads overlap them.
+    struct Ops {
+        real wx[NX], wy[NYB], ax[XT], v, wz[SPW + 1];
+    };
+    auto fetch = [&](const Round &cr, int ks, Ops &o) {
+        const int pk = 4 * ks + q;
+        const real *pw = cr.pw[pk];
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            o.wx[i] = pw[4 * i + xi];
+#pragma unroll
+        for (int i = 0; i < NYB; ++i)
+            o.wy[i] = pw[W + 4 * i + yi];
+#pragma unroll
+        for (int j = 0; j < XT; ++j)
+            o.ax[j] = pw[zx[j]] * pw[zy[j]];
+        o.v = cr.pv[pk][mrow];
+#pragma unroll
+        for (int s = 0; s < SPW; ++s)
+            o.wz[s] = pw[ZO + wave + 4 * s];
+        o.wz[SPW] = pw[ZO + W];  // slab 2m: zero for single-cell items
+    };
+    auto step = [&](const Ops &o) {
+        real a[MTB];
+#pragma unroll
+        for (int mt = 0; mt < MTB; ++mt)
+            a[mt] = o.wx[mt % NX] * o.wy[mt / NX];
+        // the point's z weight of the slab scales the B operand (its RHS
+        // values), so the A operand is the plain x-y weight product
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) {
+            const real b = o.v * o.wz[s];
+#pragma unroll
+            for (int mt = 0; mt < MTB; ++mt)
+                acc[s][mt] = mfma4(a[mt], b, acc[s][mt]);
+        }
+        if constexpr (TWO) {  // slab 2m: two-cell items only
+            const real bx2 = o.v * o.wz[SPW];
+#pragma unroll
+            for (int j = 0; j < XT; ++j)
+                accx[j] = mfma4(o.ax[j], bx2, accx[j]);
+        }
+    };
+
     load_pix(0);
     load(0);
     if (PB < it.count)
@@ -626,7 +674,12 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     }
     __syncthreads();
     int buf = 0;
-    for (int p0 = 0; p0 < it.count; p0 += PB) {
+    // FP32 (not Z1): the full rounds here, and a partial last round after the
+    // loop with only the K steps it fills; otherwise every round here (in
+    // FP64 the separate last-round loop costs registers: 228 -> 308)
+    constexpr bool TAIL = !Z1 && sizeof(real) == 4;
+    const int pend = TAIL ? it.count / PB * PB : it.count;
+    for (int p0 = 0; p0 < pend; p0 += PB) {
         const bool more = p0 + PB < it.count;
         // the next round's window values go to the other buffer, which no wave
         // reads any more (every wave passed the last round's closing barrier);
@@ -654,63 +707,34 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 }
             }
         } else {
-        // Operands of one K step (four points): the lane's x weights (one per
-        // column of squares) and y weights (one per row of squares of this
-        // block), the slab-2m A values, and the B factors (RHS value, z
-        // weights of the wave's slabs).  The next step's operands are read
-        // from LDS before this step's matrix ops issue, so the reads overlap
-        // them.
-        struct Ops {
-            real wx[NX], wy[NYB], ax[XT], v, wz[SPW + 1];
-        };
-        auto fetch = [&](int ks, Ops &o) {
-            const int pk = 4 * ks + q;
-            const real *pw = cr.pw[pk];
+            Ops ops[2];
+            fetch(cr, 0, ops[0]);
 #pragma unroll
-            for (int i = 0; i < NX; ++i)
-                o.wx[i] = pw[4 * i + xi];
-#pragma unroll
-            for (int i = 0; i < NYB; ++i)
-                o.wy[i] = pw[W + 4 * i + yi];
-#pragma unroll
-            for (int j = 0; j < XT; ++j)
-                o.ax[j] = pw[zx[j]] * pw[zy[j]];
-            o.v = cr.pv[pk][mrow];
-#pragma unroll
-            for (int s = 0; s < SPW; ++s)
-                o.wz[s] = pw[ZO + wave + 4 * s];
-            o.wz[SPW] = pw[ZO + W];  // slab 2m: zero for single-cell items
-        };
-        Ops ops[2];
-        fetch(0, ops[0]);
-#pragma unroll
-        for (int ks = 0; ks < PB / 4; ++ks) {
-            const Ops &o = ops[ks & 1];
-            if (ks + 1 < PB / 4)
-                fetch(ks + 1, ops[(ks + 1) & 1]);
-            real a[MTB];
-#pragma unroll
-            for (int mt = 0; mt < MTB; ++mt)
-                a[mt] = o.wx[mt % NX] * o.wy[mt / NX];
-            // the point's z weight of the slab scales the B operand (its RHS
-            // values), so the A operand is the plain x-y weight product
-#pragma unroll
-            for (int s = 0; s < SPW; ++s) {
-                const real b = o.v * o.wz[s];
-#pragma unroll
-                for (int mt = 0; mt < MTB; ++mt)
-                    acc[s][mt] = mfma4(a[mt], b, acc[s][mt]);
+            for (int ks = 0; ks < PB / 4; ++ks) {
+                const Ops &o = ops[ks & 1];
+                if (ks + 1 < PB / 4)
+                    fetch(cr, ks + 1, ops[(ks + 1) & 1]);
+                step(o);
+                // schedule the step as: the next step's LDS reads, this step's
+                // operand products, its matrix ops (left to itself, the compiler
+                // interleaves the reads with the matrix ops and waits for each)
+                __builtin_amdgcn_sched_group_barrier(0x100, 64, 0);  // LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x002, 64, 0);  // vector ALU
+                __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);  // matrix ops
             }
-            if constexpr (TWO) {  // slab 2m: two-cell items only
-                const real bx2 = o.v * o.wz[SPW];
-#pragma unroll
-                for (int j = 0; j < XT; ++j)
-                    accx[j] = mfma4(o.ax[j], bx2, accx[j]);
-            }
-        }
         }
         __syncthreads();
         buf ^= 1;
+    }
+    if constexpr (TAIL) {
+        // the last round's points (its window values are in rd[buf])
+        const int nks = (it.count - pend + 3) >> 2;
+#pragma unroll 1
+        for (int ks = 0; ks < nks; ++ks) {
+            Ops o;
+            fetch(rd[buf], ks, o);
+            step(o);
+        }
     }
 
     // write the item's block [oz][oy][ox][16 RHS] to its scratch slot (plain
