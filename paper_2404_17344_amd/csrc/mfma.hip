@@ -489,8 +489,10 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     constexpr int NYV = Z1 ? W : 4 * NYB;  // y window values per point: the y taps of this block's squares
     constexpr int ZO = W + NYV;            // offset of the z values
     constexpr int PS = ZO + W + 1;         // window values per point: x [W], y [NYV], z [W + 1] (item slabs)
+    constexpr int NWE = PB * PS;                     // window values per round
+    constexpr int KW = (NWE + kBlock - 1) / kBlock;  // window values per thread and round
     struct Round {
-        real pw[PB][PS];
+        real pw[KW * kBlock];  // [PB][PS] and the last thread slice's unused entries
         real pv[PB][16];
     };
     __shared__ __align__(16) Round rd[2];
@@ -523,8 +525,6 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // window evaluations.  The RHS values are gathered through the point
     // permutation, whose entries are loaded one round earlier still (pix), so
     // that no load waits for another one issued just before it.
-    constexpr int NWE = PB * PS;
-    constexpr int KW = (NWE + kBlock - 1) / kBlock;
     real pcs[KW];
     real pvv[KV];
     int pix[KV];
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // interleave it with the matrix ops of the current round.
     auto store_raw = [&](Round &d, int p0) {
         const int np = min(PB, it.count - p0);
-        real *pw = &d.pw[0][0];
+        real *pw = d.pw;
 #pragma unroll
         for (int k = 0; k < KW; ++k) {
             const int e = t + k * kBlock;
@@ -577,6 +577,41 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         for (int k = 0; k < KV; ++k) {
             const int e = t + k * kBlock;
             d.pv[e >> 4][e & 15] = pvv[k];
+        }
+    };
+    // The same work in slices, one per K step of round p0 (FP32): slice k < KW
+    // writes window value slice k of round p0 + PB to nx and loads its
+    // coordinate for round p0 + 2 PB; slice KW + j writes RHS slice j, loads
+    // it for round p0 + 2 PB (through pix) and pix for round p0 + 3 PB.  Every
+    // lane loads from a valid address and keeps the value as loaded (no select
+    // that the compiler would turn into a branch around the load and a wait
+    // for it): lanes past the item take its first point, whose window values
+    // there are zero, and RHS columns past R read the zero padding of the
+    // point-major copy.  The slices are then straight-line code that the
+    // scheduler can place among the matrix ops.
+    auto slice = [&](Round &nx, int p0, int k) {
+        if (k < KW) {
+            const int np = min(PB, it.count - (p0 + PB));
+            const int e = t + k * kBlock;
+            const int p = e / PS, o = e - p * PS;
+            const int oz = o - ZO;
+            const int dz = (int)floor(pcs[k]) - w.m + 1 - bz;
+            const real c = o < W ? (real)(bx + o) : (o < ZO ? (real)(by + 4 * ty0 + o - W) : (real)(bz + oz));
+            const bool live = p < np && (o < ZO || (unsigned)(oz - dz) < (unsigned)W);
+            const real v = kb_psi_m(pcs[k] - c, mm, kb, ie);
+            nx.pw[e] = live ? v : real(0);
+            const int np2 = min(PB, it.count - (p0 + 2 * PB));
+            const int dd = o < W ? 0 : (o < ZO ? 1 : 2);
+            pcs[k] = coords[dd * w.N + it.start + (e < NWE && p < np2 ? p0 + 2 * PB + p : 0)];
+        } else if (k < KW + KV) {
+            const int j = k - KW;
+            const int e = t + j * kBlock;
+            nx.pv[e >> 4][e & 15] = pvv[j];
+            const int r = r0 + (e & 15);  // r < ldvp (RHS padded to 16 with zeros)
+            pvv[j] = vp[(int64_t)max(pix[j], 0) * pio.ldvp + r];
+            const int np3 = min(PB, it.count - (p0 + 3 * PB));
+            const int p = e >> 4;
+            pix[j] = perm[it.start + (p < np3 ? p0 + 3 * PB + p : 0)];
         }
     };
 
@@ -624,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     };
     auto fetch = [&](const Round &cr, int ks, Ops &o) {
         const int pk = 4 * ks + q;
-        const real *pw = cr.pw[pk];
+        const real *pw = cr.pw + pk * PS;
 #pragma unroll
         for (int i = 0; i < NX; ++i)
             o.wx[i] = pw[4 * i + xi];
@@ -678,13 +713,17 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     // loop with only the K steps it fills; otherwise every round here (in
     // FP64 the separate last-round loop costs registers: 228 -> 308)
     constexpr bool TAIL = !Z1 && sizeof(real) == 4;
+    // FP32 (not Z1): the next round's window values and loads in slices inside
+    // the K loop
+    constexpr bool PIPE = TAIL;
+    static_assert(!PIPE || KW + KV <= PB / 4, "one slice per K step");
     const int pend = TAIL ? it.count / PB * PB : it.count;
     for (int p0 = 0; p0 < pend; p0 += PB) {
         const bool more = p0 + PB < it.count;
         // the next round's window values go to the other buffer, which no wave
         // reads any more (every wave passed the last round's closing barrier);
         // then the registers take the round after it (and pix the one after that)
-        if (more) {
+        if (!PIPE && more) {
             store_raw(rd[buf ^ 1], p0 + PB);
             if (p0 + 2 * PB < it.count) {
                 load(p0 + 2 * PB);
@@ -698,12 +737,13 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int ks = 0; ks < PB / 4; ++ks) {
                 const int pk = 4 * ks + q;
                 // B[point][slab mrow] = v wz(slab); zero past the item's 2m + 1 slabs
-                const real b = mrow <= W ? cr.pv[pk][0] * cr.pw[pk][ZO + min(mrow, W)] : real(0);
+                const real *pw = cr.pw + pk * PS;
+                const real b = mrow <= W ? cr.pv[pk][0] * pw[ZO + min(mrow, W)] : real(0);
 #pragma unroll
                 for (int j = 0; j < JT; ++j) {
                     const int mt = wave + 4 * j;
                     if (mt < MT)
-                        accz[j] = mfma4(cr.pw[pk][zx[j]] * cr.pw[pk][zy[j]], b, accz[j]);
+                        accz[j] = mfma4(pw[zx[j]] * pw[zy[j]], b, accz[j]);
                 }
             }
         } else {
@@ -714,6 +754,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 const Ops &o = ops[ks & 1];
                 if (ks + 1 < PB / 4)
                     fetch(cr, ks + 1, ops[(ks + 1) & 1]);
+                if constexpr (PIPE)
+                    slice(rd[buf ^ 1], p0, ks);  // past the last round: unused values, no reads past the item
                 step(o);
                 // schedule the step as: the next step's LDS reads, this step's
                 // operand products, its matrix ops (left to itself, the compiler
@@ -721,6 +763,12 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                 __builtin_amdgcn_sched_group_barrier(0x100, 64, 0);  // LDS reads
                 __builtin_amdgcn_sched_group_barrier(0x002, 64, 0);  // vector ALU
                 __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);  // matrix ops
+                if constexpr (PIPE) {
+                    // the slice's LDS write and loads stay in their step, a
+                    // round ahead of the slice that uses the loaded values
+                    __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);  // LDS writes
+                    __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);  // memory reads
+                }
             }
         }
         __syncthreads();
