@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             o.wz[s] = pw[ZO + wave + 4 * s];
         o.wz[SPW] = pw[ZO + W];  // slab 2m: zero for single-cell items
     };
-    auto step = [&](const Ops &o) {
+    auto step = [&](const Ops &o, auto xtag) {
         real a[MTB];
 #pragma unroll
         for (int mt = 0; mt < MTB; ++mt)
@@ -689,14 +689,42 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
             for (int mt = 0; mt < MTB; ++mt)
                 acc[s][mt] = mfma4(a[mt], b, acc[s][mt]);
         }
-        if constexpr (TWO) {  // slab 2m: two-cell items only
+        if constexpr (decltype(xtag)::value) {  // slab 2m: two-cell items only
             const real bx2 = o.v * o.wz[SPW];
 #pragma unroll
             for (int j = 0; j < XT; ++j)
                 accx[j] = mfma4(o.ax[j], bx2, accx[j]);
         }
     };
+    const std::integral_constant<bool, TWO> with_x;
 
+    // FP32 (not Z1): the full rounds in the main loop, and a partial last
+    // round after it with only the K steps it fills; otherwise every round in
+    // the main loop (in FP64 the separate last-round loop costs registers:
+    // 228 -> 308)
+    constexpr bool TAIL = !Z1 && sizeof(real) == 4;
+    // FP32 (not Z1): the next round's window values and loads in slices inside
+    // the K loop
+    constexpr bool PIPE = TAIL;
+    static_assert(!PIPE || KW + KV <= PB / 4, "one slice per K step");
+    // FP32 two-cell items: the points before the first one with a weight in
+    // slab 2m (the item's points are ordered by cell, the lower one first)
+    // skip slab 2m's matrix ops in the rounds they fill
+    constexpr bool SKIPX = PIPE && TWO;
+    __shared__ int first_x[SKIPX ? 4 : 1];
+    if constexpr (SKIPX) {
+        int f = it.count;
+        for (int j = t; j < it.count; j += kBlock) {
+            const real uz = coords[2 * w.N + it.start + j];
+            if ((int)floor(uz) - w.m + 1 - bz > 0)
+                f = min(f, j);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            f = min(f, __shfl_xor(f, o));
+        if (lane == 0)
+            first_x[wave] = f;  // read after the barrier below
+    }
     load_pix(0);
     load(0);
     if (PB < it.count)
@@ -709,16 +737,8 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
     }
     __syncthreads();
     int buf = 0;
-    // FP32 (not Z1): the full rounds here, and a partial last round after the
-    // loop with only the K steps it fills; otherwise every round here (in
-    // FP64 the separate last-round loop costs registers: 228 -> 308)
-    constexpr bool TAIL = !Z1 && sizeof(real) == 4;
-    // FP32 (not Z1): the next round's window values and loads in slices inside
-    // the K loop
-    constexpr bool PIPE = TAIL;
-    static_assert(!PIPE || KW + KV <= PB / 4, "one slice per K step");
     const int pend = TAIL ? it.count / PB * PB : it.count;
-    for (int p0 = 0; p0 < pend; p0 += PB) {
+    auto round = [&](int p0, auto xtag) {
         const bool more = p0 + PB < it.count;
         // the next round's window values go to the other buffer, which no wave
         // reads any more (every wave passed the last round's closing barrier);
@@ -756,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
                     fetch(cr, ks + 1, ops[(ks + 1) & 1]);
                 if constexpr (PIPE)
                     slice(rd[buf ^ 1], p0, ks);  // past the last round: unused values, no reads past the item
-                step(o);
+                step(o, xtag);
                 // schedule the step as: the next step's LDS reads, this step's
                 // operand products, its matrix ops (left to itself, the compiler
                 // interleaves the reads with the matrix ops and waits for each)
@@ -773,7 +793,15 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         }
         __syncthreads();
         buf ^= 1;
+    };
+    int p0 = 0;
+    if constexpr (SKIPX) {
+        const int fx = min(min(first_x[0], first_x[1]), min(first_x[2], first_x[3]));
+        for (; p0 + PB <= min(fx, pend); p0 += PB)
+            round(p0, std::false_type());
     }
+    for (; p0 < pend; p0 += PB)
+        round(p0, with_x);
     if constexpr (TAIL) {
         // the last round's points (its window values are in rd[buf])
         const int nks = (it.count - pend + 3) >> 2;
@@ -781,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_mfma(const WinDev *__restrict
         for (int ks = 0; ks < nks; ++ks) {
             Ops o;
             fetch(rd[buf], ks, o);
-            step(o);
+            step(o, with_x);
         }
     }
 
