@@ -882,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
     constexpr int PB = 64;               // points per round (16 K steps)
     __shared__ int pre[NT3 + 1];
     __shared__ int2 rng[NT3];
-    __shared__ real pw[PB][3][4];        // window values at the tile's 4 cells per dimension
+    __shared__ __align__(16) real pw[PB][3][4];  // window values at the tile's 4 cells per dimension
     __shared__ __align__(16) real pv[PB][16];
     const LineGroup g = tiles[blockIdx.x];
     const WinDev &w = wins[g.win];
@@ -946,12 +946,12 @@ __global__ __launch_bounds__(kBlock) void k_spread_sparse_mfma(const WinDev *__r
                 }
             }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            pv[pi][4 * kq + i] = r0 + 4 * kq + i < R ? v[i] : real(0);
-            if (kq < 3)
-                pw[pi][kq][i] = wk[i];
-        }
+        // one 4-vector store per array: the lanes' stores are consecutive
+        // (four scalar stores at a stride of four words conflict in the banks)
+        *(v4 *)&pv[pi][4 * kq] = v4{r0 + 4 * kq < R ? v[0] : real(0), r0 + 4 * kq + 1 < R ? v[1] : real(0),
+                                    r0 + 4 * kq + 2 < R ? v[2] : real(0), r0 + 4 * kq + 3 < R ? v[3] : real(0)};
+        if (kq < 3)
+            *(v4 *)&pw[pi][kq][0] = v4{wk[0], wk[1], wk[2], wk[3]};
         __syncthreads();
         const int np = min(PB, total - p0);
 #pragma unroll
