@@ -1266,12 +1266,37 @@ addk_status engine_build_device(Engine &E, int precision)
         }
     }
     // d = 3 spread items: two-cell items first (stable, so that the items of one
-    // anchor cell stay consecutive), each part spread by its own kernel variant
+    // anchor cell stay consecutive), each part spread by its own kernel variant.
+    // Inside each part the anchors run heaviest first (by their first item, the
+    // largest), so that the long blocks do not start last; an anchor's items
+    // stay consecutive and in order (the gather's block map and its sum order
+    // depend only on that).
     for (int wi = 0; wi < 2; ++wi) {
         std::vector<Chunk> &v = dsp[3][wi];
         auto two = [](const Chunk &c) { return ((c.tile >> 30) & 1) != 0; };
         std::stable_partition(v.begin(), v.end(), two);
         E.ndense_sp2[wi] = (int)std::count_if(v.begin(), v.end(), two);
+        auto heaviest_first = [&v](size_t b, size_t e) {
+            std::vector<std::pair<size_t, size_t>> runs;  // [first, end) of each anchor's items
+            for (size_t i = b; i < e;) {
+                size_t j = i + 1;
+                while (j < e && v[j].win == v[i].win && v[j].tile == v[i].tile)
+                    ++j;
+                runs.push_back({i, j});
+                i = j;
+            }
+            std::stable_sort(runs.begin(), runs.end(), [&v](const std::pair<size_t, size_t> &x,
+                                                            const std::pair<size_t, size_t> &y) {
+                return v[x.first].count > v[y.first].count;
+            });
+            std::vector<Chunk> out;
+            out.reserve(e - b);
+            for (const auto &r : runs)
+                out.insert(out.end(), v.begin() + r.first, v.begin() + r.second);
+            std::copy(out.begin(), out.end(), v.begin() + b);
+        };
+        heaviest_first(0, E.ndense_sp2[wi]);
+        heaviest_first(E.ndense_sp2[wi], v.size());
     }
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
