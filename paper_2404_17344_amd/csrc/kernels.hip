@@ -1216,6 +1216,8 @@ addk_status engine_build_device(Engine &E, int precision)
     for (int d = 1; d <= 3; ++d) {
         if (E.maxvol[d])
             E.rb[d] = pick_rb(E.maxvol[d], precision, d);
+        // sparse-tile interpolation chunks heaviest first (as the dense items)
+        std::stable_sort(chi[d].begin(), chi[d].end(), [](const Chunk &x, const Chunk &y) { return x.count > y.count; });
         for (int side = 0; side < 2; ++side) {  // spreading, interpolation
             const std::vector<Chunk> &v = side == 0 ? ch[d] : chi[d];
             Chunk *&dp = side == 0 ? E.d_chunks[d] : E.d_chunks_i[d];
@@ -1298,8 +1300,12 @@ addk_status engine_build_device(Engine &E, int precision)
         heaviest_first(0, E.ndense_sp2[wi]);
         heaviest_first(E.ndense_sp2[wi], v.size());
     }
+    // interpolation items (each point's products written once, in any order):
+    // heaviest first, so that the long blocks do not start last
+    auto by_count = [](const Chunk &x, const Chunk &y) { return x.count > y.count; };
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
+            std::stable_sort(dn[d][wi].begin(), dn[d][wi].end(), by_count);
             addk_status s = upload_items(dn[d][wi], E.d_dense[d][wi], E.ndense[d][wi]);
             if (s == ADDK_OK)
                 s = upload_items(dsp[d][wi], E.d_dense_sp[d][wi], E.ndense_sp[d][wi]);
