@@ -1336,7 +1336,7 @@ addk_status engine_build_device(Engine &E, int precision)
             mtot += (int64_t)d.nbase[0] * d.nbase[1] * d.nbase[2];
         }
         std::vector<int2> map(mtot, make_int2(0, 0));
-        std::vector<std::vector<char>> mark(E.wdev.size());
+        std::vector<std::vector<int32_t>> mark(E.wdev.size());  // per gather tile: the item blocks reaching it
         for (size_t i = 0; i < items.size(); ++i) {
             const Chunk &c = items[i];
             const WinDev &d = E.wdev[c.win];
@@ -1352,13 +1352,17 @@ addk_status engine_build_device(Engine &E, int precision)
             for (int tz = bz / 4; tz <= (bz + d.W + nzc - 2) / 4 && tz < nt2; ++tz)
                 for (int ty = by / 4; ty <= (by + d.W - 1) / 4 && ty < nt1; ++ty)
                     for (int tx = bx / 4; tx <= (bx + d.W - 1) / 4 && tx < nt0; ++tx)
-                        mark[c.win][((size_t)tz * nt1 + ty) * nt0 + tx] = 1;
+                        mark[c.win][((size_t)tz * nt1 + ty) * nt0 + tx] += 1;
         }
+        // gather tiles heaviest first (each tile's sums do not depend on the order)
         std::vector<LineGroup> tiles;
         for (size_t w = 0; w < E.wdev.size(); ++w)
             for (size_t t = 0; t < mark[w].size(); ++t)
                 if (mark[w][t])
                     tiles.push_back({(int)w, (int)t});
+        std::stable_sort(tiles.begin(), tiles.end(), [&mark](const LineGroup &x, const LineGroup &y) {
+            return mark[x.win][x.grp] > mark[y.win][y.grp];
+        });
         hipError_t e = hipMalloc(&E.d_dmap[wi], std::max<int64_t>(1, mtot) * sizeof(int2));
         if (e == hipSuccess)
             e = hipMemcpy(E.d_dmap[wi], map.data(), mtot * sizeof(int2), hipMemcpyHostToDevice);
