@@ -1301,11 +1301,14 @@ addk_status engine_build_device(Engine &E, int precision)
         heaviest_first(E.ndense_sp2[wi], v.size());
     }
     // interpolation items (each point's products written once, in any order):
-    // heaviest first, so that the long blocks do not start last
-    auto by_count = [](const Chunk &x, const Chunk &y) { return x.count > y.count; };
+    // the classes of 16-point groups per wave heaviest first, so that the long
+    // blocks do not start last, and cell order inside a class, so that blocks
+    // running together share window blocks in L2 (sorting by the exact count
+    // was 1% faster but read 8.3 GB per call instead of 2.4)
+    auto by_groups = [](const Chunk &x, const Chunk &y) { return (x.count + 63) / 64 > (y.count + 63) / 64; };
     for (int d = 1; d <= 3; ++d)
         for (int wi = 0; wi < 2; ++wi) {
-            std::stable_sort(dn[d][wi].begin(), dn[d][wi].end(), by_count);
+            std::stable_sort(dn[d][wi].begin(), dn[d][wi].end(), by_groups);
             addk_status s = upload_items(dn[d][wi], E.d_dense[d][wi], E.ndense[d][wi]);
             if (s == ADDK_OK)
                 s = upload_items(dsp[d][wi], E.d_dense_sp[d][wi], E.ndense_sp[d][wi]);
