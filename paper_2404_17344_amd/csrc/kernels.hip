@@ -1216,7 +1216,9 @@ addk_status engine_build_device(Engine &E, int precision)
     for (int d = 1; d <= 3; ++d) {
         if (E.maxvol[d])
             E.rb[d] = pick_rb(E.maxvol[d], precision, d);
-        // sparse-tile interpolation chunks heaviest first (as the dense items)
+        // sparse-tile chunks heaviest first (as the dense items; the tile spreads
+        // add to the grids with atomics, in any order)
+        std::stable_sort(ch[d].begin(), ch[d].end(), [](const Chunk &x, const Chunk &y) { return x.count > y.count; });
         std::stable_sort(chi[d].begin(), chi[d].end(), [](const Chunk &x, const Chunk &y) { return x.count > y.count; });
         for (int side = 0; side < 2; ++side) {  // spreading, interpolation
             const std::vector<Chunk> &v = side == 0 ? ch[d] : chi[d];
@@ -1300,6 +1302,11 @@ addk_status engine_build_device(Engine &E, int precision)
         heaviest_first(0, E.ndense_sp2[wi]);
         heaviest_first(E.ndense_sp2[wi], v.size());
     }
+    // d <= 2 spread items (added to the grids with atomics, in any order): heaviest first
+    for (int d = 1; d <= 2; ++d)
+        for (int wi = 0; wi < 2; ++wi)
+            std::stable_sort(dsp[d][wi].begin(), dsp[d][wi].end(),
+                             [](const Chunk &x, const Chunk &y) { return x.count > y.count; });
     // interpolation items (each point's products written once, in any order):
     // the classes of 16-point groups per wave heaviest first, so that the long
     // blocks do not start last, and cell order inside a class, so that blocks
