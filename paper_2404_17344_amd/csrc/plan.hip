@@ -1017,7 +1017,12 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
                 if (interp_side)
                     for (int s = 0; s < cnt; s += kDenseChunk)
                         w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
-                const int spc = w.d == 3 ? kSpreadChunk : kDenseChunk;
+                // spread items: up to kSpreadChunk points for d = 3 (one window block
+                // each) and d = 1 (the quad-per-point kernel takes 16 points per
+                // quad; fewer, longer blocks amortise its reduction and atomic
+                // flush: 0.92 -> 0.34 ms on fifteen 1e6-point windows), the interp
+                // item size for d = 2
+                const int spc = w.d == 2 ? kDenseChunk : kSpreadChunk;
                 if (spread_side)
                     for (int s = 0; s < cnt; s += spc)
                         w.dense_sp.push_back({0, packed, (int32_t)(pos + s), std::min(spc, cnt - s)});
