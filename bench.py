@@ -294,7 +294,8 @@ def additive_main(args, A, WL, torch):
                     "unit": "GB/s", "frac": e["frac_of_hbm_peak"],
                     "traffic": measured_traffic(dom, traffic_file) if full else None,
                     "avg_launch_ms": e["avg_launch_ms"], "algorithmic_bytes_per_launch": e["algorithmic_bytes"],
-                    "point_window_pairs": pts[dom]}
+                    # the fused window sum interpolates every point-window pair
+                    "point_window_pairs": pts.get(dom, q["dense_points"] + q["tile_points"])}
     else:
         cand = [k for k in flops if stages[k][1] > 0]
         dom = max(cand, key=lambda s: stages[s][0])
