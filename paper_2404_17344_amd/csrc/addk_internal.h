@@ -41,6 +41,7 @@ constexpr int kDenseMin = 16;    // points per base cell for the dense kernels
 constexpr int kDenseChunk = 256; // maximal points per dense interp item
 constexpr int kSpreadChunk = 1024; // maximal points per d = 3 dense spread item (one window block each;
                                    // bounds the FP32 accumulation length)
+constexpr int kSpreadChunk1 = 2048; // maximal points per d = 1 dense spread item (32 per quad of lanes)
 // Fewest RHS for which untuned engines use a matrix-core variant (it always
 // computes 16 columns): where the autotuner's choice switches on the large
 // workload (1e6 points, five d = 3 windows, K and dK/dl outputs).

@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_dense1(const WinDev *__restri
     // permutation entries and coordinates of all KP points, then the RHS rows
     // of four points at a time, each batch loaded before the previous one's
     // products.
-    constexpr int KP = kSpreadChunk / 64;
+    constexpr int KP = kSpreadChunk1 / 64;
     int pj[KP];
     real uj[KP];
 #pragma unroll

@@ -1018,11 +1018,11 @@ static addk_status plan_window(Plan &pl, WinHost &w, const double *dX, int64_t l
                     for (int s = 0; s < cnt; s += kDenseChunk)
                         w.dense.push_back({0, packed, (int32_t)(pos + s), std::min(kDenseChunk, cnt - s)});
                 // spread items: up to kSpreadChunk points for d = 3 (one window block
-                // each) and d = 1 (the quad-per-point kernel takes 16 points per
-                // quad; fewer, longer blocks amortise its reduction and atomic
-                // flush: 0.92 -> 0.34 ms on fifteen 1e6-point windows), the interp
-                // item size for d = 2
-                const int spc = w.d == 2 ? kDenseChunk : kSpreadChunk;
+                // each), kSpreadChunk1 for d = 1 (fewer, longer blocks amortise the
+                // quad-per-point kernel's reduction and atomic flush: 0.92 ms on
+                // fifteen 1e6-point windows with 256 points, 0.34 with 1024, 0.29
+                // with 2048), the interp item size for d = 2
+                const int spc = w.d == 3 ? kSpreadChunk : (w.d == 1 ? kSpreadChunk1 : kDenseChunk);
                 if (spread_side)
                     for (int s = 0; s < cnt; s += spc)
                         w.dense_sp.push_back({0, packed, (int32_t)(pos + s), std::min(spc, cnt - s)});
